@@ -1,0 +1,135 @@
+"""Workload recipes (geometry, objects, true pupils, noise) for the synthetic
+benchmarks.  Common optics: lambda = 0.52 um, objective NA 0.25, sample pixel
+0.4 um, so the pupil radius is r = 0.19231 N bins.
+"""
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from .leds import led_rings
+from .objects import object_cfg0
+
+OPTICS = {"dx_um": 0.4, "wavelength_um": 0.52, "na_obj": 0.25}
+
+
+@dataclass
+class Workload:
+    """A set of tiles sharing one geometry class."""
+    name: str
+    n: int
+    k_bf: List
+    k_df: List
+    upsample: int = 2
+    n_tiles: int = 1
+    photons: Optional[float] = None      # Poisson scale per unit clear intensity
+    cfg_id: int = 0
+    obj_fn: Callable = object_cfg0       # (rng, n) -> complex object
+    coeffs: Optional[np.ndarray] = None  # (n_tiles, 15) true Noll coefficients
+    positions: Optional[np.ndarray] = None  # (n_tiles, 2) normalised (u, v)
+    dx_um: float = OPTICS["dx_um"]
+    wavelength_um: float = OPTICS["wavelength_um"]
+    na_obj: float = OPTICS["na_obj"]
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def r(self):
+        return self.na_obj * self.n * self.dx_um / self.wavelength_um
+
+    def object(self, tile):
+        rng = np.random.default_rng([self.cfg_id, 0, tile])
+        return self.obj_fn(rng, self.n)
+
+    def geometry_kwargs(self):
+        return {"n": self.n, "dx_um": self.dx_um, "wavelength_um": self.wavelength_um,
+                "na_obj": self.na_obj, "k_bf": np.asarray(self.k_bf, np.int64),
+                "k_df": np.asarray(self.k_df, np.int64), "upsample": self.upsample}
+
+
+def pupil_cfg0(seed=(0, 2, 0)):
+    """c_j ~ N(0, 0.5^2) for Noll j in {4, 5, 6, 7, 8, 11}, others 0."""
+    rng = np.random.default_rng(list(seed))
+    c = np.zeros(15)
+    for j in (4, 5, 6, 7, 8, 11):
+        c[j - 1] = rng.normal(0.0, 0.5)
+    return c
+
+
+def config0():
+    """One 128 x 128 tile, 8 NA-matched LEDs at NA 0.25 and 8 darkfield at 0.32,
+    noise-free, smooth cfg-0 object, 2x output."""
+    n = 128
+    leds_bf = led_rings(n, [(0.25, 8, 0.0, True)])
+    leds_df = led_rings(n, [(0.32, 8, 0.0, False)])
+    return Workload("cfg0", n, leds_bf, leds_df, upsample=2, n_tiles=1, photons=None,
+                    cfg_id=0, coeffs=pupil_cfg0()[None, :], positions=np.zeros((1, 2)))
+
+
+def field_model_cfg1(u, v, max_abs=1.5):
+    """Noll c_4..c_15 quadratic in the field position (u, v), rescaled so that the
+    largest |c| over the given positions equals ``max_abs`` rad."""
+    rng = np.random.default_rng([2407, 20469])
+    a = rng.normal(0.0, 1.0, size=(12, 6))
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    basis = np.stack([np.ones_like(u), u, v, u * u, u * v, v * v], axis=-1)
+    c = np.zeros(u.shape + (15,))
+    c[..., 3:15] = basis @ a.T
+    scale = max_abs / np.abs(c).max()
+    return c * scale, a * scale
+
+
+def config1(n_tiles=1024, photons=1e4, n=256):
+    """1024 tiles of 256^2 on a 32 x 32 field grid; 16 NA-matched LEDs at 0.25,
+    16 darkfield at 0.30 and 16 at 0.38 (half-step azimuth offset); Poisson noise."""
+    leds_bf = led_rings(n, [(0.25, 16, 0.0, True)])
+    leds_df = led_rings(n, [(0.30, 16, 0.0, False), (0.38, 16, 0.5, False)])
+    g = np.arange(1024)
+    u = (g % 32 - 15.5) / 15.5
+    v = (g // 32 - 15.5) / 15.5
+    c_all, _ = field_model_cfg1(u, v)
+    pos = np.stack([u, v], axis=1)
+    return Workload("cfg1", n, leds_bf, leds_df, upsample=2, n_tiles=n_tiles, photons=photons,
+                    cfg_id=1, coeffs=c_all[:n_tiles], positions=pos[:n_tiles])
+
+
+def small_workload(n=64, n_bf=8, n_df=8, na_df=(0.32,), n_tiles=2, photons=None, cfg_id=7):
+    """A small geometry (default 64^2) for quick parity checks; same optics."""
+    leds_bf = led_rings(n, [(0.25, n_bf, 0.0, True)])
+    rings = [(na, n_df // len(na_df), 0.5 * (m % 2), False) for m, na in enumerate(na_df)]
+    leds_df = led_rings(n, rings)
+    coeffs = np.stack([pupil_cfg0((cfg_id, 2, t)) * 0.5 for t in range(n_tiles)])
+    return Workload(f"small{n}", n, leds_bf, leds_df, upsample=2, n_tiles=n_tiles,
+                    photons=photons, cfg_id=cfg_id, coeffs=coeffs,
+                    positions=np.zeros((n_tiles, 2)))
+
+
+def config2_classes():
+    """The nine geometry classes of the uneven batch: N in {128, 256, 512} x
+    n_bf in {8, 12, 16}, n_df = 2 n_bf on rings at NA 0.30 and 0.38."""
+    out = []
+    for n in (128, 256, 512):
+        for n_bf in (8, 12, 16):
+            leds_bf = led_rings(n, [(0.25, n_bf, 0.0, True)])
+            leds_df = led_rings(n, [(0.30, n_bf, 0.0, False), (0.38, n_bf, 0.5, False)])
+            out.append({"n": n, "n_bf": n_bf, "k_bf": leds_bf, "k_df": leds_df})
+    return out
+
+
+def config2_tiles(n_tiles=4096, seed=2):
+    """Per-tile (size, n_bf, background, grid position) of the uneven batch:
+    sizes 128/256/512 in the ratio 4:3:1, n_bf uniform in {8, 12, 16}, 40%
+    background tiles, on a 64 x 64 field grid."""
+    rng = np.random.default_rng([2, 2, seed])
+    sizes = np.array([128] * (n_tiles // 2) + [256] * (3 * n_tiles // 8)
+                     + [512] * (n_tiles - n_tiles // 2 - 3 * n_tiles // 8))
+    rng.shuffle(sizes)
+    nbf = rng.choice([8, 12, 16], size=n_tiles)
+    bg = np.zeros(n_tiles, dtype=bool)
+    bg[rng.choice(n_tiles, size=int(round(0.4 * n_tiles)), replace=False)] = True
+    g = np.arange(n_tiles)
+    side = int(round(np.sqrt(n_tiles)))
+    u = (g % side - (side - 1) / 2) / ((side - 1) / 2)
+    v = (g // side - (side - 1) / 2) / ((side - 1) / 2)
+    return {"n": sizes, "n_bf": nbf, "background": bg, "u": u, "v": v}

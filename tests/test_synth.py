@@ -1,0 +1,46 @@
+"""The seeded input module: LED lattice rule and the torch image formation,
+checked against the oracle's own forward model."""
+
+import numpy as np
+import torch
+
+import oracle
+import apic_synth as S
+from apic_synth.leds import led_ring
+
+
+def test_led_lattice_examples():
+    """Nearest lattice point on the ring, NA-matched LEDs inside the pupil."""
+    ring = led_ring(128, 0.25, 8, 0.0, True)
+    assert ring[:3] == [(24, 0), (17, 17), (0, 24)]
+    ring = led_ring(256, 0.25, 16, 0.0, True)
+    assert ring[:3] == [(49, 0), (45, 19), (35, 34)]
+    r = 0.25 * 256 * 0.4 / 0.52
+    assert all(x * x + y * y <= r * r for x, y in ring)
+    df = led_ring(256, 0.38, 16, 0.5, False)
+    assert all(x * x + y * y > r * r for x, y in df)
+
+
+def test_config_sizes():
+    w0 = S.config0()
+    assert w0.n == 128 and len(w0.k_bf) == 8 and len(w0.k_df) == 8
+    w1 = S.config1(n_tiles=4)
+    assert w1.n == 256 and len(w1.k_bf) == 16 and len(w1.k_df) == 32
+    assert np.isclose(np.abs(S.field_model_cfg1(*np.meshgrid(
+        (np.arange(32) - 15.5) / 15.5, (np.arange(32) - 15.5) / 15.5))[0]).max(), 1.5)
+
+
+def test_torch_image_formation_matches_oracle_forward_model():
+    w = S.small_workload(n=64, n_tiles=2)
+    objs = np.stack([w.object(t) for t in range(2)])
+    got = S.form_images(objs, w.coeffs, list(w.k_bf) + list(w.k_df), w.r).numpy()
+    for t in range(2):
+        want = oracle.forward_images(objs[t], list(w.k_bf) + list(w.k_df), w.coeffs[t], w.r)
+        assert np.abs(got[t] - want).max() < 1e-12 * want.max()
+
+
+def test_poisson_noise_scale():
+    img = torch.full((4, 64, 64), 2.0, dtype=torch.float64)
+    noisy = S.add_poisson(img, 1e4, seed=3)
+    assert abs(noisy.mean().item() - 2.0) < 1e-3
+    assert abs(noisy.var().item() - 2.0 / 1e4) < 2e-5
