@@ -1,0 +1,205 @@
+/*
+ * apic.h -- C ABI of the MI355X (gfx950) per-tile closed-form APIC
+ * reconstruction (angular ptychographic imaging with closed-form solution,
+ * as used for whole-slide scanning in arXiv 2407.20469).
+ *
+ * What the library computes, for every tile of a batch (paper Sec. 2.3, Fig. 2):
+ *   1. Kramers-Kronig field recovery from each NA-matched image
+ *      (Eq. 4-6: log, 2D FFT, half-plane mask, inverse FFT, exp; Eq. 7: FFT and
+ *      pupil support);
+ *   2. pupil-aberration estimate from the phase differences of overlapping
+ *      spectra (Eq. 8-10), in the orthonormal Noll Zernike basis j = 4..15;
+ *   3. aberration correction and stitching of the brightfield spectrum
+ *      (text after Eq. 10);
+ *   4. darkfield extension (Eq. 11-13): for each darkfield image in the order
+ *      given, a regularised least-squares solve for the unknown part of the
+ *      spectrum from the cross-correlation terms;
+ *   5. the complex field on a grid upsampled by f (inverse FFT of the
+ *      zero-embedded spectrum, times f^2).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major [y][x], x fastest.  Spectra are in FFT order (DC at
+ *     [0][0]); a frequency index is the signed pair (ky, kx) in [-N/2, N/2)^2.
+ *     DFTs are unnormalised forward (exp(-2 pi j k.n/N)) and 1/N^2 inverse.
+ *   - Pupil radius r = na_obj * n * dx_um / wavelength_um bins;
+ *     Circ(k) = [kx^2 + ky^2 <= r^2].
+ *   - Illumination vectors are integer (kx, ky) DFT bins.  NA-matched ones must
+ *     satisfy |k| <= r; every |k| + r must stay below N/2 (no wrap).
+ *   - Zernike vectors are 15 floats per tile, Noll j = 1..15, RMS-normalised
+ *     (radians); j = 1..3 (piston, tip, tilt) are outputs of 0 and ignored on
+ *     input.  theta = atan2(ky, kx), rho = |k| / r.
+ *   - Complex values are interleaved float pairs (complex64).
+ *
+ * Memory and ownership
+ *   - Every data pointer (images, outputs, workspace, seeds) is DEVICE memory
+ *     owned by the caller.  apic_geometry and apic_tile_desc arrays are HOST
+ *     memory, read during the call and not retained.
+ *   - A plan owns its host tables; it uploads its device tables on first use
+ *     (or on apic_plan_upload) to the current device and owns them until
+ *     apic_plan_destroy.  Calls never allocate: scratch comes from the
+ *     caller's workspace, sized by apic_workspace_bytes.
+ *   - Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *     stream).  A plan is immutable after upload; concurrent calls need
+ *     separate workspaces.
+ *
+ * Errors
+ *   - Argument errors return a negative apic_status before anything is
+ *     enqueued.  HIP launch errors return APIC_EHIP.
+ *   - Numerical conditions never fail a call: they set bits of the per-tile
+ *     status word (APIC_TILE_*).
+ */
+#ifndef APIC_H
+#define APIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  APIC_OK = 0,
+  APIC_EINVAL = -1,       /* bad argument (null pointer, size, offset, workspace too small) */
+  APIC_EUNSUPPORTED = -2, /* geometry outside what the kernels are built for */
+  APIC_EHIP = -3,         /* a HIP runtime call failed */
+  APIC_ENOMEM = -4,       /* plan allocation failed */
+  APIC_EPLAN = -5         /* plan invalid, corrupted, or not uploaded to this device */
+} apic_status;
+
+/* Per-tile status bits (uint32 per tile, OR-ed by the kernels). */
+#define APIC_TILE_NONFINITE_INPUT 0x001u /* NaN/Inf in an NA-matched image            */
+#define APIC_TILE_LOG_FLOOR       0x002u /* some intensity clamped to the log floor   */
+#define APIC_TILE_PUPIL_ILLCOND   0x004u /* kappa(A) of Eq. 10's normal matrix > 1e6  */
+#define APIC_TILE_PUPIL_CHOL_FAIL 0x008u /* non-positive pivot in the 12x12 solve     */
+#define APIC_TILE_DF_CHOL_FAIL    0x010u /* non-positive pivot in a darkfield solve   */
+#define APIC_TILE_DF_SKIPPED      0x020u /* a darkfield image had no unknowns         */
+#define APIC_TILE_SEEDED          0x040u /* the pupil solve was re-wrapped on a seed  */
+#define APIC_TILE_NONFINITE_OUT   0x080u /* NaN/Inf in the pupil coefficients         */
+
+/* Tile flags (apic_tile_desc.flags). */
+#define APIC_TILE_SKIP_DARKFIELD 0x1  /* stop after the brightfield stitch */
+
+typedef struct apic_plan apic_plan; /* opaque */
+
+/* One geometry class (host memory; copied by apic_plan_create). */
+typedef struct {
+  int32_t n;               /* tile side N: 64, 128, 256 or 512                     */
+  int32_t upsample;        /* output factor f: 1 or 2 (f*N <= 1024)                 */
+  double dx_um;            /* sample-plane pixel pitch                              */
+  double wavelength_um;    /* illumination wavelength                               */
+  double na_obj;           /* objective NA                                          */
+  int32_t n_bf;            /* NA-matched images, 4..32                              */
+  int32_t n_df;            /* darkfield images, 0..64                               */
+  const int32_t *k_bf;     /* [n_bf][2] (kx, ky) bins                               */
+  const int32_t *k_df;     /* [n_df][2] (kx, ky) bins, in processing order         */
+  double ridge_pupil;      /* mu: ridge mu * tr(A)/12 in Eq. 10 (default 1e-9)      */
+  double ridge_darkfield;  /* lambda: ridge lambda * tr(G)/N_u in Eq. 13 (1e-4)     */
+  double log_floor_rel;    /* eps = log_floor_rel * mean(I) before the log (1e-6)   */
+} apic_geometry;
+
+/* One tile of a batch (host memory). */
+typedef struct {
+  int32_t geom;            /* index into the plan's geometry list                   */
+  int32_t flags;           /* APIC_TILE_SKIP_DARKFIELD                              */
+  int64_t image_offset;    /* float elements into `images` of this tile's stack of
+                              n_bf + n_df images [img][N][N], NA-matched first     */
+  int64_t field_offset;    /* complex elements into the tile's output array:
+                              fN x fN field (reconstruct, upsample) or N x N
+                              spectrum (stitch, extend_darkfield)                  */
+  float pos_x, pos_y;      /* normalised field position in [-1, 1]                  */
+} apic_tile_desc;
+
+/* Build a plan for n_geom geometry classes (host work only; no GPU needed).
+ * Returns APIC_EUNSUPPORTED for sizes the kernels do not cover. */
+apic_status apic_plan_create(const apic_geometry *geoms, int32_t n_geom, apic_plan **out);
+
+/* Free the plan and its device tables.  NULL is accepted. */
+apic_status apic_plan_destroy(apic_plan *plan);
+
+/* Upload the plan's device tables to the current device (idempotent). */
+apic_status apic_plan_upload(apic_plan *plan);
+
+/* Workspace bytes a call over these tiles needs (same for every entry point). */
+apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
+                                 const apic_tile_desc *tiles, size_t *bytes);
+
+/* Plan-introspection for host-side tests: copies a plan table of geometry
+ * `geom` into `out` (int32 values, capacity `cap`), returns its length in *len.
+ *   what = 0: darkfield step j's unknown set U      (ky, kx pairs)
+ *          1: darkfield step j's known set P        (ky, kx pairs)
+ *          2: darkfield step j's linear region Q    (ky, kx pairs)
+ *          3: darkfield step j's excluded set E     (ky, kx pairs)
+ *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs
+ *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps */
+apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
+                            int32_t *out, int64_t cap, int64_t *len);
+
+/* Whole method: KK -> pupil -> stitch -> darkfield -> fN x fN field.
+ *   images        float   [per tile: n_bf + n_df][N][N]   (device, at image_offset)
+ *   zernike_seed  float   [T][15] or NULL: re-wrap the pupil phases around it
+ *   zernike_out   float   [T][15]
+ *   field_out     complex [per tile: fN][fN]             (at field_offset)
+ *   tile_status   uint32  [T]  (zeroed by the call, then OR-ed) */
+apic_status apic_reconstruct_tiles(const apic_plan *plan, int32_t n_tiles,
+                                   const apic_tile_desc *tiles, const float *images,
+                                   const float *zernike_seed, float *zernike_out,
+                                   float *field_out, uint32_t *tile_status, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
+/* Fig. 2 upper half, Eq. 4-10 only.
+ *   diag_out      float [T][4]: linearised residual R(c) (rad^2), kappa(A),
+ *                 total weight sum w, smallest Cholesky pivot
+ *   features_out  float [T][32] or NULL: log1p of the weight sums per
+ *                 (pair-angle bin 0..7) x (|K|/(2r) band 0..3), over N^4 */
+apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
+                                const apic_tile_desc *tiles, const float *images,
+                                const float *zernike_seed, float *zernike_out, float *diag_out,
+                                float *features_out, uint32_t *tile_status, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
+/* KK spectra of the NA-matched images (Eq. 4-7), complex [T][n_bf][N][N]
+ * contiguous per tile at spectra_out + t * n_bf * N * N (single geometry). */
+apic_status apic_kk_spectra(const apic_plan *plan, int32_t n_tiles,
+                            const apic_tile_desc *tiles, const float *images,
+                            float *spectra_out, uint32_t *tile_status, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* Corrected, stitched brightfield spectrum (text after Eq. 10) for given
+ * Zernike coefficients: complex N x N per tile at field_offset of spectrum_out. */
+apic_status apic_stitch_brightfield(const apic_plan *plan, int32_t n_tiles,
+                                    const apic_tile_desc *tiles, const float *images,
+                                    const float *zernike, float *spectrum_out,
+                                    uint32_t *tile_status, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
+/* Fig. 2 lower half, Eq. 11-13: extend each tile's stitched brightfield
+ * spectrum (complex N x N at field_offset of spectrum_inout, zero outside the
+ * brightfield known set) through every darkfield image, in place. */
+apic_status apic_extend_darkfield(const apic_plan *plan, int32_t n_tiles,
+                                  const apic_tile_desc *tiles, const float *images,
+                                  const float *zernike, float *spectrum_inout,
+                                  uint32_t *tile_status, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
+/* fN x fN field from an N x N spectrum (zero embedding, inverse FFT, f^2):
+ * reads tile t's spectrum at spectrum_in + t * N * N (contiguous per tile,
+ * single geometry), writes the field at field_offset of field_out. */
+apic_status apic_upsample_field(const apic_plan *plan, int32_t n_tiles,
+                                const apic_tile_desc *tiles, const float *spectrum_in,
+                                float *field_out, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/* Batched 2D complex FFT of `batch` contiguous L x L arrays, L in
+ * {64, 128, 256, 512, 1024}, unnormalised in both directions, out of place
+ * allowed (in == out allowed).  Precision: 0 = complex64, 1 = complex128. */
+apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,
+                      const void *in, void *out, void *stream);
+
+/* Library version string. */
+const char *apic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APIC_H */

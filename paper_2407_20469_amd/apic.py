@@ -1,0 +1,330 @@
+"""ctypes binding of libapic.so (the C ABI in include/apic.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of the library.  torch tensors provide device memory and streams.
+Importing this module does not need a GPU; calling an entry point does.  If
+the library is not built, loading raises instead of falling back to anything.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapic.so")
+
+APIC_OK, APIC_EINVAL, APIC_EUNSUPPORTED, APIC_EHIP, APIC_ENOMEM, APIC_EPLAN = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "APIC_OK", -1: "APIC_EINVAL", -2: "APIC_EUNSUPPORTED", -3: "APIC_EHIP",
+                -4: "APIC_ENOMEM", -5: "APIC_EPLAN"}
+
+TILE_NONFINITE_INPUT = 0x001
+TILE_LOG_FLOOR = 0x002
+TILE_PUPIL_ILLCOND = 0x004
+TILE_PUPIL_CHOL_FAIL = 0x008
+TILE_DF_CHOL_FAIL = 0x010
+TILE_DF_SKIPPED = 0x020
+TILE_SEEDED = 0x040
+TILE_NONFINITE_OUT = 0x080
+TILE_SKIP_DARKFIELD = 0x1
+
+EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_workspace_bytes",
+           "apic_plan_query", "apic_reconstruct_tiles", "apic_estimate_pupil", "apic_kk_spectra",
+           "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
+           "apic_version"]
+
+
+class ApicError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} returned {STATUS_NAMES.get(code, code)}")
+        self.code = code
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("upsample", ctypes.c_int32),
+                ("dx_um", ctypes.c_double), ("wavelength_um", ctypes.c_double),
+                ("na_obj", ctypes.c_double), ("n_bf", ctypes.c_int32), ("n_df", ctypes.c_int32),
+                ("k_bf", ctypes.POINTER(ctypes.c_int32)), ("k_df", ctypes.POINTER(ctypes.c_int32)),
+                ("ridge_pupil", ctypes.c_double), ("ridge_darkfield", ctypes.c_double),
+                ("log_floor_rel", ctypes.c_double)]
+
+
+class TileDesc(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("image_offset", ctypes.c_int64), ("field_offset", ctypes.c_int64),
+                ("pos_x", ctypes.c_float), ("pos_y", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libapic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libapic.so not found at {path}: run "
+                           "`python -m paper_2407_20469_amd.build` (hipcc, gfx950) first")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.apic_plan_create.argtypes = [ctypes.POINTER(Geometry), i32, ctypes.POINTER(P)]
+    lib.apic_plan_destroy.argtypes = [P]
+    lib.apic_plan_upload.argtypes = [P]
+    lib.apic_workspace_bytes.argtypes = [P, i32, ctypes.POINTER(TileDesc), ctypes.POINTER(sz)]
+    lib.apic_plan_query.argtypes = [P, i32, i32, i32, ctypes.POINTER(i32), i64,
+                                    ctypes.POINTER(i64)]
+    lib.apic_reconstruct_tiles.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, P, sz,
+                                           P]
+    lib.apic_estimate_pupil.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, P, P, sz,
+                                        P]
+    lib.apic_kk_spectra.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, sz, P]
+    lib.apic_stitch_brightfield.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, sz, P]
+    lib.apic_extend_darkfield.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, sz, P]
+    lib.apic_upsample_field.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
+    lib.apic_fft2.argtypes = [i32, i32, i32, i32, P, P, P]
+    for name in EXPORTS:
+        getattr(lib, name).restype = ctypes.c_char_p if name == "apic_version" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(fn, code):
+    if code != APIC_OK:
+        raise ApicError(fn, code)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan over one or more geometry classes (dicts with keys n, upsample,
+    dx_um, wavelength_um, na_obj, k_bf, k_df and optional ridges/log floor)."""
+
+    def __init__(self, geometries):
+        self.lib = load_library()
+        if isinstance(geometries, dict):
+            geometries = [geometries]
+        self.geoms = [dict(g) for g in geometries]
+        self._keep = []
+        arr = (Geometry * len(self.geoms))()
+        for g, c in zip(self.geoms, arr):
+            kbf = np.ascontiguousarray(np.asarray(g["k_bf"], dtype=np.int32).reshape(-1, 2))
+            kdf = np.ascontiguousarray(np.asarray(g.get("k_df", np.zeros((0, 2))),
+                                                  dtype=np.int32).reshape(-1, 2))
+            self._keep += [kbf, kdf]
+            c.n = int(g["n"])
+            c.upsample = int(g.get("upsample", 2))
+            c.dx_um = float(g["dx_um"])
+            c.wavelength_um = float(g["wavelength_um"])
+            c.na_obj = float(g["na_obj"])
+            c.n_bf = kbf.shape[0]
+            c.n_df = kdf.shape[0]
+            c.k_bf = kbf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            c.k_df = kdf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            c.ridge_pupil = float(g.get("ridge_pupil", 1e-9))
+            c.ridge_darkfield = float(g.get("ridge_darkfield", 1e-4))
+            c.log_floor_rel = float(g.get("log_floor_rel", 1e-6))
+            g["n_bf"], g["n_df"] = int(c.n_bf), int(c.n_df)
+        self.handle = ctypes.c_void_p()
+        _check("apic_plan_create", self.lib.apic_plan_create(arr, len(self.geoms),
+                                                             ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            self.lib.apic_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self):
+        _check("apic_plan_upload", self.lib.apic_plan_upload(self.handle))
+
+    def query(self, what, geom=0, j=0):
+        n = ctypes.c_int64()
+        _check("apic_plan_query", self.lib.apic_plan_query(self.handle, geom, what, j, None, 0,
+                                                           ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), dtype=np.int32)
+        _check("apic_plan_query", self.lib.apic_plan_query(
+            self.handle, geom, what, j, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            out.size, ctypes.byref(n)))
+        return out[:n.value]
+
+    def sizes(self, geom=0):
+        v = self.query(5, geom)
+        return dict(zip(["n_pairs", "n_rows", "nu_max", "m_max", "ne_max", "n_active"], v.tolist()))
+
+    def workspace_bytes(self, descs):
+        b = ctypes.c_size_t()
+        _check("apic_workspace_bytes", self.lib.apic_workspace_bytes(
+            self.handle, len(descs), descs, ctypes.byref(b)))
+        return b.value
+
+
+def tile_descs(n_tiles, n_img, n, out_elems, geom=0, flags=0, positions=None):
+    """Descriptors of a contiguous batch: tile t's images at t * n_img * N^2 and
+    its output at t * out_elems."""
+    arr = (TileDesc * n_tiles)()
+    for t in range(n_tiles):
+        arr[t].geom = geom
+        arr[t].flags = flags
+        arr[t].image_offset = t * n_img * n * n
+        arr[t].field_offset = t * out_elems
+        if positions is not None:
+            arr[t].pos_x, arr[t].pos_y = float(positions[t][0]), float(positions[t][1])
+    return arr
+
+
+class Workspace:
+    """Caller-owned device scratch (a torch uint8 tensor, 256-B aligned)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes + 256 or self.buf.device != device:
+            self.buf = None
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        return ctypes.c_void_p((base + 255) & ~255), nbytes
+
+
+def _batch_args(plan, images, geom=0):
+    g = plan.geoms[geom]
+    n, n_img = g["n"], g["n_bf"] + g["n_df"]
+    if images.dim() != 4 or images.shape[1:] != (n_img, n, n):
+        raise ValueError(f"images must be (T, {n_img}, {n}, {n}), got {tuple(images.shape)}")
+    if not images.is_cuda or images.dtype.__str__() != "torch.float32" or not images.is_contiguous():
+        raise ValueError("images must be a contiguous float32 CUDA tensor")
+    return g, n, n_img, images.shape[0]
+
+
+def reconstruct(plan, images, seed=None, workspace=None, stream=None):
+    """Whole method on a contiguous single-geometry batch (T, n_img, N, N).
+    Returns (field complex64 (T, fN, fN), zernike (T, 15), status (T,))."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    nf = n * g.get("upsample", 2)
+    dev = images.device
+    field = torch.empty((T, nf, nf), dtype=torch.complex64, device=dev)
+    zern = torch.empty((T, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, nf * nf)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    if seed is not None:
+        seed = seed.contiguous().to(torch.float32)
+    _check("apic_reconstruct_tiles", plan.lib.apic_reconstruct_tiles(
+        plan.handle, T, descs, _ptr(images), _ptr(seed), _ptr(zern), _ptr(field), _ptr(status),
+        wp, wb, _stream(stream)))
+    return field, zern, status
+
+
+def estimate_pupil(plan, images, seed=None, workspace=None, stream=None):
+    """Eq. 4-10 on a batch.  Returns (zernike (T,15), diag (T,4), features (T,32), status)."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    zern = torch.empty((T, 15), dtype=torch.float32, device=dev)
+    diag = torch.empty((T, 4), dtype=torch.float32, device=dev)
+    feat = torch.empty((T, 32), dtype=torch.float32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, 0)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    if seed is not None:
+        seed = seed.contiguous().to(torch.float32)
+    _check("apic_estimate_pupil", plan.lib.apic_estimate_pupil(
+        plan.handle, T, descs, _ptr(images), _ptr(seed), _ptr(zern), _ptr(diag), _ptr(feat),
+        _ptr(status), wp, wb, _stream(stream)))
+    return zern, diag, feat, status
+
+
+def kk_spectra(plan, images, workspace=None, stream=None):
+    """KK spectra (T, n_bf, N, N) complex64."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    out = torch.empty((T, g["n_bf"], n, n), dtype=torch.complex64, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, 0)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    _check("apic_kk_spectra", plan.lib.apic_kk_spectra(
+        plan.handle, T, descs, _ptr(images), _ptr(out), _ptr(status), wp, wb, _stream(stream)))
+    return out, status
+
+
+def stitch_brightfield(plan, images, zernike, workspace=None, stream=None):
+    """Corrected, stitched brightfield spectra (T, N, N) complex64."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    out = torch.empty((T, n, n), dtype=torch.complex64, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, n * n)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    z = zernike.contiguous().to(torch.float32)
+    _check("apic_stitch_brightfield", plan.lib.apic_stitch_brightfield(
+        plan.handle, T, descs, _ptr(images), _ptr(z), _ptr(out), _ptr(status), wp, wb,
+        _stream(stream)))
+    return out, status
+
+
+def extend_darkfield(plan, images, zernike, spectrum, workspace=None, stream=None):
+    """Eq. 11-13 in place on a copy of `spectrum` (T, N, N) complex64."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    spec = spectrum.contiguous().clone()
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, n * n)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    z = zernike.contiguous().to(torch.float32)
+    _check("apic_extend_darkfield", plan.lib.apic_extend_darkfield(
+        plan.handle, T, descs, _ptr(images), _ptr(z), _ptr(spec), _ptr(status), wp, wb,
+        _stream(stream)))
+    return spec, status
+
+
+def upsample_field(plan, spectrum, workspace=None, stream=None):
+    """fN x fN fields from (T, N, N) complex64 spectra."""
+    import torch
+    g = plan.geoms[0]
+    n, nf = g["n"], g["n"] * g.get("upsample", 2)
+    T = spectrum.shape[0]
+    spec = spectrum.contiguous()
+    out = torch.empty((T, nf, nf), dtype=torch.complex64, device=spec.device)
+    descs = tile_descs(T, g["n_bf"] + g["n_df"], n, nf * nf)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), spec.device)
+    _check("apic_upsample_field", plan.lib.apic_upsample_field(
+        plan.handle, T, descs, _ptr(spec), _ptr(out), wp, wb, _stream(stream)))
+    return out
+
+
+def fft2(x, inverse=False, stream=None):
+    """Unnormalised batched 2D FFT of (B, L, L) complex64/complex128 CUDA tensors."""
+    import torch
+    lib = load_library()
+    x = x.contiguous()
+    prec = 1 if x.dtype == torch.complex128 else 0
+    out = torch.empty_like(x)
+    _check("apic_fft2", lib.apic_fft2(x.shape[-1], x.numel() // (x.shape[-1] ** 2), int(inverse),
+                                      prec, _ptr(x), _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,672 @@
+// C ABI of the per-tile APIC reconstruction: plan lifecycle, workspace
+// layout, and the enqueue sequences of the entry points declared in apic.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/apic.h"
+#include "common.hpp"
+#include "fft.hpp"
+#include "kernels_bf.hpp"
+#include "kernels_df.hpp"
+#include "plan.hpp"
+
+namespace apic {
+namespace {
+
+#define APIC_HIP(call)                        \
+  do {                                        \
+    if ((call) != hipSuccess) return APIC_EHIP; \
+  } while (0)
+#define APIC_LAUNCHED()                                 \
+  do {                                                  \
+    if (hipGetLastError() != hipSuccess) return APIC_EHIP; \
+  } while (0)
+
+// ------------------------------------------------------------ twiddles
+std::mutex g_tw_mu;
+bool g_tw_ready[64] = {};
+
+apic_status ensure_twiddles() {
+  int dev = 0;
+  APIC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return APIC_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  if (g_tw_ready[dev]) return APIC_OK;
+  std::vector<c32> t32(kTwTotal);
+  std::vector<c64> t64(kTwTotal);
+  for (int L = 64; L <= 1024; L *= 2)
+    for (int t = 0; t < L; ++t) {
+      // exp(-2 pi j t / L), angle reduced to the first octant for accuracy
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * t / L;
+      const double c = (double)cosl(ang), s = (double)sinl(ang);
+      t64[L - 64 + t] = make_double2(c, s);
+      t32[L - 64 + t] = make_float2((float)c, (float)s);
+    }
+  APIC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw32), t32.data(), sizeof(c32) * kTwTotal));
+  APIC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw64), t64.data(), sizeof(c64) * kTwTotal));
+  g_tw_ready[dev] = true;
+  return APIC_OK;
+}
+
+bool plan_ok(const apic_plan *p) { return p && p->magic == kPlanMagic && !p->geoms.empty(); }
+
+template <class T> apic_status upload_vec(const std::vector<T> &v, void **dst) {
+  const size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
+  APIC_HIP(hipMalloc(dst, bytes));
+  if (!v.empty()) APIC_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return APIC_OK;
+}
+
+void free_geom(GeomPlan &g) {
+  void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords};
+  for (void **p : ptrs)
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+}
+
+// ------------------------------------------------------------ call setup
+struct ClassRun {
+  int geom = 0;
+  bool skip_df = false;
+  bool affine = false;   // offsets and batch indices are affine in the class index
+  std::vector<int64_t> img_off, out_off;
+  std::vector<int32_t> gidx, flags;
+  int64_t desc_at = 0;   // byte offset of this class's descriptor arrays
+  int64_t ws_at = 0;     // byte offset of tile 0's block
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Group tiles by (geometry, skip-darkfield) and lay out the workspace:
+// descriptor arrays first, then one block per tile.
+apic_status layout_call(const apic_plan *p, int32_t n_tiles, const apic_tile_desc *tiles,
+                        std::vector<ClassRun> &runs, int64_t &total) {
+  if (n_tiles < 0) return APIC_EINVAL;
+  if (n_tiles > 0 && !tiles) return APIC_EINVAL;
+  runs.clear();
+  const int ng = (int)p->geoms.size();
+  std::vector<int> slot(2 * ng, -1);
+  for (int t = 0; t < n_tiles; ++t) {
+    const apic_tile_desc &d = tiles[t];
+    if (d.geom < 0 || d.geom >= ng) return APIC_EINVAL;
+    if (d.image_offset < 0 || d.field_offset < 0) return APIC_EINVAL;
+    const int key = 2 * d.geom + ((d.flags & APIC_TILE_SKIP_DARKFIELD) ? 1 : 0);
+    if (slot[key] < 0) {
+      slot[key] = (int)runs.size();
+      runs.emplace_back();
+      runs.back().geom = d.geom;
+      runs.back().skip_df = (key & 1) != 0;
+    }
+    ClassRun &r = runs[slot[key]];
+    r.img_off.push_back(d.image_offset);
+    r.out_off.push_back(d.field_offset);
+    r.gidx.push_back(t);
+    r.flags.push_back(d.flags);
+  }
+  for (ClassRun &r : runs) {
+    const size_t T = r.gidx.size();
+    r.affine = true;
+    for (size_t t = 2; t < T && r.affine; ++t)
+      r.affine = r.img_off[t] - r.img_off[t - 1] == r.img_off[1] - r.img_off[0] &&
+                 r.out_off[t] - r.out_off[t - 1] == r.out_off[1] - r.out_off[0] &&
+                 r.gidx[t] - r.gidx[t - 1] == r.gidx[1] - r.gidx[0];
+  }
+  int64_t o = 0;
+  for (ClassRun &r : runs) {
+    r.desc_at = o;
+    const int64_t T = (int64_t)r.gidx.size();
+    o = align256(o + T * (8 + 8 + 4 + 4));
+  }
+  for (ClassRun &r : runs) {
+    r.ws_at = o;
+    o += (int64_t)r.gidx.size() * p->geoms[r.geom].lay.stride;
+  }
+  total = std::max<int64_t>(o, 256);
+  return APIC_OK;
+}
+
+ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, char *ws,
+                    uint32_t *status) {
+  const GeomPlan &g = p->geoms[r.geom];
+  ClassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = g.n;
+  a.nf = g.nf;
+  a.n_bf = g.n_bf;
+  a.n_df = g.n_df;
+  a.n_img = g.n_bf + g.n_df;
+  a.T = (int)r.gidx.size();
+  a.r2 = (int)g.r2;
+  a.r = (float)g.r;
+  a.inv_r = (float)(1.0 / g.r);
+  a.log_floor_rel = (float)g.log_floor_rel;
+  a.n_rows = g.n_rows;
+  a.n_chunks = g.n_chunks;
+  a.nu_pad = g.nu_pad;
+  a.ridge_pupil = g.ridge_pupil;
+  a.ridge_df = g.ridge_df;
+  for (int i = 0; i < g.n_bf; ++i) {
+    a.kx[i] = g.kbf[2 * i];
+    a.ky[i] = g.kbf[2 * i + 1];
+  }
+  for (int j = 0; j < g.n_df; ++j) {
+    a.kx[g.n_bf + j] = g.kdf[2 * j];
+    a.ky[g.n_bf + j] = g.kdf[2 * j + 1];
+  }
+  a.images = images;
+  const int64_t T = a.T;
+  char *d = ws + r.desc_at;
+  a.affine = r.affine ? 1 : 0;
+  a.img0 = r.img_off[0];
+  a.out0 = r.out_off[0];
+  a.g0 = r.gidx[0];
+  a.img_step = T > 1 ? r.img_off[1] - r.img_off[0] : 0;
+  a.out_step = T > 1 ? r.out_off[1] - r.out_off[0] : 0;
+  a.g_step = T > 1 ? r.gidx[1] - r.gidx[0] : 0;
+  a.d_img_off = reinterpret_cast<const int64_t *>(d);
+  a.d_out_off = reinterpret_cast<const int64_t *>(d + 8 * T);
+  a.d_gidx = reinterpret_cast<const int32_t *>(d + 16 * T);
+  a.ws = ws + r.ws_at;
+  a.stride = g.lay.stride;
+  a.lay = g.lay;
+  a.status = status;
+  a.row_il = (const uint32_t *)g.d_row_il;
+  a.row_k = (const uint32_t *)g.d_row_k;
+  a.known_at = (const int16_t *)g.d_known_at;
+  a.coords = (const uint32_t *)g.d_coords;
+  return a;
+}
+
+// Irregular descriptor lists go to the workspace with a blocking copy, after
+// the stream has drained (earlier work on it may still read that region).
+apic_status upload_descriptors(const std::vector<ClassRun> &runs, char *ws, hipStream_t st) {
+  bool synced = false;
+  for (const ClassRun &r : runs) {
+    if (r.affine) continue;
+    if (!synced) {
+      APIC_HIP(hipStreamSynchronize(st));
+      synced = true;
+    }
+    const int64_t T = (int64_t)r.gidx.size();
+    std::vector<char> buf(T * 24);
+    memcpy(buf.data(), r.img_off.data(), 8 * T);
+    memcpy(buf.data() + 8 * T, r.out_off.data(), 8 * T);
+    memcpy(buf.data() + 16 * T, r.gidx.data(), 4 * T);
+    memcpy(buf.data() + 20 * T, r.flags.data(), 4 * T);
+    APIC_HIP(hipMemcpy(ws + r.desc_at, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  }
+  return APIC_OK;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int n, uint32_t v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_status_or_all(ClassArgs a, uint32_t bits) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < a.T) status_or(a, t, bits);
+}
+// Copy a caller spectrum (complex N x N at out_off) into / out of O_hat.
+__global__ void k_spec_copy(ClassArgs a, float *spec, int to_ohat) {
+  const int nn = a.n * a.n;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (int64_t)a.T * nn) return;
+  const int t = (int)(gid / nn), pix = (int)(gid % nn);
+  c32 *s = reinterpret_cast<c32 *>(spec) + a.out_off(t) + pix;
+  c32 *o = a.at<c32>(t, a.lay.ohat) + pix;
+  if (to_ohat) *o = *s;
+  else *s = *o;
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// ------------------------------------------------------------ stage runners
+template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t st) {
+  const int arrays = a.T * a.n_bf;
+  hipLaunchKernelGGL(k_image_stats, dim3(arrays), dim3(256), 0, st, a);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL((k_rows<c32, N, OpKK1<N>>), dim3(row_blocks<c32, N>(arrays, N)),
+                     dim3(kFftThreads), 0, st, OpKK1<N>{a});
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL((k_cols<c32, N, OpKK2<N>>), dim3(col_blocks<c32, N>(arrays)),
+                     dim3(kFftThreads), 0, st, OpKK2<N>{a});
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL((k_rows<c32, N, OpKK3<N>>), dim3(row_blocks<c32, N>(arrays, N)),
+                     dim3(kFftThreads), 0, st, OpKK3<N>{a});
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL((k_cols<c32, N, OpKK4<N>>), dim3(col_blocks<c32, N>(arrays)),
+                     dim3(kFftThreads), 0, st, OpKK4<N>{a, kk_out});
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+apic_status run_pupil(const ClassArgs &a, const float *seed, float *zout, float *diag,
+                      float *feat, hipStream_t st) {
+  hipLaunchKernelGGL(k_pupil_partial, dim3(a.T * a.n_chunks), dim3(256), 0, st, a, seed);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_pupil_reduce, dim3(a.T), dim3(128), 0, st, a);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_pupil_solve, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, seed, zout,
+                     diag, feat);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+apic_status run_stitch(const ClassArgs &a, float *spec_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_stitch, dim3(blocks_for((int64_t)a.T * a.n * a.n, 256)), dim3(256), 0, st,
+                     a, spec_out);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+template <int N>
+apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs &a,
+                          hipStream_t st) {
+  const GeomPlan &g = p->geoms[r.geom];
+  bool skipped = false;
+  for (int j = 0; j < g.n_df; ++j) {
+    const DfStep &d = g.steps[j];
+    if (d.nu == 0) {
+      skipped = true;
+      continue;
+    }
+    StepArgs s;
+    s.j = j;
+    s.img = g.n_bf + j;
+    s.kx = d.kx;
+    s.ky = d.ky;
+    s.nu = d.nu;
+    s.np = d.np;
+    s.m = d.m;
+    s.ne = d.ne;
+    s.u = a.coords + d.off_u;
+    s.p = a.coords + d.off_p;
+    s.q = a.coords + d.off_q;
+    s.e = a.coords + d.off_e;
+    const int64_t pix = (int64_t)a.T * N * N;
+    hipLaunchKernelGGL(k_df_phat, dim3(blocks_for(pix, 256)), dim3(256), 0, st, a, s);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                       dim3(kFftThreads), 0, st, OpP1<N>{a});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_cols<c64, N, OpP2<N>>), dim3(col_blocks<c64, N>(a.T)),
+                       dim3(kFftThreads), 0, st, OpP2<N>{a});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                       dim3(kFftThreads), 0, st, OpP3<N>{a});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_rows<c64, N, OpImg1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                       dim3(kFftThreads), 0, st, OpImg1<N>{a, s.img});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_cols<c64, N, OpImg2<N>>), dim3(col_blocks<c64, N>(a.T)),
+                       dim3(kFftThreads), 0, st, OpImg2<N>{a});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_df_rhs_b, dim3(blocks_for(d.m, 256), a.T), dim3(256), 0, st, a, s);
+    APIC_LAUNCHED();
+    const int nb = (d.nu + kGramBlock - 1) / kGramBlock;
+    hipLaunchKernelGGL(k_df_gram, dim3((unsigned)(a.T * (nb * (nb + 1) / 2))), dim3(256), 0, st,
+                       a, s);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_df_rhs_v, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st, a, s);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_df_chol, dim3(a.T), dim3(256), 0, st, a, s);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_df_scatter, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st, a, s);
+    APIC_LAUNCHED();
+  }
+  if (skipped) {
+    hipLaunchKernelGGL(k_status_or_all, dim3(blocks_for(a.T, 256)), dim3(256), 0, st, a,
+                       (uint32_t)APIC_TILE_DF_SKIPPED);
+    APIC_LAUNCHED();
+  }
+  return APIC_OK;
+}
+
+template <int N, int NF>
+apic_status run_output_nf(const ClassArgs &a, const c32 *src, float *field, hipStream_t st) {
+  hipLaunchKernelGGL((k_rows<c32, NF, OpOut1<NF>>), dim3(row_blocks<c32, NF>(a.T, N)),
+                     dim3(kFftThreads), 0, st, OpOut1<NF>{a, src});
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL((k_cols<c32, NF, OpOut2<NF>>), dim3(col_blocks<c32, NF>(a.T)),
+                     dim3(kFftThreads), 0, st, OpOut2<NF>{a, reinterpret_cast<c32 *>(field)});
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+template <int N>
+apic_status run_output(const ClassArgs &a, const c32 *src, float *field, hipStream_t st) {
+  if (a.nf == N) return run_output_nf<N, N>(a, src, field, st);
+  if constexpr (2 * N <= 1024) return run_output_nf<N, 2 * N>(a, src, field, st);
+  return APIC_EUNSUPPORTED;
+}
+
+enum Stage : unsigned {
+  S_KK = 1, S_PUPIL = 2, S_COEF_IN = 4, S_STITCH = 8, S_SPEC_IN = 16, S_DF = 32, S_SPEC_OUT = 64,
+  S_OUT = 128
+};
+
+struct CallIO {
+  const float *seed = nullptr;
+  const float *zin = nullptr;
+  float *zout = nullptr, *diag = nullptr, *feat = nullptr;
+  float *kk_out = nullptr, *spec_out = nullptr, *spec_io = nullptr, *field = nullptr;
+  const float *spec_src = nullptr;
+};
+
+template <int N>
+apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &a, unsigned st_mask,
+                        const CallIO &io, hipStream_t st) {
+  apic_status rc = APIC_OK;
+  if (st_mask & S_KK) {
+    rc = run_kk<N>(a, reinterpret_cast<c32 *>(io.kk_out), st);
+    if (rc) return rc;
+  }
+  if (st_mask & S_PUPIL) {
+    rc = run_pupil(a, io.seed, io.zout, io.diag, io.feat, st);
+    if (rc) return rc;
+  }
+  if (st_mask & S_COEF_IN) {
+    hipLaunchKernelGGL(k_coef_load, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, io.zin);
+    APIC_LAUNCHED();
+  }
+  if (st_mask & S_STITCH) {
+    rc = run_stitch(a, io.spec_out, st);
+    if (rc) return rc;
+  } else if (st_mask & (S_DF | S_SPEC_IN)) {
+    hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);
+    APIC_LAUNCHED();
+  }
+  if (st_mask & S_SPEC_IN) {
+    hipLaunchKernelGGL(k_spec_copy, dim3(blocks_for((int64_t)a.T * N * N, 256)), dim3(256), 0, st,
+                       a, io.spec_io, 1);
+    APIC_LAUNCHED();
+  }
+  if ((st_mask & S_DF) && !r.skip_df) {
+    rc = run_darkfield<N>(p, r, a, st);
+    if (rc) return rc;
+  }
+  if (st_mask & S_SPEC_OUT) {
+    hipLaunchKernelGGL(k_spec_copy, dim3(blocks_for((int64_t)a.T * N * N, 256)), dim3(256), 0, st,
+                       a, io.spec_io, 0);
+    APIC_LAUNCHED();
+  }
+  if (st_mask & S_OUT) {
+    rc = run_output<N>(a, reinterpret_cast<const c32 *>(io.spec_src), io.field, st);
+    if (rc) return rc;
+  }
+  return APIC_OK;
+}
+
+apic_status run_call(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
+                     const float *images, uint32_t *status, void *workspace, size_t ws_bytes,
+                     void *stream, unsigned st_mask, const CallIO &io) {
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  std::vector<ClassRun> runs;
+  int64_t need = 0;
+  apic_status rc = layout_call(plan, n_tiles, tiles, runs, need);
+  if (rc) return rc;
+  if (n_tiles == 0) return APIC_OK;
+  if (!workspace || (int64_t)ws_bytes < need) return APIC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return APIC_EINVAL;
+  rc = apic_plan_upload(const_cast<apic_plan *>(plan));
+  if (rc) return rc;
+  rc = ensure_twiddles();
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *ws = reinterpret_cast<char *>(workspace);
+  if (status) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n_tiles, 256)), dim3(256), 0, st, status,
+                       n_tiles, 0u);
+    APIC_LAUNCHED();
+  }
+  rc = upload_descriptors(runs, ws, st);
+  if (rc) return rc;
+  for (const ClassRun &r : runs) {
+    const ClassArgs a = make_args(plan, r, images, ws, status);
+    switch (a.n) {
+      case 64: rc = run_class_n<64>(plan, r, a, st_mask, io, st); break;
+      case 128: rc = run_class_n<128>(plan, r, a, st_mask, io, st); break;
+      case 256: rc = run_class_n<256>(plan, r, a, st_mask, io, st); break;
+      case 512: rc = run_class_n<512>(plan, r, a, st_mask, io, st); break;
+      default: rc = APIC_EUNSUPPORTED;
+    }
+    if (rc) return rc;
+  }
+  return APIC_OK;
+}
+
+template <class C, int L>
+apic_status fft2_l(int batch, bool inv, const void *in, void *out, hipStream_t st) {
+  const C *src = reinterpret_cast<const C *>(in);
+  C *dst = reinterpret_cast<C *>(out);
+  if (inv) {
+    hipLaunchKernelGGL((k_rows<C, L, OpPlainRows<C, L, true>>), dim3(row_blocks<C, L>(batch, L)),
+                       dim3(kFftThreads), 0, st, OpPlainRows<C, L, true>{src, dst});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_cols<C, L, OpPlainCols<C, L, true>>), dim3(col_blocks<C, L>(batch)),
+                       dim3(kFftThreads), 0, st, OpPlainCols<C, L, true>{dst});
+  } else {
+    hipLaunchKernelGGL((k_rows<C, L, OpPlainRows<C, L, false>>), dim3(row_blocks<C, L>(batch, L)),
+                       dim3(kFftThreads), 0, st, OpPlainRows<C, L, false>{src, dst});
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL((k_cols<C, L, OpPlainCols<C, L, false>>), dim3(col_blocks<C, L>(batch)),
+                       dim3(kFftThreads), 0, st, OpPlainCols<C, L, false>{dst});
+  }
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+template <class C>
+apic_status fft2_c(int l, int batch, bool inv, const void *in, void *out, hipStream_t st) {
+  switch (l) {
+    case 64: return fft2_l<C, 64>(batch, inv, in, out, st);
+    case 128: return fft2_l<C, 128>(batch, inv, in, out, st);
+    case 256: return fft2_l<C, 256>(batch, inv, in, out, st);
+    case 512: return fft2_l<C, 512>(batch, inv, in, out, st);
+    case 1024: return fft2_l<C, 1024>(batch, inv, in, out, st);
+    default: return APIC_EUNSUPPORTED;
+  }
+}
+
+}  // namespace
+}  // namespace apic
+
+using namespace apic;
+
+extern "C" {
+
+const char *apic_version(void) { return "apic-mi355x 0.1 (gfx950)"; }
+
+apic_status apic_plan_create(const apic_geometry *geoms, int32_t n_geom, apic_plan **out) {
+  if (!out) return APIC_EINVAL;
+  *out = nullptr;
+  if (!geoms || n_geom <= 0 || n_geom > 64) return APIC_EINVAL;
+  apic_plan *p = new (std::nothrow) apic_plan();
+  if (!p) return APIC_ENOMEM;
+  p->geoms.resize(n_geom);
+  for (int i = 0; i < n_geom; ++i) {
+    const apic_status rc = build_geom_plan(geoms[i], p->geoms[i]);
+    if (rc != APIC_OK) {
+      delete p;
+      return rc;
+    }
+  }
+  *out = p;
+  return APIC_OK;
+}
+
+apic_status apic_plan_destroy(apic_plan *plan) {
+  if (!plan) return APIC_OK;
+  if (plan->magic != kPlanMagic) return APIC_EPLAN;
+  for (GeomPlan &g : plan->geoms) free_geom(g);
+  plan->magic = 0;
+  delete plan;
+  return APIC_OK;
+}
+
+apic_status apic_plan_upload(apic_plan *plan) {
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  int dev = 0;
+  APIC_HIP(hipGetDevice(&dev));
+  if (plan->uploaded) return plan->device == dev ? APIC_OK : APIC_EPLAN;
+  for (GeomPlan &g : plan->geoms) {
+    apic_status rc;
+    if ((rc = upload_vec(g.row_il, &g.d_row_il)) || (rc = upload_vec(g.row_k, &g.d_row_k)) ||
+        (rc = upload_vec(g.known_at, &g.d_known_at)) || (rc = upload_vec(g.coords, &g.d_coords))) {
+      for (GeomPlan &h : plan->geoms) free_geom(h);
+      return rc;
+    }
+  }
+  plan->device = dev;
+  plan->uploaded = true;
+  return ensure_twiddles();
+}
+
+apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
+                                 const apic_tile_desc *tiles, size_t *bytes) {
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  if (!bytes) return APIC_EINVAL;
+  std::vector<ClassRun> runs;
+  int64_t need = 0;
+  const apic_status rc = layout_call(plan, n_tiles, tiles, runs, need);
+  if (rc) return rc;
+  *bytes = (size_t)need;
+  return APIC_OK;
+}
+
+apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
+                            int32_t *out, int64_t cap, int64_t *len) {
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  if (!len || geom < 0 || geom >= (int)plan->geoms.size()) return APIC_EINVAL;
+  const GeomPlan &g = plan->geoms[geom];
+  std::vector<int32_t> v;
+  if (what >= 0 && what <= 3) {
+    if (j < 0 || j >= g.n_df) return APIC_EINVAL;
+    const DfStep &d = g.steps[j];
+    const int64_t off[] = {d.off_u, d.off_p, d.off_q, d.off_e};
+    const int cnt[] = {d.nu, d.np, d.m, d.ne};
+    for (int i = 0; i < cnt[what]; ++i) {
+      const uint32_t w = g.coords[off[what] + i];
+      v.push_back(unpack_ky(w));
+      v.push_back(unpack_kx(w));
+    }
+  } else if (what == 4) {
+    for (int i = 0; i < g.n_rows; ++i) {
+      v.push_back(g.row_il[i] & 0xff);
+      v.push_back((g.row_il[i] >> 8) & 0xff);
+      v.push_back(unpack_ky(g.row_k[i]));
+      v.push_back(unpack_kx(g.row_k[i]));
+      v.push_back((int32_t)(g.row_il[i] >> 16));
+    }
+  } else if (what == 5) {
+    v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active};
+  } else {
+    return APIC_EINVAL;
+  }
+  *len = (int64_t)v.size();
+  if (out) {
+    if (cap < (int64_t)v.size()) return APIC_EINVAL;
+    std::copy(v.begin(), v.end(), out);
+  }
+  return APIC_OK;
+}
+
+apic_status apic_reconstruct_tiles(const apic_plan *plan, int32_t n_tiles,
+                                   const apic_tile_desc *tiles, const float *images,
+                                   const float *zernike_seed, float *zernike_out,
+                                   float *field_out, uint32_t *tile_status, void *workspace,
+                                   size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike_out || !field_out || !tile_status)) return APIC_EINVAL;
+  CallIO io;
+  io.seed = zernike_seed;
+  io.zout = zernike_out;
+  io.field = field_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT, io);
+}
+
+apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
+                                const apic_tile_desc *tiles, const float *images,
+                                const float *zernike_seed, float *zernike_out, float *diag_out,
+                                float *features_out, uint32_t *tile_status, void *workspace,
+                                size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike_out || !tile_status)) return APIC_EINVAL;
+  CallIO io;
+  io.seed = zernike_seed;
+  io.zout = zernike_out;
+  io.diag = diag_out;
+  io.feat = features_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_PUPIL, io);
+}
+
+apic_status apic_kk_spectra(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
+                            const float *images, float *spectra_out, uint32_t *tile_status,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !spectra_out || !tile_status)) return APIC_EINVAL;
+  if (plan_ok(plan) && plan->geoms.size() != 1) return APIC_EUNSUPPORTED;
+  CallIO io;
+  io.kk_out = spectra_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK, io);
+}
+
+apic_status apic_stitch_brightfield(const apic_plan *plan, int32_t n_tiles,
+                                    const apic_tile_desc *tiles, const float *images,
+                                    const float *zernike, float *spectrum_out,
+                                    uint32_t *tile_status, void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike || !spectrum_out || !tile_status)) return APIC_EINVAL;
+  CallIO io;
+  io.zin = zernike;
+  io.spec_out = spectrum_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_COEF_IN | S_STITCH, io);
+}
+
+apic_status apic_extend_darkfield(const apic_plan *plan, int32_t n_tiles,
+                                  const apic_tile_desc *tiles, const float *images,
+                                  const float *zernike, float *spectrum_inout,
+                                  uint32_t *tile_status, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike || !spectrum_inout || !tile_status)) return APIC_EINVAL;
+  CallIO io;
+  io.zin = zernike;
+  io.spec_io = spectrum_inout;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_COEF_IN | S_SPEC_IN | S_DF | S_SPEC_OUT, io);
+}
+
+apic_status apic_upsample_field(const apic_plan *plan, int32_t n_tiles,
+                                const apic_tile_desc *tiles, const float *spectrum_in,
+                                float *field_out, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+  if (n_tiles > 0 && (!spectrum_in || !field_out)) return APIC_EINVAL;
+  if (plan_ok(plan) && plan->geoms.size() != 1) return APIC_EUNSUPPORTED;
+  CallIO io;
+  io.spec_src = spectrum_in;
+  io.field = field_out;
+  return run_call(plan, n_tiles, tiles, nullptr, nullptr, workspace, workspace_bytes, stream,
+                  S_OUT, io);
+}
+
+apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,
+                      const void *in, void *out, void *stream) {
+  if (batch < 0 || !in || !out) return APIC_EINVAL;
+  if (batch == 0) return APIC_OK;
+  if (precision != 0 && precision != 1) return APIC_EINVAL;
+  const apic_status rc = ensure_twiddles();
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return precision == 0 ? fft2_c<c32>(l, batch, inverse != 0, in, out, st)
+                        : fft2_c<c64>(l, batch, inverse != 0, in, out, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,409 @@
+// Brightfield half of the reconstruction (Fig. 2 upper part): image
+// statistics, Kramers-Kronig recovery (Eq. 4-7), pupil normal equations and
+// solve (Eq. 8-10), and correction + stitching (text after Eq. 10).
+#pragma once
+
+#include "fft.hpp"
+#include "zern.hpp"
+
+namespace apic {
+
+// ---------------------------------------------------------------- statistics
+// Mean of every NA-matched image -> log floor eps = log_floor_rel * mean(I);
+// flags non-finite input and floor hits.
+__global__ __launch_bounds__(256) void k_image_stats(ClassArgs a) {
+  const int t = blockIdx.x / a.n_bf, i = blockIdx.x % a.n_bf;
+  const float *img = a.image(t, i);
+  const int nn = a.n * a.n;
+  double s = 0.0;
+  float mn = 3.0e38f;
+  int bad = 0;
+  for (int p = threadIdx.x; p < nn; p += 256) {
+    const float v = img[p];
+    if (!isfinite(v)) bad = 1;
+    else {
+      s += v;
+      mn = fminf(mn, v);
+    }
+  }
+  __shared__ double ss[256];
+  __shared__ float sm[256];
+  __shared__ int sb;
+  if (threadIdx.x == 0) sb = 0;
+  ss[threadIdx.x] = s;
+  sm[threadIdx.x] = mn;
+  __syncthreads();
+  if (bad) atomicOr(&sb, 1);
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      sm[threadIdx.x] = fminf(sm[threadIdx.x], sm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float eps = (float)(a.log_floor_rel * (ss[0] / nn));
+    a.at<float>(t, a.lay.eps)[i] = eps;
+    uint32_t bits = 0;
+    if (sb) bits |= APIC_TILE_NONFINITE_INPUT;
+    if (sm[0] < eps) bits |= APIC_TILE_LOG_FLOOR;
+    if (bits) status_or(a, t, bits);
+  }
+}
+
+// ---------------------------------------------------------------- KK passes
+// Pass 1 (rows): L = log(max(I, eps)), row FFT.
+template <int N> struct OpKK1 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c32 load(int arr, int y, int x) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    const float v = a.image(t, i)[y * N + x];
+    const float eps = a.at<float>(t, a.lay.eps)[i];
+    return make_float2(logf(fmaxf(v, eps)), 0.f);
+  }
+  __device__ void mid(int, int, int, c32 &) const {}
+  __device__ void store(int arr, int y, int x, c32 v) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x] = v;
+  }
+};
+
+// Pass 2 (columns): column FFT completes Lambda = fft2(L); multiply by Eq. 5's
+// half-plane weights (1, 1/2, 0 by the sign of the integer k.k_i); column IFFT.
+template <int N> struct OpKK2 {
+  static constexpr bool INV1 = false, TWO = true, INV2 = true;
+  ClassArgs a;
+  __device__ c32 load(int arr, int y, int x) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    return a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x];
+  }
+  __device__ void mid(int arr, int y, int x, c32 &v) const {
+    const int i = arr % a.n_bf;
+    const int dot = signed_idx(x, N) * a.kx[i] + signed_idx(y, N) * a.ky[i];
+    const float m = dot < 0 ? 1.f : (dot == 0 ? 0.5f : 0.f);
+    v = cscale(v, m);
+  }
+  __device__ void store(int arr, int y, int x, c32 v) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x] = v;
+  }
+};
+
+// Pass 3 (rows): row IFFT completes ifft2(G) (times N^2); s = exp(. / N^2)
+// (Eq. 6); row FFT.
+template <int N> struct OpKK3 {
+  static constexpr bool INV1 = true, TWO = true, INV2 = false;
+  ClassArgs a;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c32 load(int arr, int y, int x) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    return a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x];
+  }
+  __device__ void mid(int, int, int, c32 &v) const {
+    constexpr float inv = 1.0f / (float(N) * float(N));
+    const float mag = expf(v.x * inv);
+    float sn, cs;
+    sincosf(v.y * inv, &sn, &cs);
+    v = make_float2(mag * cs, mag * sn);
+  }
+  __device__ void store(int arr, int y, int x, c32 v) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x] = v;
+  }
+};
+
+// Pass 4 (columns): column FFT completes fft2(s); keep the pupil support
+// Circ(k + k_i) (Eq. 7) -> KK stack.  `out` (optional) receives a copy.
+template <int N> struct OpKK4 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  c32 *out;  // [T][n_bf][N][N] or nullptr
+  __device__ c32 load(int arr, int y, int x) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    return a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x];
+  }
+  __device__ void mid(int, int, int, c32 &) const {}
+  __device__ void store(int arr, int y, int x, c32 v) const {
+    const int t = arr / a.n_bf, i = arr % a.n_bf;
+    const int ky = signed_idx(y, N), kx = signed_idx(x, N);
+    if (!a.circ(ky + a.ky[i], kx + a.kx[i])) v = make_float2(0.f, 0.f);
+    a.at<c32>(t, a.lay.stack)[((int64_t)i * N + y) * N + x] = v;
+    if (out) out[(((int64_t)t * a.n_bf + i) * N + y) * N + x] = v;
+  }
+};
+
+// ---------------------------------------------------------------- pupil solve
+// One row of Eq. 10 per (pair, K): beta = arg(s_i conj(s_l)), w = |s_i s_l|,
+// a_j = Z_j(K+k_i) - Z_j(K+k_l) - Z_j(k_i) + Z_j(k_l).  A workgroup takes a
+// chunk of rows of one tile, stages (w a, a, beta, w, cell) of 256 rows in
+// LDS, and 124 threads accumulate one normal-equation entry each in FP64:
+// 78 entries of A's upper triangle, 12 of b, sum w beta^2, sum w, 32 cells.
+__global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float *seed) {
+  const int t = blockIdx.x / a.n_chunks, chunk = blockIdx.x % a.n_chunks;
+  __shared__ float s_wa[256][13];
+  __shared__ float s_a[256][13];
+  __shared__ float s_beta[256], s_w[256];
+  __shared__ int s_cell[256];
+  const int tid = threadIdx.x;
+  // entry owned by this thread
+  int p = 0, q = 0;
+  if (tid < 78) {  // upper-triangle index -> (p, q), p <= q
+    int rem = tid;
+    p = 0;
+    while (rem >= 12 - p) {
+      rem -= 12 - p;
+      ++p;
+    }
+    q = p + rem;
+  }
+  float c0[12];
+  const bool seeded = seed != nullptr;
+  if (seeded) {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) c0[j] = seed[(int64_t)a.gidx(t) * 15 + 3 + j];
+  }
+  const c32 *stack = a.at<c32>(t, a.lay.stack);
+  const int nn = a.n * a.n;
+  double acc = 0.0;
+  const int row_end = min(a.n_rows, (chunk + 1) * kAbChunk);
+  for (int rb = chunk * kAbChunk; rb < row_end; rb += 256) {
+    const int row = rb + tid;
+    float w = 0.f, beta = 0.f, av[12];
+    int cell = -1;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) av[j] = 0.f;
+    if (row < row_end) {
+      const uint32_t il = a.row_il[row], kw = a.row_k[row];
+      const int i = il & 0xff, l = (il >> 8) & 0xff;
+      cell = (int)(il >> 16);
+      const int Ky = kunpack_y(kw), Kx = kunpack_x(kw);
+      const int pos = fft_pos(Ky, a.n) * a.n + fft_pos(Kx, a.n);
+      const c32 si = stack[(int64_t)i * nn + pos], sl = stack[(int64_t)l * nn + pos];
+      const c32 z = cmulc(si, sl);
+      beta = atan2f(z.y, z.x);
+      w = hypotf(z.x, z.y);
+      float zi[12], zl[12], zi0[12], zl0[12];
+      zernike12((float)(Kx + a.kx[i]), (float)(Ky + a.ky[i]), a.inv_r, zi);
+      zernike12((float)(Kx + a.kx[l]), (float)(Ky + a.ky[l]), a.inv_r, zl);
+      zernike12((float)a.kx[i], (float)a.ky[i], a.inv_r, zi0);
+      zernike12((float)a.kx[l], (float)a.ky[l], a.inv_r, zl0);
+#pragma unroll
+      for (int j = 0; j < 12; ++j) av[j] = (zi[j] - zi0[j]) - (zl[j] - zl0[j]);
+      if (seeded) {
+        float pred = 0.f;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) pred = fmaf(av[j], c0[j], pred);
+        const float d = beta - pred;
+        beta = d - 6.283185307179586f * rintf(d * 0.15915494309189535f);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      s_wa[tid][j] = w * av[j];
+      s_a[tid][j] = av[j];
+    }
+    s_beta[tid] = beta;
+    s_w[tid] = w;
+    s_cell[tid] = cell;
+    __syncthreads();
+    if (tid < 78) {
+      for (int r = 0; r < 256; ++r) acc += (double)(s_wa[r][p] * s_a[r][q]);
+    } else if (tid < 90) {
+      const int pp = tid - 78;
+      for (int r = 0; r < 256; ++r) acc += (double)(s_wa[r][pp] * s_beta[r]);
+    } else if (tid == 90) {
+      for (int r = 0; r < 256; ++r) acc += (double)(s_w[r] * s_beta[r] * s_beta[r]);
+    } else if (tid == 91) {
+      for (int r = 0; r < 256; ++r) acc += (double)s_w[r];
+    } else if (tid < kAbEntries) {
+      const int cc = tid - 92;
+      for (int r = 0; r < 256; ++r) acc += (s_cell[r] == cc) ? (double)s_w[r] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (tid < kAbEntries)
+    a.at<double>(t, a.lay.part)[(int64_t)chunk * kAbEntries + tid] = acc;
+}
+
+// Sum the chunk partials of each tile in a fixed order (deterministic).
+__global__ __launch_bounds__(128) void k_pupil_reduce(ClassArgs a) {
+  const int t = blockIdx.x, e = threadIdx.x;
+  if (e >= kAbEntries) return;
+  const double *part = a.at<double>(t, a.lay.part);
+  double s = 0.0;
+  for (int c = 0; c < a.n_chunks; ++c) s += part[(int64_t)c * kAbEntries + e];
+  a.at<double>(t, a.lay.sums)[e] = s;
+}
+
+// Eigenvalues of a symmetric 12x12 matrix by cyclic Jacobi (kappa = max/min).
+__device__ inline void jacobi_eig12(double m[12][12], double ev[12]) {
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < 12; ++i)
+      for (int j = 0; j < 12; ++j) {
+        tot += m[i][j] * m[i][j];
+        if (i != j) off += m[i][j] * m[i][j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < 11; ++p)
+      for (int q = p + 1; q < 12; ++q) {
+        if (m[p][q] == 0.0) continue;
+        const double th = (m[q][q] - m[p][p]) / (2.0 * m[p][q]);
+        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
+        for (int k = 0; k < 12; ++k) {
+          const double mkp = m[k][p], mkq = m[k][q];
+          m[k][p] = c * mkp - s * mkq;
+          m[k][q] = s * mkp + c * mkq;
+        }
+        for (int k = 0; k < 12; ++k) {
+          const double mpk = m[p][k], mqk = m[q][k];
+          m[p][k] = c * mpk - s * mqk;
+          m[q][k] = s * mpk + c * mqk;
+        }
+      }
+  }
+  for (int i = 0; i < 12; ++i) ev[i] = m[i][i];
+}
+
+// One thread per tile: c_J = (A + mu tr(A)/12 I)^-1 b by FP64 Cholesky;
+// diagnostics R(c) = (sum w beta^2 - 2 c.b + c.A.c)/sum w, kappa(A), sum w,
+// smallest pivot; surrogate features log1p(cell / N^4).
+__global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *seed,
+                                                    float *zout, float *diag, float *feat) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= a.T) return;
+  const double *s = a.at<double>(t, a.lay.sums);
+  double A[12][12], L[12][12], b[12], x[12];
+  int e = 0;
+  for (int p = 0; p < 12; ++p)
+    for (int q = p; q < 12; ++q, ++e) A[p][q] = A[q][p] = s[e];
+  for (int p = 0; p < 12; ++p) b[p] = s[78 + p];
+  const double sbb = s[90], sw = s[91];
+  double tr = 0.0;
+  for (int p = 0; p < 12; ++p) tr += A[p][p];
+  const double mu = a.ridge_pupil * tr / 12.0;
+  double minpiv = 1e300;
+  uint32_t bits = seed ? APIC_TILE_SEEDED : 0u;
+  for (int j = 0; j < 12; ++j) {
+    double d = A[j][j] + mu;
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    minpiv = fmin(minpiv, d);
+    if (!(d > 0.0)) {
+      bits |= APIC_TILE_PUPIL_CHOL_FAIL;
+      d = fmax(fabs(tr), 1e-300) * 1e-12;
+    }
+    L[j][j] = sqrt(d);
+    for (int i = j + 1; i < 12; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  for (int i = 0; i < 12; ++i) {
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= L[i][k] * x[k];
+    x[i] = v / L[i][i];
+  }
+  for (int i = 11; i >= 0; --i) {
+    double v = x[i];
+    for (int k = i + 1; k < 12; ++k) v -= L[k][i] * x[k];
+    x[i] = v / L[i][i];
+  }
+  double cb = 0.0, cac = 0.0;
+  for (int p = 0; p < 12; ++p) {
+    cb += x[p] * b[p];
+    double r = 0.0;
+    for (int q = 0; q < 12; ++q) r += A[p][q] * x[q];
+    cac += x[p] * r;
+  }
+  const double resid = (sbb - 2.0 * cb + cac) / sw;
+  double ev[12];
+  jacobi_eig12(A, ev);
+  double emax = ev[0], emin = ev[0];
+  for (int i = 1; i < 12; ++i) {
+    emax = fmax(emax, ev[i]);
+    emin = fmin(emin, ev[i]);
+  }
+  const double kappa = emin > 0 ? emax / emin : 1e300;
+  if (kappa > 1e6) bits |= APIC_TILE_PUPIL_ILLCOND;
+  const int g = a.gidx(t);
+  float *co = a.at<float>(t, a.lay.coef);
+  for (int j = 0; j < 12; ++j) {
+    double cj = x[j];
+    if (seed) cj += (double)seed[(int64_t)g * 15 + 3 + j];
+    if (!isfinite(cj)) bits |= APIC_TILE_NONFINITE_OUT;
+    co[j] = (float)cj;
+    if (zout) zout[(int64_t)g * 15 + 3 + j] = (float)cj;
+  }
+  if (zout)
+    for (int j = 0; j < 3; ++j) zout[(int64_t)g * 15 + j] = 0.f;
+  if (diag) {
+    diag[(int64_t)g * 4 + 0] = (float)resid;
+    diag[(int64_t)g * 4 + 1] = (float)kappa;
+    diag[(int64_t)g * 4 + 2] = (float)sw;
+    diag[(int64_t)g * 4 + 3] = (float)minpiv;
+  }
+  if (feat) {
+    const double n4 = (double)a.n * a.n * (double)a.n * a.n;
+    for (int c = 0; c < kNumFeat; ++c) feat[(int64_t)g * kNumFeat + c] = (float)log1p(s[92 + c] / n4);
+  }
+  if (bits) status_or(a, t, bits);
+}
+
+// Copy caller-given coefficients into the tile's coefficient block.
+__global__ __launch_bounds__(64) void k_coef_load(ClassArgs a, const float *zin) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= a.T) return;
+  float *co = a.at<float>(t, a.lay.coef);
+  for (int j = 0; j < 12; ++j) co[j] = zin[(int64_t)a.gidx(t) * 15 + 3 + j];
+}
+
+// phi_c(k_i) of every illumination vector (the constant offsets theta_i).
+__global__ __launch_bounds__(64) void k_coef_led_phase(ClassArgs a) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= a.T) return;
+  float *co = a.at<float>(t, a.lay.coef);
+  float c[12];
+  for (int j = 0; j < 12; ++j) c[j] = co[j];
+  for (int i = 0; i < a.n_img; ++i)
+    co[16 + i] = pupil_phase12(c, (float)a.kx[i], (float)a.ky[i], a.inv_r);
+}
+
+// ---------------------------------------------------------------- stitch
+// O_hat(k) = mean over covering i of s_i(k) exp(-j[phi_c(k+k_i) - phi_c(k_i)]).
+__global__ __launch_bounds__(256) void k_stitch(ClassArgs a, float *spec_out) {
+  const int nn = a.n * a.n;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (int64_t)a.T * nn) return;
+  const int t = (int)(gid / nn), pix = (int)(gid % nn);
+  const int ky = signed_idx(pix / a.n, a.n), kx = signed_idx(pix % a.n, a.n);
+  const float *co = a.at<float>(t, a.lay.coef);
+  float c[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) c[j] = co[j];
+  const c32 *stack = a.at<c32>(t, a.lay.stack);
+  float ax = 0.f, ay = 0.f;
+  int cnt = 0;
+  for (int i = 0; i < a.n_bf; ++i) {
+    const int qy = ky + a.ky[i], qx = kx + a.kx[i];
+    if (!a.circ(qy, qx)) continue;
+    const float ph = pupil_phase12(c, (float)qx, (float)qy, a.inv_r) - co[16 + i];
+    float sn, cs;
+    sincosf(ph, &sn, &cs);
+    const c32 v = stack[(int64_t)i * nn + pix];
+    ax += v.x * cs + v.y * sn;  // v * exp(-j ph)
+    ay += v.y * cs - v.x * sn;
+    ++cnt;
+  }
+  const float inv = cnt ? 1.f / (float)cnt : 0.f;
+  const c32 o = make_float2(ax * inv, ay * inv);
+  a.at<c32>(t, a.lay.ohat)[pix] = o;
+  if (spec_out) reinterpret_cast<c32 *>(spec_out)[a.out_off(t) + pix] = o;
+}
+
+}  // namespace apic

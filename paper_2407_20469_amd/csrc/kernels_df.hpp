@@ -1,0 +1,472 @@
+// Darkfield half of the reconstruction (Fig. 2 lower part, Eq. 11-13) and the
+// upsampled output.  For darkfield image j (known set P, unknown set U, linear
+// region Q, excluded set E = (P - U) - Q, all plan tables):
+//
+//   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P              (k_df_phat)
+//   fpp      = fft2(|ifft2 P_hat|^2)        FP64 passes          (OpP*)
+//   fimg     = fft2(I_j)                    FP64 passes          (OpImg*)
+//   b(k)     = conj(fimg(k) - fpp(k)),  k in Q                   (k_df_rhs_b)
+//   G[u,u']  = sum_{k in Q} P_hat(u+k) conj(P_hat(u'+k)) / N^4   (k_df_gram)
+//            = fpp(u - u') / N^2 - sum_{k in E} P_hat(u+k) conj(P_hat(u'+k)) / N^4
+//   v[u]     = sum_{k in Q} P_hat(u+k) b(k) / N^2                (k_df_rhs_v)
+//   x        = (G + lambda tr(G)/N_u I)^-1 v   FP64 Cholesky     (k_df_chol)
+//   O_hat(u) = x(u) exp(-j phi_c(u + k_j)),  u in U              (k_df_scatter)
+//
+// The gram identity: the sum over every k of P_hat(u+k) conj(P_hat(u'+k)) is
+// the autocorrelation of P_hat at u' - u, which is N^2 fpp(u - u'); Q and E
+// partition P - U, so the Q-sum is that minus the (smaller) E-sum.
+#pragma once
+
+#include "fft.hpp"
+#include "zern.hpp"
+
+namespace apic {
+
+__global__ __launch_bounds__(256) void k_df_phat(ClassArgs a, StepArgs s) {
+  const int nn = a.n * a.n;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (int64_t)a.T * nn) return;
+  const int t = (int)(gid / nn), pix = (int)(gid % nn);
+  const int ky = signed_idx(pix / a.n, a.n), kx = signed_idx(pix % a.n, a.n);
+  c64 v = make_double2(0.0, 0.0);
+  const int qy = ky + s.ky, qx = kx + s.kx;
+  if (a.circ(qy, qx) && a.known_at[pix] < s.j) {
+    const float *co = a.at<float>(t, a.lay.coef);
+    float c[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) c[j] = co[j];
+    const float ph = pupil_phase12(c, (float)qx, (float)qy, a.inv_r);
+    float sn, cs;
+    sincosf(ph, &sn, &cs);
+    const c32 o = a.at<c32>(t, a.lay.ohat)[pix];
+    v = make_double2((double)o.x * cs - (double)o.y * sn, (double)o.x * sn + (double)o.y * cs);
+  }
+  a.at<c64>(t, a.lay.phat)[pix] = v;
+}
+
+// P chain, pass 1 (rows): row IFFT of P_hat.
+template <int N> struct OpP1 {
+  static constexpr bool INV1 = true, TWO = false, INV2 = false;
+  ClassArgs a;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.phat)[y * N + x]; }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+};
+// Pass 2 (columns): column IFFT gives N^2 P; |P|^2 = |.|^2 / N^4; column FFT.
+template <int N> struct OpP2 {
+  static constexpr bool INV1 = true, TWO = true, INV2 = false;
+  ClassArgs a;
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  __device__ void mid(int, int, int, c64 &v) const {
+    constexpr double inv4 = 1.0 / ((double)N * N * (double)N * N);
+    v = make_double2((v.x * v.x + v.y * v.y) * inv4, 0.0);
+  }
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+};
+// Pass 3 (rows): row FFT completes fpp = fft2(|P|^2).
+template <int N> struct OpP3 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fpp)[y * N + x] = v; }
+};
+// fft2 of the darkfield image in FP64: rows, then columns in place.
+template <int N> struct OpImg1 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  int img;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c64 load(int t, int y, int x) const {
+    return make_double2((double)a.image(t, img)[y * N + x], 0.0);
+  }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fimg)[y * N + x] = v; }
+};
+template <int N> struct OpImg2 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.fimg)[y * N + x]; }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fimg)[y * N + x] = v; }
+};
+
+// b(k) = conj(fft2(I_j)(k) - fft2(|P|^2)(k)) on Q (Eq. 13, conjugated).
+__global__ __launch_bounds__(256) void k_df_rhs_b(ClassArgs a, StepArgs s) {
+  const int t = blockIdx.y;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= s.m) return;
+  const uint32_t w = s.q[q];
+  const int pos = fft_pos(kunpack_y(w), a.n) * a.n + fft_pos(kunpack_x(w), a.n);
+  const c64 d = csub(a.at<c64>(t, a.lay.fimg)[pos], a.at<c64>(t, a.lay.fpp)[pos]);
+  a.at<c64>(t, a.lay.bvec)[q] = cconj(d);
+}
+
+__device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
+  if (!in_grid(ky, kx, n)) return make_double2(0.0, 0.0);
+  return phat[fft_pos(ky, n) * n + fft_pos(kx, n)];
+}
+
+// Gram of the darkfield system, 64 x 64 lower-triangle blocks (I >= J) of the
+// N_u x N_u Hermitian matrix; 16 x 16 threads, 4 x 4 complex outputs each.
+// Row operands P_hat(u + k) for 16 excluded k at a time are staged in LDS.
+constexpr int kGramKC = 16;
+__global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
+  const int nb = (s.nu + kGramBlock - 1) / kGramBlock;
+  const int ntri = nb * (nb + 1) / 2;
+  const int t = blockIdx.x / ntri;
+  int rem = blockIdx.x % ntri, I = 0;
+  while (rem > I) {
+    rem -= I + 1;
+    ++I;
+  }
+  const int J = rem;
+  const c64 *phat = a.at<c64>(t, a.lay.phat);
+  __shared__ c64 sA[kGramKC][kGramBlock];
+  __shared__ c64 sB[kGramKC][kGramBlock];
+  __shared__ uint32_t su[2][kGramBlock];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  if (tid < kGramBlock) {
+    const int ui = I * kGramBlock + tid, uj = J * kGramBlock + tid;
+    su[0][tid] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: far outside the grid
+    su[1][tid] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
+  }
+  c64 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int kc = 0; kc < s.ne; kc += kGramKC) {
+#pragma unroll
+    for (int m = 0; m < (kGramKC * kGramBlock) / 256; ++m) {
+      const int e = tid + m * 256;
+      const int kk = e / kGramBlock, uu = e % kGramBlock;
+      c64 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (kc + kk < s.ne) {
+        const uint32_t kw = s.e[kc + kk];
+        const int ky = kunpack_y(kw), kx = kunpack_x(kw);
+        const uint32_t wa = su[0][uu], wb = su[1][uu];
+        if (wa != 0x7fff7fffu) va = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
+        if (wb != 0x7fff7fffu) vb = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
+      }
+      sA[kk][uu] = va;
+      sB[kk][uu] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kGramKC; ++kk) {
+      c64 av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
+          acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
+          acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
+        }
+    }
+    __syncthreads();
+  }
+  const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
+  const c64 *fpp = a.at<c64>(t, a.lay.fpp);
+  c64 *G = a.at<c64>(t, a.lay.gram);
+  const int ld = a.nu_pad;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = I * kGramBlock + ty * 4 + i;
+    if (r >= s.nu) continue;
+    const uint32_t wr = su[0][ty * 4 + i];
+    const int ry = kunpack_y(wr), rx = kunpack_x(wr);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = J * kGramBlock + tx * 4 + j;
+      if (c >= s.nu) continue;
+      const uint32_t wc = su[1][tx * 4 + j];
+      const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
+      const c64 tv = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
+      G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,
+                                            tv.y * inv2 - acc[i][j].y * inv4);
+    }
+  }
+}
+
+// v[u] = N^-2 sum_{k in Q} P_hat(u + k) b(k)   (C^H b).
+__global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
+  const int t = blockIdx.y;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  const c64 *phat = a.at<c64>(t, a.lay.phat);
+  const c64 *b = a.at<c64>(t, a.lay.bvec);
+  __shared__ uint32_t sk[256];
+  __shared__ c64 sb[256];
+  int uy = 0, ux = 0;
+  if (u < s.nu) {
+    uy = kunpack_y(s.u[u]);
+    ux = kunpack_x(s.u[u]);
+  }
+  double vx = 0.0, vy = 0.0;
+  for (int q0 = 0; q0 < s.m; q0 += 256) {
+    const int q = q0 + threadIdx.x;
+    sk[threadIdx.x] = q < s.m ? s.q[q] : 0x7fff7fffu;
+    sb[threadIdx.x] = q < s.m ? b[q] : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (u < s.nu) {
+      const int lim = min(256, s.m - q0);
+      for (int k = 0; k < lim; ++k) {
+        const uint32_t kw = sk[k];
+        const c64 p = phat_at(phat, a.n, uy + kunpack_y(kw), ux + kunpack_x(kw));
+        const c64 bb = sb[k];
+        vx = fma(p.x, bb.x, fma(-p.y, bb.y, vx));
+        vy = fma(p.x, bb.y, fma(p.y, bb.x, vy));
+      }
+    }
+    __syncthreads();
+  }
+  if (u < s.nu) {
+    const double inv2 = 1.0 / ((double)a.n * a.n);
+    a.at<c64>(t, a.lay.vec)[u] = make_double2(vx * inv2, vy * inv2);
+  }
+}
+
+// Batched FP64 Cholesky of G + lambda tr(G)/N_u I (lower, in place, blocked
+// right-looking with 32-wide panels) and the two triangular solves for x.
+// One workgroup per tile matrix.
+constexpr int kCholNB = 32;
+__global__ __launch_bounds__(256) void k_df_chol(ClassArgs a, StepArgs s) {
+  const int t = blockIdx.x;
+  const int n = s.nu, ld = a.nu_pad, tid = threadIdx.x;
+  c64 *G = a.at<c64>(t, a.lay.gram);
+  c64 *vec = a.at<c64>(t, a.lay.vec);
+  __shared__ c64 D[kCholNB][kCholNB + 1];
+  __shared__ c64 Pi[kCholNB][kCholNB + 1];
+  __shared__ c64 Pj[kCholNB][kCholNB + 1];
+  __shared__ double red[256];
+  __shared__ int fail;
+  __shared__ c64 yb[kCholNB];
+  if (tid == 0) fail = 0;
+  // ridge lambda * tr(G) / N_u on the diagonal
+  double tr = 0.0;
+  for (int i = tid; i < n; i += 256) tr += G[(int64_t)i * ld + i].x;
+  red[tid] = tr;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double ridge = a.ridge_df * red[0] / n;
+  for (int i = tid; i < n; i += 256) G[(int64_t)i * ld + i].x += ridge;
+  __syncthreads();
+  const double tiny = fmax(fabs(red[0]) / n, 1e-300) * 1e-14;
+
+  for (int kb = 0; kb < n; kb += kCholNB) {
+    const int bs = min(kCholNB, n - kb);
+    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
+      const int r = e / kCholNB, c = e % kCholNB;
+      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c = 0; c < bs; ++c) {
+      if (tid == 0) {
+        double d = D[c][c].x;
+        if (!(d > 0.0)) {
+          fail = 1;
+          d = tiny;
+        }
+        D[c][c] = make_double2(sqrt(d), 0.0);
+      }
+      __syncthreads();
+      if (tid > c && tid < bs) {
+        const double inv = 1.0 / D[c][c].x;
+        D[tid][c] = cscale(D[tid][c], inv);
+      }
+      __syncthreads();
+      for (int e = tid; e < bs * bs; e += 256) {
+        const int r = e / bs, cc = e % bs;
+        if (cc > c && r >= cc) D[r][cc] = csub(D[r][cc], cmulc(D[r][c], D[cc][c]));
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
+      const int r = e / kCholNB, c = e % kCholNB;
+      if (r < bs && c <= r) G[(int64_t)(kb + r) * ld + kb + c] = D[r][c];
+    }
+    // panel solve: row i of the panel satisfies x L_kk^H = a
+    for (int i = kb + bs + tid; i < n; i += 256) {
+      c64 x[kCholNB];
+      c64 *row = G + (int64_t)i * ld + kb;
+#pragma unroll
+      for (int c = 0; c < kCholNB; ++c) {
+        if (c < bs) {
+          c64 v = row[c];
+          for (int p = 0; p < c; ++p) v = csub(v, cmulc(x[p], D[c][p]));
+          x[c] = cscale(v, 1.0 / D[c][c].x);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kCholNB; ++c)
+        if (c < bs) row[c] = x[c];
+    }
+    __syncthreads();
+    // trailing update A[I][J] -= L[I, panel] L[J, panel]^H over 32 x 32 tiles
+    const int r0 = kb + bs;
+    const int nt = (n - r0 + kCholNB - 1) / kCholNB;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int ti = 0; ti < ntiles; ++ti) {
+      int rem = ti, I = 0;
+      while (rem > I) {
+        rem -= I + 1;
+        ++I;
+      }
+      const int J = rem;
+      const int ib = r0 + I * kCholNB, jb = r0 + J * kCholNB;
+      for (int e = tid; e < kCholNB * kCholNB; e += 256) {
+        const int r = e / kCholNB, p = e % kCholNB;
+        Pi[r][p] = (ib + r < n && p < bs) ? G[(int64_t)(ib + r) * ld + kb + p] : make_double2(0.0, 0.0);
+        Pj[r][p] = (jb + r < n && p < bs) ? G[(int64_t)(jb + r) * ld + kb + p] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      const int ty = tid >> 4, tx = tid & 15;
+      c64 acc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = make_double2(0.0, 0.0);
+      for (int p = 0; p < bs; ++p) {
+        const c64 a0 = Pi[ty * 2][p], a1 = Pi[ty * 2 + 1][p];
+        const c64 b0 = Pj[tx * 2][p], b1 = Pj[tx * 2 + 1][p];
+        acc[0][0] = cadd(acc[0][0], cmulc(a0, b0));
+        acc[0][1] = cadd(acc[0][1], cmulc(a0, b1));
+        acc[1][0] = cadd(acc[1][0], cmulc(a1, b0));
+        acc[1][1] = cadd(acc[1][1], cmulc(a1, b1));
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int r = ib + ty * 2 + i, c = jb + tx * 2 + j;
+          if (r < n && c < n && c <= r) {
+            c64 *gp = G + (int64_t)r * ld + c;
+            *gp = csub(*gp, acc[i][j]);
+          }
+        }
+      __syncthreads();
+    }
+  }
+  // forward substitution L y = v (in place in vec)
+  for (int kb = 0; kb < n; kb += kCholNB) {
+    const int bs = min(kCholNB, n - kb);
+    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
+      const int r = e / kCholNB, c = e % kCholNB;
+      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
+    }
+    if (tid < bs) yb[tid] = vec[kb + tid];
+    __syncthreads();
+    for (int c = 0; c < bs; ++c) {
+      if (tid == 0) yb[c] = cscale(yb[c], 1.0 / D[c][c].x);
+      __syncthreads();
+      if (tid > c && tid < bs) yb[tid] = csub(yb[tid], cmul(D[tid][c], yb[c]));
+      __syncthreads();
+    }
+    if (tid < bs) vec[kb + tid] = yb[tid];
+    for (int i = kb + bs + tid; i < n; i += 256) {
+      c64 v = vec[i];
+      const c64 *row = G + (int64_t)i * ld + kb;
+      for (int p = 0; p < bs; ++p) v = csub(v, cmul(row[p], yb[p]));
+      vec[i] = v;
+    }
+    __syncthreads();
+  }
+  // back substitution L^H x = y
+  const int nblk = (n + kCholNB - 1) / kCholNB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int kb = bi * kCholNB, bs = min(kCholNB, n - kb);
+    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
+      const int r = e / kCholNB, c = e % kCholNB;
+      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
+    }
+    if (tid < bs) yb[tid] = vec[kb + tid];
+    __syncthreads();
+    for (int c = bs - 1; c >= 0; --c) {
+      if (tid == 0) yb[c] = cscale(yb[c], 1.0 / D[c][c].x);
+      __syncthreads();
+      if (tid < c) yb[tid] = csub(yb[tid], cmul(cconj(D[c][tid]), yb[c]));
+      __syncthreads();
+    }
+    if (tid < bs) vec[kb + tid] = yb[tid];
+    for (int i = tid; i < kb; i += 256) {
+      c64 v = vec[i];
+      for (int p = 0; p < bs; ++p) v = csub(v, cmul(cconj(G[(int64_t)(kb + p) * ld + i]), yb[p]));
+      vec[i] = v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && fail) status_or(a, t, APIC_TILE_DF_CHOL_FAIL);
+}
+
+// O_hat(u) = x(u) exp(-j phi_c(u + k_j)) on U.
+__global__ __launch_bounds__(256) void k_df_scatter(ClassArgs a, StepArgs s) {
+  const int t = blockIdx.y;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= s.nu) return;
+  const uint32_t w = s.u[u];
+  const int ky = kunpack_y(w), kx = kunpack_x(w);
+  const float *co = a.at<float>(t, a.lay.coef);
+  float c[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) c[j] = co[j];
+  const float ph = pupil_phase12(c, (float)(kx + s.kx), (float)(ky + s.ky), a.inv_r);
+  float sn, cs;
+  sincosf(ph, &sn, &cs);
+  const c64 x = a.at<c64>(t, a.lay.vec)[u];
+  const int pos = fft_pos(ky, a.n) * a.n + fft_pos(kx, a.n);
+  a.at<c32>(t, a.lay.ohat)[pos] =
+      make_float2((float)(x.x * cs + x.y * sn), (float)(x.y * cs - x.x * sn));
+}
+
+// Output pass 1 (rows of the fN grid that carry spectrum, i.e. |ky| < N/2):
+// zero-embed the N x N spectrum and row-IFFT.
+template <int NF> struct OpOut1 {
+  static constexpr bool INV1 = true, TWO = false, INV2 = false;
+  ClassArgs a;
+  const c32 *src;     // if set: spectra at src + t * N * N, else the tile's O_hat
+  __device__ int rows() const { return a.n; }
+  __device__ int row_of(int r) const { return fft_pos(signed_idx(r, a.n), NF); }
+  __device__ c32 load(int t, int y, int x) const {
+    const int ky = signed_idx(y, NF), kx = signed_idx(x, NF);
+    const int h = a.n >> 1;
+    if (kx < -h || kx >= h) return make_float2(0.f, 0.f);
+    const int pos = fft_pos(ky, a.n) * a.n + fft_pos(kx, a.n);
+    return src ? src[(int64_t)t * a.n * a.n + pos] : a.at<c32>(t, a.lay.ohat)[pos];
+  }
+  __device__ void mid(int, int, int, c32 &) const {}
+  __device__ void store(int t, int y, int x, c32 v) const {
+    a.at<c32>(t, a.lay.stack)[(int64_t)y * NF + x] = v;
+  }
+};
+// Output pass 2 (columns): rows without spectrum are zero; column IFFT,
+// scale f^2 / (fN)^2 = 1 / N^2, store the field.
+template <int NF> struct OpOut2 {
+  static constexpr bool INV1 = true, TWO = false, INV2 = false;
+  ClassArgs a;
+  c32 *field;
+  __device__ c32 load(int t, int y, int x) const {
+    const int ky = signed_idx(y, NF), h = a.n >> 1;
+    if (ky < -h || ky >= h) return make_float2(0.f, 0.f);
+    return a.at<c32>(t, a.lay.stack)[(int64_t)y * NF + x];
+  }
+  __device__ void mid(int, int, int, c32 &) const {}
+  __device__ void store(int t, int y, int x, c32 v) const {
+    const float inv = 1.0f / ((float)a.n * (float)a.n);
+    field[a.out_off(t) + (int64_t)y * NF + x] = cscale(v, inv);
+  }
+};
+
+}  // namespace apic

@@ -1,0 +1,224 @@
+// Geometry plan builder (host only).  Builds, for one geometry class, the
+// index sets the kernels consume:
+//   - pupil rows: every overlapping pair i < l and every K != 0 in the overlap
+//     S_il of Eq. 8, with the surrogate feature cell of the row;
+//   - darkfield steps: for each darkfield image in processing order the known
+//     set P, the unknown set U, the linear region Q of Eq. 13 and the excluded
+//     part E of P - U (used by the gram identity), plus the map of the step at
+//     which each frequency became known.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace apic {
+
+namespace {
+
+bool is_pow2_size(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
+
+inline int signed_of(int idx, int n) { return idx < n / 2 ? idx : idx - n; }
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Pair-angle bin (8 bins over (0, pi]) of two illumination vectors.
+int angle_bin(int kix, int kiy, int klx, int kly) {
+  const double dot = double(kix) * klx + double(kiy) * kly;
+  const double ni = std::sqrt(double(kix) * kix + double(kiy) * kiy);
+  const double nl = std::sqrt(double(klx) * klx + double(kly) * kly);
+  double c = dot / (ni * nl);
+  c = std::min(1.0, std::max(-1.0, c));
+  const double ang = std::acos(c);
+  double b = std::ceil(ang / (M_PI / 8.0) - 1e-9) - 1.0;
+  b = std::min(7.0, std::max(0.0, b));
+  return int(b);
+}
+
+// Radial band (4 bands of |K| / (2r) over (0, 1]).
+int radial_band(int ky, int kx, double r) {
+  const double rho = std::hypot(double(kx), double(ky)) / (2.0 * r);
+  double b = std::ceil(4.0 * rho - 1e-9) - 1.0;
+  b = std::min(3.0, std::max(0.0, b));
+  return int(b);
+}
+
+}  // namespace
+
+apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
+  if (!is_pow2_size(g.n)) return APIC_EUNSUPPORTED;
+  if (g.upsample != 1 && g.upsample != 2) return APIC_EUNSUPPORTED;
+  if (g.n * g.upsample > 1024) return APIC_EUNSUPPORTED;
+  if (g.n_bf < 4 || g.n_bf > kMaxBf || g.n_df < 0 || g.n_df > kMaxDf) return APIC_EUNSUPPORTED;
+  if (!g.k_bf || (g.n_df > 0 && !g.k_df)) return APIC_EINVAL;
+  if (!(g.dx_um > 0) || !(g.wavelength_um > 0) || !(g.na_obj > 0)) return APIC_EINVAL;
+  if (!(g.ridge_pupil >= 0) || !(g.ridge_darkfield >= 0) || !(g.log_floor_rel > 0))
+    return APIC_EINVAL;
+
+  const int n = g.n;
+  p.n = n;
+  p.f = g.upsample;
+  p.nf = n * g.upsample;
+  p.n_bf = g.n_bf;
+  p.n_df = g.n_df;
+  p.dx = g.dx_um;
+  p.lam = g.wavelength_um;
+  p.na = g.na_obj;
+  p.r = g.na_obj * n * g.dx_um / g.wavelength_um;
+  p.r2 = (int64_t)std::floor(p.r * p.r);
+  p.ridge_pupil = g.ridge_pupil;
+  p.ridge_df = g.ridge_darkfield;
+  p.log_floor_rel = g.log_floor_rel;
+  if (p.r < 2.0) return APIC_EUNSUPPORTED;
+  p.kbf.assign(g.k_bf, g.k_bf + 2 * g.n_bf);
+  p.kdf.assign(g.k_df ? g.k_df : g.k_bf, (g.k_df ? g.k_df : g.k_bf) + 2 * g.n_df);
+
+  auto circ = [&](int ky, int kx) { return int64_t(kx) * kx + int64_t(ky) * ky <= p.r2; };
+  // Every shifted support must stay inside the grid: |k| + r < N/2.
+  for (int i = 0; i < g.n_bf + g.n_df; ++i) {
+    const int kx = i < g.n_bf ? p.kbf[2 * i] : p.kdf[2 * (i - g.n_bf)];
+    const int ky = i < g.n_bf ? p.kbf[2 * i + 1] : p.kdf[2 * (i - g.n_bf) + 1];
+    const double mag = std::sqrt(double(kx) * kx + double(ky) * ky);
+    if (mag + p.r >= n / 2 - 1) return APIC_EUNSUPPORTED;
+    if (i < g.n_bf && !circ(ky, kx)) return APIC_EINVAL;  // NA-matched must sit in the pupil
+  }
+
+  // ---- pupil rows (Eq. 8-10)
+  p.row_il.clear();
+  p.row_k.clear();
+  p.n_pairs = 0;
+  for (int i = 0; i < g.n_bf; ++i) {
+    const int kix = p.kbf[2 * i], kiy = p.kbf[2 * i + 1];
+    for (int l = i + 1; l < g.n_bf; ++l) {
+      const int klx = p.kbf[2 * l], kly = p.kbf[2 * l + 1];
+      const int abin = angle_bin(kix, kiy, klx, kly);
+      size_t before = p.row_k.size();
+      for (int y = 0; y < n; ++y) {
+        const int ky = signed_of(y, n);
+        for (int x = 0; x < n; ++x) {
+          const int kx = signed_of(x, n);
+          if (ky == 0 && kx == 0) continue;
+          if (!circ(ky + kiy, kx + kix) || !circ(ky + kly, kx + klx)) continue;
+          const int cell = abin * 4 + radial_band(ky, kx, p.r);
+          p.row_il.push_back(uint32_t(i) | (uint32_t(l) << 8) | (uint32_t(cell) << 16));
+          p.row_k.push_back(pack_k(ky, kx));
+        }
+      }
+      if (p.row_k.size() > before) ++p.n_pairs;
+    }
+  }
+  p.n_rows = int(p.row_k.size());
+  p.n_chunks = std::max(1, (p.n_rows + kAbChunk - 1) / kAbChunk);
+
+  // ---- darkfield sets (Eq. 11-13)
+  const int nn = n * n;
+  p.known_at.assign(nn, int16_t(32767));
+  std::vector<uint8_t> known(nn, 0);
+  for (int y = 0; y < n; ++y)
+    for (int x = 0; x < n; ++x) {
+      const int ky = signed_of(y, n), kx = signed_of(x, n);
+      for (int i = 0; i < g.n_bf; ++i)
+        if (circ(ky + p.kbf[2 * i + 1], kx + p.kbf[2 * i])) {
+          known[y * n + x] = 1;
+          p.known_at[y * n + x] = -1;
+          break;
+        }
+    }
+  const int W = 2 * n + 1;  // difference grid over [-N, N]^2
+  std::vector<uint8_t> mpu(size_t(W) * W), mex(size_t(W) * W);
+  p.steps.assign(g.n_df, DfStep());
+  p.coords.clear();
+  p.nu_max = p.np_max = p.m_max = p.ne_max = p.n_active = 0;
+  for (int j = 0; j < g.n_df; ++j) {
+    DfStep &st = p.steps[j];
+    st.kx = p.kdf[2 * j];
+    st.ky = p.kdf[2 * j + 1];
+    std::vector<uint32_t> U, P;
+    std::vector<std::pair<int, int>> Uc, Pc;
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const int ky = signed_of(y, n), kx = signed_of(x, n);
+        if (!circ(ky + st.ky, kx + st.kx)) continue;
+        if (known[y * n + x]) {
+          P.push_back(pack_k(ky, kx));
+          Pc.emplace_back(ky, kx);
+        } else {
+          U.push_back(pack_k(ky, kx));
+          Uc.emplace_back(ky, kx);
+        }
+      }
+    st.nu = int(U.size());
+    st.np = int(P.size());
+    st.off_u = int64_t(p.coords.size());
+    p.coords.insert(p.coords.end(), U.begin(), U.end());
+    st.off_p = int64_t(p.coords.size());
+    p.coords.insert(p.coords.end(), P.begin(), P.end());
+    st.off_q = st.off_e = int64_t(p.coords.size());
+    if (U.empty()) continue;
+    std::fill(mpu.begin(), mpu.end(), 0);
+    std::fill(mex.begin(), mex.end(), 0);
+    for (auto &u : Uc) {
+      for (auto &q : Pc) mpu[size_t(q.first - u.first + n) * W + (q.second - u.second + n)] = 1;
+      for (auto &q : Uc) mex[size_t(q.first - u.first + n) * W + (q.second - u.second + n)] = 1;
+    }
+    for (auto &q : Pc)  // U - P: a - b with a in U, b in P
+      for (auto &u : Uc) mex[size_t(u.first - q.first + n) * W + (u.second - q.second + n)] = 1;
+    int64_t n_pu = 0;
+    for (size_t i = 0; i < mpu.size(); ++i) n_pu += mpu[i];
+    std::vector<uint32_t> Q, E;
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const int ky = signed_of(y, n), kx = signed_of(x, n);
+        const size_t o = size_t(ky + n) * W + (kx + n);
+        if (!mpu[o]) continue;
+        (mex[o] ? E : Q).push_back(pack_k(ky, kx));
+      }
+    if (int64_t(Q.size() + E.size()) != n_pu) return APIC_EUNSUPPORTED;  // would wrap
+    st.m = int(Q.size());
+    st.ne = int(E.size());
+    st.off_q = int64_t(p.coords.size());
+    p.coords.insert(p.coords.end(), Q.begin(), Q.end());
+    st.off_e = int64_t(p.coords.size());
+    p.coords.insert(p.coords.end(), E.begin(), E.end());
+    for (auto &u : Uc) {
+      const int y = (u.first + n) % n, x = (u.second + n) % n;
+      known[y * n + x] = 1;
+      p.known_at[y * n + x] = int16_t(j);
+    }
+    ++p.n_active;
+    p.nu_max = std::max(p.nu_max, st.nu);
+    p.np_max = std::max(p.np_max, st.np);
+    p.m_max = std::max(p.m_max, st.m);
+    p.ne_max = std::max(p.ne_max, st.ne);
+  }
+  p.nu_pad = std::max(kGramBlock, (p.nu_max + kGramBlock - 1) / kGramBlock * kGramBlock);
+
+  // ---- per-tile workspace layout
+  TileLayout &L = p.lay;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const int64_t c32 = 8, c64 = 16;
+  const int64_t stack_bytes = std::max<int64_t>(int64_t(p.n_bf) * nn * c32,
+                                                int64_t(p.nf) * p.nf * c32);
+  L.stack = take(stack_bytes);
+  L.ohat = take(int64_t(nn) * c32);
+  L.phat = take(int64_t(nn) * c64);
+  L.dtmp = take(int64_t(nn) * c64);
+  L.fpp = take(int64_t(nn) * c64);
+  L.fimg = take(int64_t(nn) * c64);
+  L.bvec = take(std::max<int64_t>(1, p.m_max) * c64);
+  L.vec = take(int64_t(p.nu_pad) * c64);
+  L.gram = take(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256);
+  L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);
+  L.sums = take(128 * 8);
+  L.coef = take((16 + kMaxImg) * 4);
+  L.eps = take(kMaxImg * 4);
+  L.stride = o;
+  return APIC_OK;
+}
+
+}  // namespace apic

@@ -1,0 +1,75 @@
+// Host-side geometry plan: every index set of the method depends only on the
+// tile size, the pupil radius and the illumination vectors, so it is built
+// once per geometry class on the host and reused for every tile of the class.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/apic.h"
+
+namespace apic {
+
+constexpr int kMaxBf = 32;
+constexpr int kMaxDf = 64;
+constexpr int kMaxImg = kMaxBf + kMaxDf;
+constexpr int kNumJ = 12;           // Noll 4..15 carried by the pupil solve
+constexpr int kNumFeat = 32;        // 8 pair-angle bins x 4 radial bands
+constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cells
+constexpr int kAbChunk = 2048;      // pupil rows per workgroup
+constexpr int kGramBlock = 64;      // gram / Cholesky padding granularity
+constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
+
+// Signed (ky, kx) packed in one word: low half ky, high half kx (int16 each).
+inline uint32_t pack_k(int ky, int kx) {
+  return (uint32_t)(uint16_t)(int16_t)ky | ((uint32_t)(uint16_t)(int16_t)kx << 16);
+}
+inline int unpack_ky(uint32_t w) { return (int)(int16_t)(uint16_t)(w & 0xffffu); }
+inline int unpack_kx(uint32_t w) { return (int)(int16_t)(uint16_t)(w >> 16); }
+
+// One darkfield image's index sets (Eq. 11-13).
+struct DfStep {
+  int32_t kx = 0, ky = 0;
+  int32_t nu = 0, np = 0, m = 0, ne = 0;
+  int64_t off_u = 0, off_p = 0, off_q = 0, off_e = 0;  // into GeomPlan::coords
+};
+
+// Per-tile workspace layout (byte offsets from the tile's base).
+struct TileLayout {
+  int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, fimg = 0, bvec = 0, vec = 0,
+          gram = 0, part = 0, sums = 0, coef = 0, eps = 0, stride = 0;
+};
+
+struct GeomPlan {
+  int n = 0, f = 1, nf = 0, n_bf = 0, n_df = 0;
+  double dx = 0, lam = 0, na = 0, r = 0;
+  int64_t r2 = 0;                    // floor(r * r): Circ(k) <=> kx^2 + ky^2 <= r2
+  double ridge_pupil = 1e-9, ridge_df = 1e-4, log_floor_rel = 1e-6;
+  std::vector<int32_t> kbf, kdf;     // (kx, ky) pairs
+  // pupil rows (Eq. 8-10): one row per (pair, K) with K in S_il, K != 0
+  int n_pairs = 0, n_rows = 0, n_chunks = 0;
+  std::vector<uint32_t> row_il;      // i | l << 8 | feature cell << 16
+  std::vector<uint32_t> row_k;       // packed K
+  // darkfield (Eq. 11-13)
+  std::vector<int16_t> known_at;     // N*N in FFT order: -1 brightfield, j solved at step j,
+                                     // 32767 never known
+  std::vector<DfStep> steps;
+  std::vector<uint32_t> coords;      // packed U, P, Q, E lists of all steps
+  int nu_max = 0, np_max = 0, m_max = 0, ne_max = 0, n_active = 0, nu_pad = 0;
+  TileLayout lay;
+  // device copies (owned; filled by upload)
+  void *d_row_il = nullptr, *d_row_k = nullptr, *d_known_at = nullptr, *d_coords = nullptr;
+};
+
+// Build the host tables of one geometry; returns APIC_OK or an error code.
+apic_status build_geom_plan(const apic_geometry &g, GeomPlan &out);
+
+}  // namespace apic
+
+struct apic_plan {
+  uint32_t magic = apic::kPlanMagic;
+  std::vector<apic::GeomPlan> geoms;
+  int device = -1;
+  bool uploaded = false;
+};
