@@ -37,6 +37,18 @@ class Workload:
     def r(self):
         return self.na_obj * self.n * self.dx_um / self.wavelength_um
 
+    @property
+    def n_bf(self):
+        return len(self.k_bf)
+
+    @property
+    def n_df(self):
+        return len(self.k_df)
+
+    @property
+    def n_img(self):
+        return len(self.k_bf) + len(self.k_df)
+
     def object(self, tile):
         rng = np.random.default_rng([self.cfg_id, 0, tile])
         return self.obj_fn(rng, self.n)

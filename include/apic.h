@@ -196,6 +196,28 @@ apic_status apic_upsample_field(const apic_plan *plan, int32_t n_tiles,
 apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,
                       const void *in, void *out, void *stream);
 
+/* Opt-in profiling of kernel groups (for benchmarks).  apic_profile(1) clears
+ * and enables recording: every later launch of a group records a HIP event
+ * pair on the call's stream plus the group's algorithmic work; apic_profile(0)
+ * stops recording (and clears).  apic_profile_read waits for the recorded
+ * events and returns the summed duration, the number of recorded launches
+ * and the summed work of one group.  Work is flops for the FP64 groups
+ * (GRAM: 8 flops per complex MAC of the Hermitian E-sum; CHOL: (4/3) n^3 +
+ * 8 n^2) and compulsory HBM bytes for the others.  Recording creates HIP
+ * events, so it is not meant for graph capture. */
+#define APIC_PROF_KK 0     /* statistics + 4 fused KK passes        (bytes) */
+#define APIC_PROF_PUPIL 1  /* pupil rows, reduction, 12x12 solves   (bytes) */
+#define APIC_PROF_STITCH 2 /* correction + stitching                (bytes) */
+#define APIC_PROF_DF_FFT 3 /* P_hat, FP64 |P|^2 chain, image FFT    (bytes) */
+#define APIC_PROF_DF_RHS 4 /* b on Q and C^H b                      (bytes) */
+#define APIC_PROF_GRAM 5   /* darkfield gram                        (flops) */
+#define APIC_PROF_CHOL 6   /* darkfield Cholesky + solves           (flops) */
+#define APIC_PROF_OUT 7    /* embedding + upsampled inverse FFT     (bytes) */
+#define APIC_PROF_GROUPS 8
+apic_status apic_profile(int32_t enable);
+apic_status apic_profile_read(int32_t group, double *total_ms, int64_t *launches,
+                              double *total_work);
+
 /* Library version string. */
 const char *apic_version(void);
 

@@ -31,7 +31,9 @@ TILE_SKIP_DARKFIELD = 0x1
 EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_workspace_bytes",
            "apic_plan_query", "apic_reconstruct_tiles", "apic_estimate_pupil", "apic_kk_spectra",
            "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
-           "apic_version"]
+           "apic_profile", "apic_profile_read", "apic_version"]
+
+PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
 
 class ApicError(RuntimeError):
@@ -84,6 +86,9 @@ def load_library(path=LIB_PATH):
     lib.apic_extend_darkfield.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, sz, P]
     lib.apic_upsample_field.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
     lib.apic_fft2.argtypes = [i32, i32, i32, i32, P, P, P]
+    lib.apic_profile.argtypes = [i32]
+    lib.apic_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_char_p if name == "apic_version" else ctypes.c_int
     _lib = lib
@@ -315,6 +320,23 @@ def upsample_field(plan, spectrum, workspace=None, stream=None):
     wp, wb = ws.get(plan.workspace_bytes(descs), spec.device)
     _check("apic_upsample_field", plan.lib.apic_upsample_field(
         plan.handle, T, descs, _ptr(spec), _ptr(out), wp, wb, _stream(stream)))
+    return out
+
+
+def profile(enable):
+    """Start (True) or stop (False) recording kernel-group timings."""
+    _check("apic_profile", load_library().apic_profile(int(bool(enable))))
+
+
+def profile_read():
+    """{group: (total_ms, launches, total_work)} of the recorded launches."""
+    lib = load_library()
+    out = {}
+    for gid, name in enumerate(PROF_GROUPS):
+        ms, n, work = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check("apic_profile_read", lib.apic_profile_read(gid, ctypes.byref(ms), ctypes.byref(n),
+                                                          ctypes.byref(work)))
+        out[name] = (ms.value, n.value, work.value)
     return out
 
 

@@ -13,6 +13,7 @@
 #include "fft.hpp"
 #include "kernels_bf.hpp"
 #include "kernels_df.hpp"
+#include "chol.hpp"
 #include "plan.hpp"
 
 namespace apic {
@@ -54,6 +55,45 @@ apic_status ensure_twiddles() {
 }
 
 bool plan_ok(const apic_plan *p) { return p && p->magic == kPlanMagic && !p->geoms.empty(); }
+
+// ------------------------------------------------------------ profiling
+// Opt-in: HIP events recorded on the launch stream around each kernel group,
+// with the group's algorithmic work (flops or bytes) per launch.
+struct ProfEntry {
+  hipEvent_t e0, e1;
+  double work;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfEntry> g_prof[APIC_PROF_GROUPS];
+
+struct ProfScope {
+  int id;
+  double work;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(int id_, double work_, hipStream_t st_) : id(id_), work(work_), st(st_) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    (void)hipEventRecord(e0, st);
+  }
+  ~ProfScope() {
+    if (!e0 || !e1) return;
+    (void)hipEventRecord(e1, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[id].push_back({e0, e1, work});
+  }
+};
+
+void prof_clear() {
+  for (auto &v : g_prof) {
+    for (auto &e : v) {
+      (void)hipEventDestroy(e.e0);
+      (void)hipEventDestroy(e.e1);
+    }
+    v.clear();
+  }
+}
 
 template <class T> apic_status upload_vec(const std::vector<T> &v, void **dst) {
   const size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
@@ -230,6 +270,8 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 // ------------------------------------------------------------ stage runners
 template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t st) {
   const int arrays = a.T * a.n_bf;
+  // bytes: image read twice (stats, pass 1), 4 complex64 read+write passes minus pass-1 read
+  ProfScope ps(APIC_PROF_KK, (double)arrays * N * N * (4.0 + 4.0 + 8.0 * 7.0), st);
   hipLaunchKernelGGL(k_image_stats, dim3(arrays), dim3(256), 0, st, a);
   APIC_LAUNCHED();
   hipLaunchKernelGGL((k_rows<c32, N, OpKK1<N>>), dim3(row_blocks<c32, N>(arrays, N)),
@@ -249,6 +291,7 @@ template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t
 
 apic_status run_pupil(const ClassArgs &a, const float *seed, float *zout, float *diag,
                       float *feat, hipStream_t st) {
+  ProfScope ps(APIC_PROF_PUPIL, (double)a.T * a.n_rows * 16.0, st);  // two complex64 reads per row
   hipLaunchKernelGGL(k_pupil_partial, dim3(a.T * a.n_chunks), dim3(256), 0, st, a, seed);
   APIC_LAUNCHED();
   hipLaunchKernelGGL(k_pupil_reduce, dim3(a.T), dim3(128), 0, st, a);
@@ -260,6 +303,7 @@ apic_status run_pupil(const ClassArgs &a, const float *seed, float *zout, float 
 }
 
 apic_status run_stitch(const ClassArgs &a, float *spec_out, hipStream_t st) {
+  ProfScope ps(APIC_PROF_STITCH, (double)a.T * a.n * a.n * 8.0 * (a.n_bf + 1), st);
   hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);
   APIC_LAUNCHED();
   hipLaunchKernelGGL(k_stitch, dim3(blocks_for((int64_t)a.T * a.n * a.n, 256)), dim3(256), 0, st,
@@ -293,35 +337,66 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.q = a.coords + d.off_q;
     s.e = a.coords + d.off_e;
     const int64_t pix = (int64_t)a.T * N * N;
-    hipLaunchKernelGGL(k_df_phat, dim3(blocks_for(pix, 256)), dim3(256), 0, st, a, s);
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                       dim3(kFftThreads), 0, st, OpP1<N>{a});
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL((k_cols<c64, N, OpP2<N>>), dim3(col_blocks<c64, N>(a.T)),
-                       dim3(kFftThreads), 0, st, OpP2<N>{a});
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                       dim3(kFftThreads), 0, st, OpP3<N>{a});
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL((k_rows<c64, N, OpImg1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                       dim3(kFftThreads), 0, st, OpImg1<N>{a, s.img});
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL((k_cols<c64, N, OpImg2<N>>), dim3(col_blocks<c64, N>(a.T)),
-                       dim3(kFftThreads), 0, st, OpImg2<N>{a});
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_df_rhs_b, dim3(blocks_for(d.m, 256), a.T), dim3(256), 0, st, a, s);
-    APIC_LAUNCHED();
-    const int nb = (d.nu + kGramBlock - 1) / kGramBlock;
-    hipLaunchKernelGGL(k_df_gram, dim3((unsigned)(a.T * (nb * (nb + 1) / 2))), dim3(256), 0, st,
-                       a, s);
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_df_rhs_v, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st, a, s);
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_df_chol, dim3(a.T), dim3(256), 0, st, a, s);
-    APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_df_scatter, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st, a, s);
-    APIC_LAUNCHED();
+    const double nu = d.nu, T = a.T;
+    {
+      // P_hat (read O_hat 8 B, write 16 B), 3 FP64 passes (32 B each), image
+      // FFT (read 4 B, write 16 B, then 32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 3 * 32.0 + 20.0 + 32.0), st);
+      hipLaunchKernelGGL(k_df_phat, dim3(blocks_for(pix, 256)), dim3(256), 0, st, a, s);
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                         dim3(kFftThreads), 0, st, OpP1<N>{a});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_cols<c64, N, OpP2<N>>), dim3(col_blocks<c64, N>(a.T)),
+                         dim3(kFftThreads), 0, st, OpP2<N>{a});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                         dim3(kFftThreads), 0, st, OpP3<N>{a});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_rows<c64, N, OpImg1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                         dim3(kFftThreads), 0, st, OpImg1<N>{a, s.img});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_cols<c64, N, OpImg2<N>>), dim3(col_blocks<c64, N>(a.T)),
+                         dim3(kFftThreads), 0, st, OpImg2<N>{a});
+      APIC_LAUNCHED();
+    }
+    {
+      ProfScope ps(APIC_PROF_DF_RHS, T * (d.m * 48.0 + 8.0 * d.m * nu), st);
+      hipLaunchKernelGGL(k_df_rhs_b, dim3(blocks_for(d.m, 256), a.T), dim3(256), 0, st, a, s);
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL(k_df_rhs_v, dim3(blocks_for(d.nu, 64), a.T), dim3(256), 0, st, a, s);
+      APIC_LAUNCHED();
+    }
+    {
+      // algorithmic flops of the gram: 8 per complex MAC over the E-sum of the
+      // Hermitian lower triangle
+      ProfScope ps(APIC_PROF_GRAM, T * 8.0 * d.ne * nu * (nu + 1) / 2, st);
+      const int nb = (d.nu + kGramBlock - 1) / kGramBlock;
+      hipLaunchKernelGGL(k_df_gram, dim3((unsigned)(a.T * (nb * (nb + 1) / 2))), dim3(256), 0,
+                         st, a, s);
+      APIC_LAUNCHED();
+    }
+    {
+      // complex Cholesky (4/3) n^3 flops plus the two triangular solves 8 n^2
+      ProfScope ps(APIC_PROF_CHOL, T * (4.0 / 3.0 * nu * nu * nu + 8.0 * nu * nu), st);
+      const int n = d.nu;
+      for (int kb = 0; kb < n; kb += kCB) {
+        const CholArgs ca{n, kb, a.lay.linv};
+        const int bs = std::min(kCB, n - kb);
+        hipLaunchKernelGGL(k_chol_potrf, dim3(a.T), dim3(256), 0, st, a, ca);
+        APIC_LAUNCHED();
+        const int nrb = (n + 1 - (kb + bs) + kCB - 1) / kCB;
+        if (nrb > 0) {
+          hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)(a.T * nrb)), dim3(256), 0, st, a, ca);
+          APIC_LAUNCHED();
+          hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(a.T * (nrb * (nrb + 1) / 2))),
+                             dim3(256), 0, st, a, ca);
+          APIC_LAUNCHED();
+        }
+      }
+      hipLaunchKernelGGL(k_chol_back, dim3(a.T), dim3(64), 0, st, a, s, n);
+      APIC_LAUNCHED();
+    }
   }
   if (skipped) {
     hipLaunchKernelGGL(k_status_or_all, dim3(blocks_for(a.T, 256)), dim3(256), 0, st, a,
@@ -333,6 +408,9 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
 
 template <int N, int NF>
 apic_status run_output_nf(const ClassArgs &a, const c32 *src, float *field, hipStream_t st) {
+  // read N^2 spectrum, write/read N x NF row results, write NF^2 field (complex64)
+  ProfScope ps(APIC_PROF_OUT, (double)a.T * 8.0 * ((double)N * N + 2.0 * N * NF + (double)NF * NF),
+               st);
   hipLaunchKernelGGL((k_rows<c32, NF, OpOut1<NF>>), dim3(row_blocks<c32, NF>(a.T, N)),
                      dim3(kFftThreads), 0, st, OpOut1<NF>{a, src});
   APIC_LAUNCHED();
@@ -483,6 +561,32 @@ using namespace apic;
 extern "C" {
 
 const char *apic_version(void) { return "apic-mi355x 0.1 (gfx950)"; }
+
+apic_status apic_profile(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_clear();
+  g_prof_on = enable != 0;
+  return APIC_OK;
+}
+
+apic_status apic_profile_read(int32_t group, double *total_ms, int64_t *launches,
+                              double *total_work) {
+  if (group < 0 || group >= APIC_PROF_GROUPS || !total_ms || !launches || !total_work)
+    return APIC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms = 0.0, work = 0.0;
+  for (auto &e : g_prof[group]) {
+    APIC_HIP(hipEventSynchronize(e.e1));
+    float t = 0.f;
+    APIC_HIP(hipEventElapsedTime(&t, e.e0, e.e1));
+    ms += t;
+    work += e.work;
+  }
+  *total_ms = ms;
+  *launches = (int64_t)g_prof[group].size();
+  *total_work = work;
+  return APIC_OK;
+}
 
 apic_status apic_plan_create(const apic_geometry *geoms, int32_t n_geom, apic_plan **out) {
   if (!out) return APIC_EINVAL;

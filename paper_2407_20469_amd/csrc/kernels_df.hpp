@@ -9,8 +9,8 @@
 //   G[u,u']  = sum_{k in Q} P_hat(u+k) conj(P_hat(u'+k)) / N^4   (k_df_gram)
 //            = fpp(u - u') / N^2 - sum_{k in E} P_hat(u+k) conj(P_hat(u'+k)) / N^4
 //   v[u]     = sum_{k in Q} P_hat(u+k) b(k) / N^2                (k_df_rhs_v)
-//   x        = (G + lambda tr(G)/N_u I)^-1 v   FP64 Cholesky     (k_df_chol)
-//   O_hat(u) = x(u) exp(-j phi_c(u + k_j)),  u in U              (k_df_scatter)
+//   x        = (G + lambda tr(G)/N_u I)^-1 v   FP64 Cholesky     (chol.hpp)
+//   O_hat(u) = x(u) exp(-j phi_c(u + k_j)),  u in U              (k_chol_back)
 //
 // The gram identity: the sum over every k of P_hat(u+k) conj(P_hat(u'+k)) is
 // the autocorrelation of P_hat at u' - u, which is N^2 fpp(u - u'); Q and E
@@ -199,14 +199,18 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   }
 }
 
-// v[u] = N^-2 sum_{k in Q} P_hat(u + k) b(k)   (C^H b).
+// v[u] = N^-2 sum_{k in Q} P_hat(u + k) b(k)   (C^H b), stored as conj(v) in
+// row n of the gram storage (the Cholesky's right-hand-side row).
+// Workgroup = 64 unknowns x 4 lanes over Q.
 __global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
   const int t = blockIdx.y;
-  const int u = blockIdx.x * 256 + threadIdx.x;
+  const int lu = threadIdx.x & 63, lq = threadIdx.x >> 6;
+  const int u = blockIdx.x * 64 + lu;
   const c64 *phat = a.at<c64>(t, a.lay.phat);
   const c64 *b = a.at<c64>(t, a.lay.bvec);
   __shared__ uint32_t sk[256];
   __shared__ c64 sb[256];
+  __shared__ c64 red[4][64];
   int uy = 0, ux = 0;
   if (u < s.nu) {
     uy = kunpack_y(s.u[u]);
@@ -215,12 +219,12 @@ __global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
   double vx = 0.0, vy = 0.0;
   for (int q0 = 0; q0 < s.m; q0 += 256) {
     const int q = q0 + threadIdx.x;
-    sk[threadIdx.x] = q < s.m ? s.q[q] : 0x7fff7fffu;
+    sk[threadIdx.x] = q < s.m ? s.q[q] : 0u;
     sb[threadIdx.x] = q < s.m ? b[q] : make_double2(0.0, 0.0);
     __syncthreads();
     if (u < s.nu) {
       const int lim = min(256, s.m - q0);
-      for (int k = 0; k < lim; ++k) {
+      for (int k = lq; k < lim; k += 4) {
         const uint32_t kw = sk[k];
         const c64 p = phat_at(phat, a.n, uy + kunpack_y(kw), ux + kunpack_x(kw));
         const c64 bb = sb[k];
@@ -230,205 +234,16 @@ __global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
     }
     __syncthreads();
   }
-  if (u < s.nu) {
+  red[lq][lu] = make_double2(vx, vy);
+  __syncthreads();
+  if (lq == 0 && u < s.nu) {
+    c64 v = red[0][lu];
+    v = cadd(v, red[1][lu]);
+    v = cadd(v, red[2][lu]);
+    v = cadd(v, red[3][lu]);
     const double inv2 = 1.0 / ((double)a.n * a.n);
-    a.at<c64>(t, a.lay.vec)[u] = make_double2(vx * inv2, vy * inv2);
+    a.at<c64>(t, a.lay.gram)[(int64_t)s.nu * a.nu_pad + u] = make_double2(v.x * inv2, -v.y * inv2);
   }
-}
-
-// Batched FP64 Cholesky of G + lambda tr(G)/N_u I (lower, in place, blocked
-// right-looking with 32-wide panels) and the two triangular solves for x.
-// One workgroup per tile matrix.
-constexpr int kCholNB = 32;
-__global__ __launch_bounds__(256) void k_df_chol(ClassArgs a, StepArgs s) {
-  const int t = blockIdx.x;
-  const int n = s.nu, ld = a.nu_pad, tid = threadIdx.x;
-  c64 *G = a.at<c64>(t, a.lay.gram);
-  c64 *vec = a.at<c64>(t, a.lay.vec);
-  __shared__ c64 D[kCholNB][kCholNB + 1];
-  __shared__ c64 Pi[kCholNB][kCholNB + 1];
-  __shared__ c64 Pj[kCholNB][kCholNB + 1];
-  __shared__ double red[256];
-  __shared__ int fail;
-  __shared__ c64 yb[kCholNB];
-  if (tid == 0) fail = 0;
-  // ridge lambda * tr(G) / N_u on the diagonal
-  double tr = 0.0;
-  for (int i = tid; i < n; i += 256) tr += G[(int64_t)i * ld + i].x;
-  red[tid] = tr;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double ridge = a.ridge_df * red[0] / n;
-  for (int i = tid; i < n; i += 256) G[(int64_t)i * ld + i].x += ridge;
-  __syncthreads();
-  const double tiny = fmax(fabs(red[0]) / n, 1e-300) * 1e-14;
-
-  for (int kb = 0; kb < n; kb += kCholNB) {
-    const int bs = min(kCholNB, n - kb);
-    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
-      const int r = e / kCholNB, c = e % kCholNB;
-      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int c = 0; c < bs; ++c) {
-      if (tid == 0) {
-        double d = D[c][c].x;
-        if (!(d > 0.0)) {
-          fail = 1;
-          d = tiny;
-        }
-        D[c][c] = make_double2(sqrt(d), 0.0);
-      }
-      __syncthreads();
-      if (tid > c && tid < bs) {
-        const double inv = 1.0 / D[c][c].x;
-        D[tid][c] = cscale(D[tid][c], inv);
-      }
-      __syncthreads();
-      for (int e = tid; e < bs * bs; e += 256) {
-        const int r = e / bs, cc = e % bs;
-        if (cc > c && r >= cc) D[r][cc] = csub(D[r][cc], cmulc(D[r][c], D[cc][c]));
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
-      const int r = e / kCholNB, c = e % kCholNB;
-      if (r < bs && c <= r) G[(int64_t)(kb + r) * ld + kb + c] = D[r][c];
-    }
-    // panel solve: row i of the panel satisfies x L_kk^H = a
-    for (int i = kb + bs + tid; i < n; i += 256) {
-      c64 x[kCholNB];
-      c64 *row = G + (int64_t)i * ld + kb;
-#pragma unroll
-      for (int c = 0; c < kCholNB; ++c) {
-        if (c < bs) {
-          c64 v = row[c];
-          for (int p = 0; p < c; ++p) v = csub(v, cmulc(x[p], D[c][p]));
-          x[c] = cscale(v, 1.0 / D[c][c].x);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kCholNB; ++c)
-        if (c < bs) row[c] = x[c];
-    }
-    __syncthreads();
-    // trailing update A[I][J] -= L[I, panel] L[J, panel]^H over 32 x 32 tiles
-    const int r0 = kb + bs;
-    const int nt = (n - r0 + kCholNB - 1) / kCholNB;
-    const int ntiles = nt * (nt + 1) / 2;
-    for (int ti = 0; ti < ntiles; ++ti) {
-      int rem = ti, I = 0;
-      while (rem > I) {
-        rem -= I + 1;
-        ++I;
-      }
-      const int J = rem;
-      const int ib = r0 + I * kCholNB, jb = r0 + J * kCholNB;
-      for (int e = tid; e < kCholNB * kCholNB; e += 256) {
-        const int r = e / kCholNB, p = e % kCholNB;
-        Pi[r][p] = (ib + r < n && p < bs) ? G[(int64_t)(ib + r) * ld + kb + p] : make_double2(0.0, 0.0);
-        Pj[r][p] = (jb + r < n && p < bs) ? G[(int64_t)(jb + r) * ld + kb + p] : make_double2(0.0, 0.0);
-      }
-      __syncthreads();
-      const int ty = tid >> 4, tx = tid & 15;
-      c64 acc[2][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = make_double2(0.0, 0.0);
-      for (int p = 0; p < bs; ++p) {
-        const c64 a0 = Pi[ty * 2][p], a1 = Pi[ty * 2 + 1][p];
-        const c64 b0 = Pj[tx * 2][p], b1 = Pj[tx * 2 + 1][p];
-        acc[0][0] = cadd(acc[0][0], cmulc(a0, b0));
-        acc[0][1] = cadd(acc[0][1], cmulc(a0, b1));
-        acc[1][0] = cadd(acc[1][0], cmulc(a1, b0));
-        acc[1][1] = cadd(acc[1][1], cmulc(a1, b1));
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int r = ib + ty * 2 + i, c = jb + tx * 2 + j;
-          if (r < n && c < n && c <= r) {
-            c64 *gp = G + (int64_t)r * ld + c;
-            *gp = csub(*gp, acc[i][j]);
-          }
-        }
-      __syncthreads();
-    }
-  }
-  // forward substitution L y = v (in place in vec)
-  for (int kb = 0; kb < n; kb += kCholNB) {
-    const int bs = min(kCholNB, n - kb);
-    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
-      const int r = e / kCholNB, c = e % kCholNB;
-      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
-    }
-    if (tid < bs) yb[tid] = vec[kb + tid];
-    __syncthreads();
-    for (int c = 0; c < bs; ++c) {
-      if (tid == 0) yb[c] = cscale(yb[c], 1.0 / D[c][c].x);
-      __syncthreads();
-      if (tid > c && tid < bs) yb[tid] = csub(yb[tid], cmul(D[tid][c], yb[c]));
-      __syncthreads();
-    }
-    if (tid < bs) vec[kb + tid] = yb[tid];
-    for (int i = kb + bs + tid; i < n; i += 256) {
-      c64 v = vec[i];
-      const c64 *row = G + (int64_t)i * ld + kb;
-      for (int p = 0; p < bs; ++p) v = csub(v, cmul(row[p], yb[p]));
-      vec[i] = v;
-    }
-    __syncthreads();
-  }
-  // back substitution L^H x = y
-  const int nblk = (n + kCholNB - 1) / kCholNB;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int kb = bi * kCholNB, bs = min(kCholNB, n - kb);
-    for (int e = tid; e < kCholNB * kCholNB; e += 256) {
-      const int r = e / kCholNB, c = e % kCholNB;
-      D[r][c] = (r < bs && c <= r) ? G[(int64_t)(kb + r) * ld + kb + c] : make_double2(0.0, 0.0);
-    }
-    if (tid < bs) yb[tid] = vec[kb + tid];
-    __syncthreads();
-    for (int c = bs - 1; c >= 0; --c) {
-      if (tid == 0) yb[c] = cscale(yb[c], 1.0 / D[c][c].x);
-      __syncthreads();
-      if (tid < c) yb[tid] = csub(yb[tid], cmul(cconj(D[c][tid]), yb[c]));
-      __syncthreads();
-    }
-    if (tid < bs) vec[kb + tid] = yb[tid];
-    for (int i = tid; i < kb; i += 256) {
-      c64 v = vec[i];
-      for (int p = 0; p < bs; ++p) v = csub(v, cmul(cconj(G[(int64_t)(kb + p) * ld + i]), yb[p]));
-      vec[i] = v;
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && fail) status_or(a, t, APIC_TILE_DF_CHOL_FAIL);
-}
-
-// O_hat(u) = x(u) exp(-j phi_c(u + k_j)) on U.
-__global__ __launch_bounds__(256) void k_df_scatter(ClassArgs a, StepArgs s) {
-  const int t = blockIdx.y;
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= s.nu) return;
-  const uint32_t w = s.u[u];
-  const int ky = kunpack_y(w), kx = kunpack_x(w);
-  const float *co = a.at<float>(t, a.lay.coef);
-  float c[12];
-#pragma unroll
-  for (int j = 0; j < 12; ++j) c[j] = co[j];
-  const float ph = pupil_phase12(c, (float)(kx + s.kx), (float)(ky + s.ky), a.inv_r);
-  float sn, cs;
-  sincosf(ph, &sn, &cs);
-  const c64 x = a.at<c64>(t, a.lay.vec)[u];
-  const int pos = fft_pos(ky, a.n) * a.n + fft_pos(kx, a.n);
-  a.at<c32>(t, a.lay.ohat)[pos] =
-      make_float2((float)(x.x * cs + x.y * sn), (float)(x.y * cs - x.x * sn));
 }
 
 // Output pass 1 (rows of the fN grid that carry spectrum, i.e. |ky| < N/2):

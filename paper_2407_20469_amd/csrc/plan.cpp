@@ -191,7 +191,8 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     p.m_max = std::max(p.m_max, st.m);
     p.ne_max = std::max(p.ne_max, st.ne);
   }
-  p.nu_pad = std::max(kGramBlock, (p.nu_max + kGramBlock - 1) / kGramBlock * kGramBlock);
+  // one spare row: the Cholesky carries the right-hand side as row n
+  p.nu_pad = (p.nu_max + 1 + kGramBlock - 1) / kGramBlock * kGramBlock;
 
   // ---- per-tile workspace layout
   TileLayout &L = p.lay;
@@ -213,6 +214,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.bvec = take(std::max<int64_t>(1, p.m_max) * c64);
   L.vec = take(int64_t(p.nu_pad) * c64);
   L.gram = take(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256);
+  L.linv = take(int64_t(kGramBlock) * kGramBlock * c64);
   L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);
   L.sums = take(128 * 8);
   L.coef = take((16 + kMaxImg) * 4);
