@@ -32,6 +32,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per gram launch from the committed counter summary, or None when
+    the gram's sources changed since the counters were taken."""
+    from paper_2407_20469_amd import pmc_summary
+    path = os.path.join(ROOT, "profiles", "gram_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != pmc_summary.gram_source_hash():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(images_host, w):
     """The FP64 oracle on one tile of the same workload, on the host cores."""
     import numpy as np
@@ -118,6 +133,9 @@ def main():
     plain_s = (time.perf_counter() - t0) / P
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
 
+    # executed gram work: live (block pair, E chunk) triples x 16 x 64 x 64 complex MACs
+    steps_tab = plan.query(6).reshape(-1, 4)
+    gram_exec = w.n_tiles * float(steps_tab[:, 3].sum()) * 16 * 64 * 64 * 8.0
     groups = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
                   "work_per_step": v[2] / args.steps} for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
@@ -126,6 +144,10 @@ def main():
         achieved = work / (tot_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+        if dom == "gram":
+            roof["executed_tflops"] = gram_exec / (tot_ms / args.steps * 1e-3) / 1e12
+            if w.n_tiles == 1024:
+                roof["traffic"] = measured_traffic()
     else:
         achieved = work / (tot_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

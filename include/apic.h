@@ -131,7 +131,8 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *          2: darkfield step j's linear region Q    (ky, kx pairs)
  *          3: darkfield step j's excluded set E     (ky, kx pairs)
  *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs
- *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps */
+ *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps
+ *          6: per darkfield step (N_u, |Q|, |E|, live gram block-pair chunks) */
 apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
                             int32_t *out, int64_t cap, int64_t *len);
 
@@ -217,6 +218,15 @@ apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precisi
 apic_status apic_profile(int32_t enable);
 apic_status apic_profile_read(int32_t group, double *total_ms, int64_t *launches,
                               double *total_work);
+
+/* Measurement probes (roofline reporting, not part of the method).
+ * apic_calib_fma64: `blocks` x 256 threads, each `iters` x 128 dependent-free
+ *   FP64 FMAs (8 chains), writing one double per thread to out[blocks * 256];
+ *   flops = blocks * 256 * iters * 256.
+ * apic_calib_copy: copies `bytes` (multiple of 16) from `in` to `out` with a
+ *   grid-stride 16-byte loop; HBM traffic is bytes read + bytes written. */
+apic_status apic_calib_fma64(double *out, int32_t blocks, int32_t iters, void *stream);
+apic_status apic_calib_copy(const void *in, void *out, int64_t bytes, void *stream);
 
 /* Library version string. */
 const char *apic_version(void);

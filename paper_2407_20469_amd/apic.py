@@ -31,7 +31,8 @@ TILE_SKIP_DARKFIELD = 0x1
 EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_workspace_bytes",
            "apic_plan_query", "apic_reconstruct_tiles", "apic_estimate_pupil", "apic_kk_spectra",
            "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
-           "apic_profile", "apic_profile_read", "apic_version"]
+           "apic_profile", "apic_profile_read", "apic_calib_fma64", "apic_calib_copy",
+           "apic_version"]
 
 PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
@@ -86,6 +87,8 @@ def load_library(path=LIB_PATH):
     lib.apic_extend_darkfield.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, sz, P]
     lib.apic_upsample_field.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
     lib.apic_fft2.argtypes = [i32, i32, i32, i32, P, P, P]
+    lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
+    lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
     lib.apic_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double)]

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libapic.so")
 ARCH = os.environ.get("APIC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "plan.cpp"]
-HEADERS = ["common.hpp", "fft.hpp", "zern.hpp", "kernels_bf.hpp", "kernels_df.hpp", "plan.hpp"]
+HEADERS = ["common.hpp", "fft.hpp", "zern.hpp", "kernels_bf.hpp", "kernels_df.hpp", "chol.hpp",
+           "calib.hpp", "plan.hpp"]
 
 
 def hipcc():

@@ -14,6 +14,7 @@
 #include "kernels_bf.hpp"
 #include "kernels_df.hpp"
 #include "chol.hpp"
+#include "calib.hpp"
 #include "plan.hpp"
 
 namespace apic {
@@ -103,7 +104,7 @@ template <class T> apic_status upload_vec(const std::vector<T> &v, void **dst) {
 }
 
 void free_geom(GeomPlan &g) {
-  void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords};
+  void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords, &g.d_masks};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -221,6 +222,7 @@ ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, 
   a.row_k = (const uint32_t *)g.d_row_k;
   a.known_at = (const int16_t *)g.d_known_at;
   a.coords = (const uint32_t *)g.d_coords;
+  a.masks = (const uint64_t *)g.d_masks;
   return a;
 }
 
@@ -336,6 +338,10 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.p = a.coords + d.off_p;
     s.q = a.coords + d.off_q;
     s.e = a.coords + d.off_e;
+    s.gmask = a.masks + d.off_gmask;
+    s.qmask = a.masks + d.off_qmask;
+    s.nwe = d.nwe;
+    s.nwq = d.nwq;
     const int64_t pix = (int64_t)a.T * N * N;
     const double nu = d.nu, T = a.T;
     {
@@ -394,7 +400,7 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
           APIC_LAUNCHED();
         }
       }
-      hipLaunchKernelGGL(k_chol_back, dim3(a.T), dim3(64), 0, st, a, s, n);
+      hipLaunchKernelGGL(k_chol_back, dim3(a.T), dim3(256), 0, st, a, s, n, a.lay.linv);
       APIC_LAUNCHED();
     }
   }
@@ -623,7 +629,8 @@ apic_status apic_plan_upload(apic_plan *plan) {
   for (GeomPlan &g : plan->geoms) {
     apic_status rc;
     if ((rc = upload_vec(g.row_il, &g.d_row_il)) || (rc = upload_vec(g.row_k, &g.d_row_k)) ||
-        (rc = upload_vec(g.known_at, &g.d_known_at)) || (rc = upload_vec(g.coords, &g.d_coords))) {
+        (rc = upload_vec(g.known_at, &g.d_known_at)) || (rc = upload_vec(g.coords, &g.d_coords)) ||
+        (rc = upload_vec(g.masks, &g.d_masks))) {
       for (GeomPlan &h : plan->geoms) free_geom(h);
       return rc;
     }
@@ -671,6 +678,13 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
     }
   } else if (what == 5) {
     v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active};
+  } else if (what == 6) {
+    for (const DfStep &d : g.steps) {
+      v.push_back(d.nu);
+      v.push_back(d.m);
+      v.push_back(d.ne);
+      v.push_back((int32_t)std::min<int64_t>(d.gram_live, INT32_MAX));
+    }
   } else {
     return APIC_EINVAL;
   }
@@ -759,6 +773,23 @@ apic_status apic_upsample_field(const apic_plan *plan, int32_t n_tiles,
   io.field = field_out;
   return run_call(plan, n_tiles, tiles, nullptr, nullptr, workspace, workspace_bytes, stream,
                   S_OUT, io);
+}
+
+apic_status apic_calib_fma64(double *out, int32_t blocks, int32_t iters, void *stream) {
+  if (!out || blocks <= 0 || iters < 0) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_calib_fma64, dim3(blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                     out, iters, 0.999999, 1e-7);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+apic_status apic_calib_copy(const void *in, void *out, int64_t bytes, void *stream) {
+  if (!in || !out || bytes <= 0 || (bytes % 16) != 0) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_calib_copy, dim3(256 * 64), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(in),
+                     reinterpret_cast<float4 *>(out), bytes / 16);
+  APIC_LAUNCHED();
+  return APIC_OK;
 }
 
 apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,

@@ -29,15 +29,20 @@ struct CholArgs {
   int64_t linv_off; // per-tile byte offset of the 64 x 64 inverse block
 };
 
-// Factor the diagonal block [kb, kb+bs) in place (lower), write it back, and
-// write its lower-triangular inverse to the tile's inverse block.
+// Factor the diagonal block [kb, kb+bs) (lower) and write it back; write its
+// lower-triangular inverse to the tile's inverse block kb / 64.  The factor
+// uses the unscaled update D[r][c] -= D[r][q] conj(D[c][q]) / D[q][q] (one
+// barrier per column: column q is only read in step q) and scales the columns
+// by 1/sqrt(pivot) at the end.  The inverse M = L^-1 is built one column per
+// thread by forward substitution, stored transposed in the unused upper
+// triangle of the same LDS block.
 __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
   const int t = blockIdx.x, tid = threadIdx.x;
   const int n = c.n, kb = c.kb, ld = a.nu_pad;
   const int bs = min(kCB, n - kb);
   c64 *G = a.at<c64>(t, a.lay.gram);
   __shared__ c64 D[kCB][kCB + 1];
-  __shared__ c64 tmp[kCB];
+  __shared__ double piv[kCB], mdiag[kCB];
   __shared__ double red[256];
   __shared__ int fail;
   if (tid == 0) fail = 0;
@@ -59,46 +64,55 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     D[r][q] = (r < bs && q <= r) ? G[(int64_t)(kb + r) * ld + kb + q] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  const double tiny = 1e-300;
   for (int q = 0; q < bs; ++q) {
-    if (tid == 0) {
-      double d = D[q][q].x;
-      if (!(d > 0.0)) {
-        fail = 1;
-        d = fmax(fabs(d), tiny);
-      }
-      D[q][q] = make_double2(sqrt(d), 0.0);
-    }
-    __syncthreads();
-    if (tid > q && tid < bs) D[tid][q] = cscale(D[tid][q], 1.0 / D[q][q].x);
-    __syncthreads();
-    for (int e = tid; e < bs * bs; e += 256) {
-      const int r = e / bs, cc = e % bs;
-      if (cc > q && r >= cc) D[r][cc] = csub(D[r][cc], cmulc(D[r][q], D[cc][q]));
+    double d = D[q][q].x;
+    if (!(d > 0.0)) d = 1e-300;  // flagged below
+    const double inv = 1.0 / d;
+    const int m = bs - q - 1;    // trailing block size
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = q + 1 + e / m, cc = q + 1 + e % m;
+      if (cc <= r) D[r][cc] = csub(D[r][cc], cscale(cmulc(D[r][q], D[cc][q]), inv));
     }
     __syncthreads();
   }
+  if (tid < bs) {
+    double d = D[tid][tid].x;
+    if (!(d > 0.0)) {
+      fail = 1;
+      d = 1e-300;
+    }
+    piv[tid] = sqrt(d);
+  }
+  __syncthreads();
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int r = e / kCB, q = e % kCB;
+    if (r < bs && q < r) D[r][q] = cscale(D[r][q], 1.0 / piv[q]);
+  }
+  if (tid < bs) D[tid][tid] = make_double2(piv[tid], 0.0);
+  __syncthreads();
   for (int e = tid; e < kCB * kCB; e += 256) {
     const int r = e / kCB, q = e % kCB;
     if (r < bs && q <= r) G[(int64_t)(kb + r) * ld + kb + q] = D[r][q];
   }
-  // in-place inverse of the lower-triangular block, last column first
-  for (int j = bs - 1; j >= 0; --j) {
-    if (tid < bs) tmp[tid] = D[tid][j];
-    __syncthreads();
-    const double djj = 1.0 / tmp[j].x;
-    if (tid > j && tid < bs) {
-      c64 s = make_double2(0.0, 0.0);
-      for (int p = j + 1; p <= tid; ++p) s = cadd(s, cmul(D[tid][p], tmp[p]));
-      D[tid][j] = cscale(s, -djj);
+  // column q of M = L^-1 by thread q: M[i][q] = -(sum_{p=q}^{i-1} L[i][p] M[p][q]) / L[i][i],
+  // kept at D[q][i] (upper triangle); M[q][q] = 1 / L[q][q].
+  if (tid < bs) {
+    const int q = tid;
+    mdiag[q] = 1.0 / piv[q];
+    for (int i = q + 1; i < bs; ++i) {
+      c64 s = cscale(D[i][q], mdiag[q]);
+      for (int p = q + 1; p < i; ++p) s = cadd(s, cmul(D[i][p], D[q][p]));
+      D[q][i] = cscale(s, -1.0 / piv[i]);
     }
-    if (tid == j) D[j][j] = make_double2(djj, 0.0);
-    __syncthreads();
   }
-  c64 *linv = a.at<c64>(t, c.linv_off);
+  __syncthreads();
+  c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
   for (int e = tid; e < kCB * kCB; e += 256) {
     const int r = e / kCB, q = e % kCB;
-    linv[e] = (r < bs && q <= r) ? D[r][q] : make_double2(0.0, 0.0);
+    c64 v = make_double2(0.0, 0.0);
+    if (r < bs && q < r) v = D[q][r];
+    else if (r < bs && q == r) v = make_double2(mdiag[r], 0.0);
+    linv[e] = v;
   }
   if (tid == 0 && fail) status_or(a, t, APIC_TILE_DF_CHOL_FAIL);
 }
@@ -148,7 +162,7 @@ __global__ __launch_bounds__(256) void k_chol_trsm(ClassArgs a, CholArgs c) {
   const int t = blockIdx.x / nrb, rb = blockIdx.x % nrb;
   const int rbase = r0 + rb * kCB;
   c64 *G = a.at<c64>(t, a.lay.gram);
-  const c64 *linv = a.at<c64>(t, c.linv_off);
+  const c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
   __shared__ c64 sA[kCK][kCB], sB[kCK][kCB];
   c64 acc[4][4];
 #pragma unroll
@@ -222,39 +236,49 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   }
 }
 
-// L^H x = y with y = conj(row n), one wavefront per tile; then
-// O_hat(u) = x(u) exp(-j phi_c(u + k_j)) on U.
-__global__ __launch_bounds__(64) void k_chol_back(ClassArgs a, StepArgs s, int n) {
-  const int t = blockIdx.x, lane = threadIdx.x, ld = a.nu_pad;
+// L^H x = y with y = conj(row n), block by block from the last: four
+// wavefronts form r = y_b - sum_{p beyond the block} conj(L[p][b]) x_p over
+// strided rows, then x_b = M_b^H r with the stored inverse M_b of the block's
+// diagonal factor.  Finally O_hat(u) = x(u) exp(-j phi_c(u + k_j)) on U.
+__global__ __launch_bounds__(256) void k_chol_back(ClassArgs a, StepArgs s, int n,
+                                                   int64_t linv_off) {
+  const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wq = tid >> 6;
+  const int ld = a.nu_pad;
   const c64 *G = a.at<c64>(t, a.lay.gram);
+  const c64 *linv = a.at<c64>(t, linv_off);
   c64 *x = a.at<c64>(t, a.lay.vec);
-  __shared__ c64 acc[64], xs[64];
+  __shared__ c64 part[4][64], rr[64];
   const int nblk = (n + 63) / 64;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int b0 = b * 64, b1 = min(n, b0 + 64);
+    const int b0 = b * 64, b1 = min(n, b0 + 64), bs = b1 - b0;
     const int i = b0 + lane;
     c64 v = make_double2(0.0, 0.0);
-    if (i < b1) {
-      v = cconj(G[(int64_t)n * ld + i]);
-      for (int p = b1; p < n; ++p) v = csub(v, cmul(cconj(G[(int64_t)p * ld + i]), x[p]));
-    }
-    acc[lane] = v;
+    if (i < b1)
+      for (int p = b1 + wq; p < n; p += 4) v = cadd(v, cmul(cconj(G[(int64_t)p * ld + i]), x[p]));
+    part[wq][lane] = v;
     __syncthreads();
-    for (int q = b1 - 1; q >= b0; --q) {
-      if (lane == q - b0) xs[lane] = cscale(acc[lane], 1.0 / G[(int64_t)q * ld + q].x);
-      __syncthreads();
-      if (lane < q - b0) acc[lane] = csub(acc[lane], cmul(cconj(G[(int64_t)q * ld + b0 + lane]),
-                                                          xs[q - b0]));
-      __syncthreads();
+    if (wq == 0) {
+      c64 r = make_double2(0.0, 0.0);
+      if (lane < bs) {
+        r = cconj(G[(int64_t)n * ld + i]);
+        r = csub(r, cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane])));
+      }
+      rr[lane] = r;
     }
-    if (i < b1) x[i] = xs[lane];
+    __syncthreads();
+    if (wq == 0 && lane < bs) {
+      const c64 *m = linv + (int64_t)b * 64 * 64;
+      c64 xv = make_double2(0.0, 0.0);
+      for (int q = lane; q < bs; ++q) xv = cadd(xv, cmul(cconj(m[q * 64 + lane]), rr[q]));
+      x[i] = xv;
+    }
     __syncthreads();
   }
   const float *co = a.at<float>(t, a.lay.coef);
   float cz[12];
 #pragma unroll
   for (int j = 0; j < 12; ++j) cz[j] = co[j];
-  for (int u = lane; u < n; u += 64) {
+  for (int u = tid; u < n; u += 256) {
     const uint32_t w = s.u[u];
     const int ky = kunpack_y(w), kx = kunpack_x(w);
     const float ph = pupil_phase12(cz, (float)(kx + s.kx), (float)(ky + s.ky), a.inv_r);

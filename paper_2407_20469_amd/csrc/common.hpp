@@ -92,6 +92,7 @@ struct ClassArgs {
   const uint32_t *row_il, *row_k; // pupil rows
   const int16_t *known_at;        // N*N
   const uint32_t *coords;         // darkfield coordinate lists
+  const uint64_t *masks;          // darkfield block-sparsity masks
 
   __device__ __forceinline__ char *tile(int t) const { return ws + (int64_t)t * stride; }
   template <class T> __device__ __forceinline__ T *at(int t, int64_t off) const {
@@ -119,6 +120,8 @@ struct StepArgs {
   int kx, ky;
   int nu, np, m, ne;
   const uint32_t *u, *p, *q, *e;
+  const uint64_t *gmask, *qmask;  // block-sparsity masks of E and Q chunks
+  int nwe, nwq;                   // mask words per block of 64 unknowns
 };
 
 __device__ __forceinline__ void status_or(const ClassArgs &a, int t, uint32_t bits) {

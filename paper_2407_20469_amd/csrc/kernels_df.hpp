@@ -114,8 +114,12 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
 
 // Gram of the darkfield system, 64 x 64 lower-triangle blocks (I >= J) of the
 // N_u x N_u Hermitian matrix; 16 x 16 threads, 4 x 4 complex outputs each.
-// Row operands P_hat(u + k) for 16 excluded k at a time are staged in LDS.
-constexpr int kGramKC = 16;
+// Only the chunks of 16 excluded k whose products can be nonzero for both
+// blocks (plan masks) are visited, in ascending order; the operands
+// P_hat(u + k) of the next chunk are gathered into registers while the
+// current chunk is multiplied from LDS.
+constexpr int kGramKC = kEChunk;
+constexpr int kGramMaxChunks = kMaxEChunks;
 __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramBlock - 1) / kGramBlock;
   const int ntri = nb * (nb + 1) / 2;
@@ -130,11 +134,25 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   __shared__ c64 sA[kGramKC][kGramBlock];
   __shared__ c64 sB[kGramKC][kGramBlock];
   __shared__ uint32_t su[2][kGramBlock];
+  __shared__ uint16_t clist[kGramMaxChunks];
+  __shared__ int ncl;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   if (tid < kGramBlock) {
     const int ui = I * kGramBlock + tid, uj = J * kGramBlock + tid;
     su[0][tid] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: far outside the grid
     su[1][tid] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
+  }
+  if (tid == 0) {
+    int c = 0;
+    const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
+    for (int w = 0; w < s.nwe; ++w) {
+      uint64_t bits = mi[w] & mj[w];
+      while (bits && c < kGramMaxChunks) {
+        clist[c++] = (uint16_t)(w * 64 + __builtin_ctzll(bits));
+        bits &= bits - 1;
+      }
+    }
+    ncl = c;
   }
   c64 acc[4][4];
 #pragma unroll
@@ -142,23 +160,36 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
   __syncthreads();
-  for (int kc = 0; kc < s.ne; kc += kGramKC) {
+  constexpr int PER = (kGramKC * kGramBlock) / 256;
+  c64 pa[PER], pb[PER];
+  auto gather = [&](int chunk) {
 #pragma unroll
-    for (int m = 0; m < (kGramKC * kGramBlock) / 256; ++m) {
+    for (int m = 0; m < PER; ++m) {
       const int e = tid + m * 256;
       const int kk = e / kGramBlock, uu = e % kGramBlock;
-      c64 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-      if (kc + kk < s.ne) {
-        const uint32_t kw = s.e[kc + kk];
+      const int k = chunk * kGramKC + kk;
+      pa[m] = make_double2(0.0, 0.0);
+      pb[m] = make_double2(0.0, 0.0);
+      if (k < s.ne) {
+        const uint32_t kw = s.e[k];
         const int ky = kunpack_y(kw), kx = kunpack_x(kw);
         const uint32_t wa = su[0][uu], wb = su[1][uu];
-        if (wa != 0x7fff7fffu) va = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
-        if (wb != 0x7fff7fffu) vb = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
+        if (wa != 0x7fff7fffu) pa[m] = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
+        if (wb != 0x7fff7fffu) pb[m] = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
       }
-      sA[kk][uu] = va;
-      sB[kk][uu] = vb;
+    }
+  };
+  const int n_chunks = ncl;
+  if (n_chunks > 0) gather(clist[0]);
+  for (int ci = 0; ci < n_chunks; ++ci) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = tid + m * 256;
+      sA[e / kGramBlock][e % kGramBlock] = pa[m];
+      sB[e / kGramBlock][e % kGramBlock] = pb[m];
     }
     __syncthreads();
+    if (ci + 1 < n_chunks) gather(clist[ci + 1]);
 #pragma unroll 4
     for (int kk = 0; kk < kGramKC; ++kk) {
       c64 av[4], bv[4];
@@ -217,7 +248,10 @@ __global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
     ux = kunpack_x(s.u[u]);
   }
   double vx = 0.0, vy = 0.0;
-  for (int q0 = 0; q0 < s.m; q0 += 256) {
+  const uint64_t *qm = s.qmask + (int64_t)blockIdx.x * s.nwq;
+  for (int q0 = 0; q0 < s.m; q0 += kQChunk) {
+    const int qc = q0 / kQChunk;
+    if (!((qm[qc >> 6] >> (qc & 63)) & 1u)) continue;  // no u + k in P for this block
     const int q = q0 + threadIdx.x;
     sk[threadIdx.x] = q < s.m ? s.q[q] : 0u;
     sb[threadIdx.x] = q < s.m ? b[q] : make_double2(0.0, 0.0);

@@ -128,6 +128,8 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   std::vector<uint8_t> mpu(size_t(W) * W), mex(size_t(W) * W);
   p.steps.assign(g.n_df, DfStep());
   p.coords.clear();
+  p.masks.clear();
+  p.gram_chunk_pairs = 0;
   p.nu_max = p.np_max = p.m_max = p.ne_max = p.n_active = 0;
   for (int j = 0; j < g.n_df; ++j) {
     DfStep &st = p.steps[j];
@@ -176,10 +178,49 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     if (int64_t(Q.size() + E.size()) != n_pu) return APIC_EUNSUPPORTED;  // would wrap
     st.m = int(Q.size());
     st.ne = int(E.size());
+    if ((st.ne + kEChunk - 1) / kEChunk > kMaxEChunks) return APIC_EUNSUPPORTED;
     st.off_q = int64_t(p.coords.size());
     p.coords.insert(p.coords.end(), Q.begin(), Q.end());
     st.off_e = int64_t(p.coords.size());
     p.coords.insert(p.coords.end(), E.begin(), E.end());
+    // block-sparsity masks: dilate P by each block of unknowns
+    {
+      std::vector<uint8_t> live(size_t(W) * W);
+      const int nub = (st.nu + 63) / 64;
+      const int nec = (st.ne + kEChunk - 1) / kEChunk, nqc = (st.m + kQChunk - 1) / kQChunk;
+      st.nwe = (nec + 63) / 64;
+      st.nwq = (nqc + 63) / 64;
+      st.off_gmask = int64_t(p.masks.size());
+      p.masks.resize(p.masks.size() + size_t(nub) * st.nwe, 0);
+      st.off_qmask = int64_t(p.masks.size());
+      p.masks.resize(p.masks.size() + size_t(nub) * st.nwq, 0);
+      for (int b = 0; b < nub; ++b) {
+        std::fill(live.begin(), live.end(), 0);
+        for (int ui = b * 64; ui < std::min(st.nu, b * 64 + 64); ++ui)
+          for (auto &q : Pc)  // k with u + k in P: k = q - u
+            live[size_t(q.first - Uc[ui].first + n) * W + (q.second - Uc[ui].second + n)] = 1;
+        auto is_live = [&](uint32_t w) {
+          return live[size_t(unpack_ky(w) + n) * W + (unpack_kx(w) + n)] != 0;
+        };
+        for (int e = 0; e < st.ne; ++e)
+          if (is_live(E[e])) {
+            const int c = e / kEChunk;
+            p.masks[st.off_gmask + size_t(b) * st.nwe + c / 64] |= uint64_t(1) << (c % 64);
+          }
+        for (int q = 0; q < st.m; ++q)
+          if (is_live(Q[q])) {
+            const int c = q / kQChunk;
+            p.masks[st.off_qmask + size_t(b) * st.nwq + c / 64] |= uint64_t(1) << (c % 64);
+          }
+      }
+      for (int I = 0; I < nub; ++I)
+        for (int J = 0; J <= I; ++J)
+          for (int w = 0; w < st.nwe; ++w)
+            st.gram_live += __builtin_popcountll(
+                p.masks[st.off_gmask + size_t(I) * st.nwe + w] &
+                p.masks[st.off_gmask + size_t(J) * st.nwe + w]);
+      p.gram_chunk_pairs += st.gram_live;
+    }
     for (auto &u : Uc) {
       const int y = (u.first + n) % n, x = (u.second + n) % n;
       known[y * n + x] = 1;
@@ -214,7 +255,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.bvec = take(std::max<int64_t>(1, p.m_max) * c64);
   L.vec = take(int64_t(p.nu_pad) * c64);
   L.gram = take(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256);
-  L.linv = take(int64_t(kGramBlock) * kGramBlock * c64);
+  L.linv = take(int64_t(p.nu_pad / kGramBlock) * kGramBlock * kGramBlock * c64);
   L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);
   L.sums = take(128 * 8);
   L.coef = take((16 + kMaxImg) * 4);

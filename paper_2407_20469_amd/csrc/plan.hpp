@@ -19,6 +19,9 @@ constexpr int kNumFeat = 32;        // 8 pair-angle bins x 4 radial bands
 constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cells
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram / Cholesky padding granularity
+constexpr int kEChunk = 16;         // E rows per gram k-chunk
+constexpr int kQChunk = 256;        // Q rows per C^H b chunk
+constexpr int kMaxEChunks = 4096;   // gram chunk list capacity (65536 rows of E)
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
 // Signed (ky, kx) packed in one word: low half ky, high half kx (int16 each).
@@ -33,6 +36,12 @@ struct DfStep {
   int32_t kx = 0, ky = 0;
   int32_t nu = 0, np = 0, m = 0, ne = 0;
   int64_t off_u = 0, off_p = 0, off_q = 0, off_e = 0;  // into GeomPlan::coords
+  // Block-sparsity masks (into GeomPlan::masks): for each block of 64
+  // unknowns, one bit per chunk of kEChunk rows of E (gram) / kQChunk rows of
+  // Q (C^H b) that holds a k with u + k in P for some u of the block.
+  int32_t nwe = 0, nwq = 0;          // 64-bit words per block
+  int64_t off_gmask = 0, off_qmask = 0;
+  int64_t gram_live = 0;             // live (I >= J block pair, E chunk) triples
 };
 
 // Per-tile workspace layout (byte offsets from the tile's base).
@@ -56,10 +65,13 @@ struct GeomPlan {
                                      // 32767 never known
   std::vector<DfStep> steps;
   std::vector<uint32_t> coords;      // packed U, P, Q, E lists of all steps
+  std::vector<uint64_t> masks;       // block-sparsity masks of all steps
+  int64_t gram_chunk_pairs = 0;      // live (block pair, E chunk) triples, all steps
   int nu_max = 0, np_max = 0, m_max = 0, ne_max = 0, n_active = 0, nu_pad = 0;
   TileLayout lay;
   // device copies (owned; filled by upload)
-  void *d_row_il = nullptr, *d_row_k = nullptr, *d_known_at = nullptr, *d_coords = nullptr;
+  void *d_row_il = nullptr, *d_row_k = nullptr, *d_known_at = nullptr, *d_coords = nullptr,
+       *d_masks = nullptr;
 };
 
 // Build the host tables of one geometry; returns APIC_OK or an error code.
