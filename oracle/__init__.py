@@ -11,7 +11,7 @@ closed-form solution", arXiv 2407.20469):
   aberration solve ..... Sec. 2.3, Eq. 8-10           (aberration.py)
   correction + stitch .. Sec. 2.3 text after Eq. 10   (stitch.py)
   darkfield extension .. Sec. 2.3, Eq. 11-13          (darkfield.py)
-  upsampled output ..... Sec. 2.3 ("twofold")         (output.py)
+  upsampled output ..... Sec. 2.3, end of brightfield part (output.py)
   surrogate MLP twin ... not in the paper             (mlp.py)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of

@@ -20,8 +20,8 @@ Readings taken:
 * Q removes both the U-U autocorrelation support and the mirrored cross term
   support U - P (Eq. 13 is false on the latter);
 * the known spectrum carries the pupil phase of the darkfield image, and the
-  solved spectrum has it divided out (Sec. 2.3: aberrations "corrected for both
-  NA-matching and darkfield spectra");
+  solved spectrum has it divided out (Sec. 2.3 applies the estimated aberration
+  to the spectra of both image types);
 * the system is solved as Tikhonov least squares through the normal equations,
   ridge lambda * tr(C^H C) / N_u, by FP64 Cholesky.
 """

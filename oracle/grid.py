@@ -1,7 +1,7 @@
 """Discrete frequency-grid conventions of the oracle.
 
 The paper writes its spectra on continuous transverse k (Sec. 2.2, Eq. 1) and
-speaks of "flattened" positions of k on a grid (Sec. 2.3, text after Eq. 10)
+refers to positions of k on a flattened grid (Sec. 2.3, text after Eq. 10)
 without fixing a discretisation.  Reading taken here:
 
 * arrays are N x N, indexed [y][x], x fastest;

@@ -1,5 +1,5 @@
 """Upsampled complex field from the final spectrum (Sec. 2.3: the assembled
-spectrum gives a "twofold enhancement in resolution"; the output is sampled
+spectrum doubles the resolution of the objective; the output is sampled
 finer than the camera so that the wider spectrum fits).
 
 Reading taken: the N x N spectrum is zero-embedded at the same signed indices

@@ -6,7 +6,7 @@ the corrected spectra are assembled into one spectrum of twice the objective's
 bandwidth.  Eq. 7 says that image i carries exp(j[phi(k + k_i) - phi(k_i)]) on
 its support, so correction divides that factor out.
 
-Reading taken: "assembled" / "stitched" is the plain average over the NA-matched
+Reading taken: the corrected spectra are combined by the plain average over the NA-matched
 images that cover each frequency; the known set is where at least one covers.
 """
 
