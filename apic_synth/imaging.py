@@ -54,7 +54,10 @@ def form_images(objects, coeffs, k_list, r, device="cpu", dtype=torch.float64):
     Returns a torch tensor (T, n, N, N) of ``dtype`` on ``device``.
     """
     cdtype = torch.complex128 if dtype == torch.float64 else torch.complex64
-    obj = torch.as_tensor(np.asarray(objects), device=device).to(cdtype)
+    if isinstance(objects, torch.Tensor):
+        obj = objects.to(device=device, dtype=cdtype)
+    else:
+        obj = torch.as_tensor(np.asarray(objects), device=device).to(cdtype)
     c = torch.as_tensor(np.asarray(coeffs, dtype=np.float64), device=device).to(dtype)
     t_count, n, _ = obj.shape
     f = torch.fft.fftfreq(n, device=device, dtype=dtype) * n

@@ -76,6 +76,8 @@ typedef enum {
 #define APIC_TILE_DF_SKIPPED      0x020u /* a darkfield image had no unknowns         */
 #define APIC_TILE_SEEDED          0x040u /* the pupil solve was re-wrapped on a seed  */
 #define APIC_TILE_NONFINITE_OUT   0x080u /* NaN/Inf in the pupil coefficients         */
+#define APIC_TILE_SURROGATE_USED  0x100u /* the surrogate's coefficients were used    */
+#define APIC_TILE_FALLBACK_USED   0x200u /* the closed form replaced the surrogate    */
 
 /* Tile flags (apic_tile_desc.flags). */
 #define APIC_TILE_SKIP_DARKFIELD 0x1  /* stop after the brightfield stitch */
@@ -196,6 +198,105 @@ apic_status apic_upsample_field(const apic_plan *plan, int32_t n_tiles,
  * allowed (in == out allowed).  Precision: 0 = complex64, 1 = complex128. */
 apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,
                       const void *in, void *out, void *stream);
+
+/* ---------------------------------------------------------------- batches
+ * A prepared batch of tiles (tile batcher).  apic_batch_create groups the
+ * tiles by geometry class and copies their descriptors to device memory owned
+ * by the batch (needs the device; call it outside any graph capture), and
+ * creates one default-priority side stream per class.  apic_batch_reconstruct
+ * then enqueues the whole method with no host synchronisation, copy or
+ * allocation: the classes run concurrently on the side streams, forked from
+ * and joined back to `stream` with events, so an uneven batch of mixed tile
+ * sizes and LED counts overlaps its classes.  apic_batch_capture records one
+ * such call on `stream` (not the NULL stream) into a graph owned by the batch;
+ * apic_batch_launch replays it (same buffers; contents may change between
+ * replays).  Outputs and workspace as apic_reconstruct_tiles; the workspace
+ * size is apic_batch_workspace_bytes.  A batch keeps a pointer to its plan:
+ * destroy the batch first. */
+typedef struct apic_batch apic_batch;
+apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
+                              apic_batch **out);
+apic_status apic_batch_destroy(apic_batch *batch);
+apic_status apic_batch_workspace_bytes(const apic_batch *batch, size_t *bytes);
+apic_status apic_batch_reconstruct(apic_batch *batch, const float *images,
+                                   const float *zernike_seed, float *zernike_out, float *field_out,
+                                   uint32_t *tile_status, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+apic_status apic_batch_capture(apic_batch *batch, const float *images, const float *zernike_seed,
+                               float *zernike_out, float *field_out, uint32_t *tile_status,
+                               void *workspace, size_t workspace_bytes, void *stream);
+apic_status apic_batch_launch(apic_batch *batch, void *stream);
+
+/* ---------------------------------------------------------------- surrogate
+ * Learned Zernike surrogate (not part of the paper's method): a perceptron
+ * 34 -> 128 -> 128 -> 12 (ReLU) from (tile x, tile y, the 32 features of
+ * apic_estimate_pupil) to c_4..c_15, bfloat16 operands on the matrix cores with
+ * FP32 accumulation.  Parameters are one FP32 vector of APIC_MLP_PARAMS
+ * values: W1[128][64] (input columns >= 34 unused), b1[128], W2[128][128],
+ * b2[128], W3[16][128] (rows >= 12 unused), b3[16].  Inputs are normalised as
+ * (x - in_mean) / in_std before use. */
+#define APIC_MLP_PARAMS 26896
+#define APIC_MLP_INPUTS 34
+#define APIC_MLP_OUTPUTS 12
+typedef struct {
+  const float *theta;    /* [APIC_MLP_PARAMS] device */
+  const float *in_mean;  /* [34] device */
+  const float *in_std;   /* [34] device */
+} apic_mlp_model;
+
+/* outputs[n][12] = network(inputs[n][34]). */
+apic_status apic_mlp_forward(const apic_mlp_model *model, int32_t n, const float *inputs,
+                             float *outputs, void *stream);
+
+/* `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr) of the
+ * mean-squared error against targets[n][12], in one single-workgroup launch.
+ * order[steps * batch] lists the sample of each slot (-1 = empty slot); t0 is
+ * the number of Adam steps already applied to (theta, adam_m, adam_v).  grad
+ * [APIC_MLP_PARAMS] is scratch; loss_out[steps] receives each step's loss
+ * (or NULL).  All pointers device memory; theta, adam_m, adam_v updated. */
+apic_status apic_mlp_train(float *theta, float *adam_m, float *adam_v, float *grad,
+                           const float *in_mean, const float *in_std, int32_t n,
+                           const float *inputs, const float *targets, const int32_t *order,
+                           int32_t steps, int32_t batch, int32_t t0, float lr, float *loss_out,
+                           void *stream);
+
+/* Gradient of the loss over the samples order[0..batch) into grad, no update. */
+apic_status apic_mlp_grad(const float *theta, float *grad, const float *in_mean,
+                          const float *in_std, int32_t n, const float *inputs,
+                          const float *targets, const int32_t *order, int32_t batch,
+                          float *loss_out, void *stream);
+
+/* Utility for checking the matrix-core operand layout: c[m][n] = a[m][k] b[k][n],
+ * bfloat16 row-major a and b (uint16 bit patterns), FP32 c; m, n, k in
+ * {16, 32, 48, 64}. */
+apic_status apic_bf16_gemm(int32_t m, int32_t n, int32_t k, const uint16_t *a, const uint16_t *b,
+                           float *c, void *stream);
+
+/* apic_estimate_pupil with the surrogate: positions[T][2] (device, batch
+ * order) are the surrogate's tile coordinates.  For each tile the closed-form
+ * solve and the surrogate both run; rho = sqrt(max(0, R(c_sur) - R(c_cf)))
+ * with R the weighted linearised residual of Eq. 10; the closed form is kept
+ * when rho > rho_max, kappa(A) <= kappa_max and R(c_cf) <= resid_max, the
+ * surrogate otherwise (status APIC_TILE_FALLBACK_USED / _SURROGATE_USED).
+ * zernike_cf_out and zernike_sur_out ([T][15], may be NULL) receive both
+ * candidates; zernike_out the chosen one. */
+apic_status apic_estimate_pupil_sur(const apic_plan *plan, int32_t n_tiles,
+                                    const apic_tile_desc *tiles, const float *images,
+                                    const float *positions, const apic_mlp_model *model,
+                                    float rho_max, float kappa_max, float resid_max,
+                                    float *zernike_out, float *zernike_cf_out,
+                                    float *zernike_sur_out,
+                                    float *diag_out, uint32_t *tile_status, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
+/* apic_reconstruct_tiles with the surrogate choosing the pupil as above. */
+apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
+                                       const apic_tile_desc *tiles, const float *images,
+                                       const float *positions, const apic_mlp_model *model,
+                                       float rho_max, float kappa_max, float resid_max,
+                                       float *zernike_out, float *field_out,
+                                       uint32_t *tile_status, void *workspace,
+                                       size_t workspace_bytes, void *stream);
 
 /* Opt-in profiling of kernel groups (for benchmarks).  apic_profile(1) clears
  * and enables recording: every later launch of a group records a HIP event

@@ -18,6 +18,7 @@ APIC_OK, APIC_EINVAL, APIC_EUNSUPPORTED, APIC_EHIP, APIC_ENOMEM, APIC_EPLAN = 0,
 STATUS_NAMES = {0: "APIC_OK", -1: "APIC_EINVAL", -2: "APIC_EUNSUPPORTED", -3: "APIC_EHIP",
                 -4: "APIC_ENOMEM", -5: "APIC_EPLAN"}
 
+TILE_SKIP_DARKFIELD = 0x1  # descriptor flag
 TILE_NONFINITE_INPUT = 0x001
 TILE_LOG_FLOOR = 0x002
 TILE_PUPIL_ILLCOND = 0x004
@@ -26,13 +27,19 @@ TILE_DF_CHOL_FAIL = 0x010
 TILE_DF_SKIPPED = 0x020
 TILE_SEEDED = 0x040
 TILE_NONFINITE_OUT = 0x080
+TILE_SURROGATE_USED = 0x100
+TILE_FALLBACK_USED = 0x200
+MLP_PARAMS, MLP_INPUTS, MLP_OUTPUTS = 26896, 34, 12
 TILE_SKIP_DARKFIELD = 0x1
 
 EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_workspace_bytes",
            "apic_plan_query", "apic_reconstruct_tiles", "apic_estimate_pupil", "apic_kk_spectra",
            "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
            "apic_profile", "apic_profile_read", "apic_calib_fma64", "apic_calib_copy",
-           "apic_version"]
+           "apic_mlp_forward", "apic_mlp_train", "apic_mlp_grad", "apic_bf16_gemm",
+           "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
+           "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
+           "apic_batch_capture", "apic_batch_launch", "apic_version"]
 
 PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
@@ -50,6 +57,11 @@ class Geometry(ctypes.Structure):
                 ("k_bf", ctypes.POINTER(ctypes.c_int32)), ("k_df", ctypes.POINTER(ctypes.c_int32)),
                 ("ridge_pupil", ctypes.c_double), ("ridge_darkfield", ctypes.c_double),
                 ("log_floor_rel", ctypes.c_double)]
+
+
+class MlpModel(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p), ("in_mean", ctypes.c_void_p),
+                ("in_std", ctypes.c_void_p)]
 
 
 class TileDesc(ctypes.Structure):
@@ -87,6 +99,24 @@ def load_library(path=LIB_PATH):
     lib.apic_extend_darkfield.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, sz, P]
     lib.apic_upsample_field.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
     lib.apic_fft2.argtypes = [i32, i32, i32, i32, P, P, P]
+    lib.apic_mlp_forward.argtypes = [ctypes.POINTER(MlpModel), i32, P, P, P]
+    lib.apic_mlp_train.argtypes = [P, P, P, P, P, P, i32, P, P, P, i32, i32, i32, ctypes.c_float,
+                                   P, P]
+    lib.apic_mlp_grad.argtypes = [P, P, P, P, i32, P, P, P, i32, P, P]
+    lib.apic_bf16_gemm.argtypes = [i32, i32, i32, P, P, P, P]
+    f32 = ctypes.c_float
+    lib.apic_estimate_pupil_sur.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P,
+                                            ctypes.POINTER(MlpModel), f32, f32, f32, P, P, P, P, P,
+                                            P, sz, P]
+    lib.apic_reconstruct_tiles_sur.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P,
+                                               ctypes.POINTER(MlpModel), f32, f32, f32, P, P, P, P,
+                                               sz, P]
+    lib.apic_batch_create.argtypes = [P, i32, ctypes.POINTER(TileDesc), ctypes.POINTER(P)]
+    lib.apic_batch_destroy.argtypes = [P]
+    lib.apic_batch_workspace_bytes.argtypes = [P, ctypes.POINTER(sz)]
+    lib.apic_batch_reconstruct.argtypes = [P, P, P, P, P, P, P, sz, P]
+    lib.apic_batch_capture.argtypes = [P, P, P, P, P, P, P, sz, P]
+    lib.apic_batch_launch.argtypes = [P, P]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
@@ -208,6 +238,99 @@ class Workspace:
             self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.buf.data_ptr()
         return ctypes.c_void_p((base + 255) & ~255), nbytes
+
+
+def mixed_descs(plan, geom_ids, flags=None):
+    """Descriptors for tiles of several geometry classes packed back to back in
+    one flat image buffer and one flat field buffer, in the given order.
+    Returns (descs, image elements, field elements)."""
+    geom_ids = np.asarray(geom_ids, dtype=np.int64)
+    arr = (TileDesc * len(geom_ids))()
+    io = fo = 0
+    for t, gi in enumerate(geom_ids):
+        g = plan.geoms[int(gi)]
+        n, nf = g["n"], g["n"] * g.get("upsample", 2)
+        arr[t].geom = int(gi)
+        arr[t].flags = 0 if flags is None else int(flags[t])
+        arr[t].image_offset = io
+        arr[t].field_offset = fo
+        io += (g["n_bf"] + g["n_df"]) * n * n
+        fo += nf * nf
+    return arr, io, fo
+
+
+class Batch:
+    """A prepared batch (apic_batch_*): tile descriptors resident on the device,
+    the geometry classes run concurrently on side streams, and one call can be
+    captured into a graph and replayed.  ``descs`` as for the plain calls;
+    images are a flat float32 buffer and fields a flat complex64 buffer that
+    the descriptors index."""
+
+    def __init__(self, plan, descs):
+        self.plan, self.lib, self.descs = plan, plan.lib, descs
+        self.n_tiles = len(descs)
+        self.handle = ctypes.c_void_p()
+        _check("apic_batch_create", self.lib.apic_batch_create(
+            plan.handle, self.n_tiles, descs, ctypes.byref(self.handle)))
+        b = ctypes.c_size_t()
+        _check("apic_batch_workspace_bytes",
+               self.lib.apic_batch_workspace_bytes(self.handle, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+        self._bound = None
+        need_img = need_fld = 0
+        for d in descs:
+            g = plan.geoms[d.geom]
+            n, nf = g["n"], g["n"] * g.get("upsample", 2)
+            need_img = max(need_img, d.image_offset + (g["n_bf"] + g["n_df"]) * n * n)
+            need_fld = max(need_fld, d.field_offset + nf * nf)
+        self.image_elems, self.field_elems = need_img, need_fld
+
+    def close(self):
+        if self.handle:
+            self.lib.apic_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, images, field, zernike, status, workspace, seed):
+        import torch
+        if images.dtype != torch.float32 or not images.is_contiguous() or \
+                images.numel() < self.image_elems:
+            raise ValueError("images: contiguous float32 with room for every descriptor")
+        if field.dtype != torch.complex64 or not field.is_contiguous() or \
+                field.numel() < self.field_elems:
+            raise ValueError("field: contiguous complex64 with room for every descriptor")
+        if zernike.numel() < 15 * self.n_tiles or status.numel() < self.n_tiles:
+            raise ValueError("zernike (T, 15) and status (T,) buffers too small")
+        if seed is not None and (seed.dtype != torch.float32 or seed.numel() < 15 * self.n_tiles):
+            raise ValueError("seed must be float32 (T, 15)")
+        wp, wb = workspace.get(self.workspace_bytes, images.device)
+        return [_ptr(images), _ptr(seed), _ptr(zernike), _ptr(field), _ptr(status), wp, wb]
+
+    def reconstruct(self, images, field, zernike, status, workspace, seed=None, stream=None):
+        """Enqueue the whole method for the batch on ``stream``; no host sync."""
+        _check("apic_batch_reconstruct", self.lib.apic_batch_reconstruct(
+            self.handle, *self._args(images, field, zernike, status, workspace, seed),
+            _stream(stream)))
+
+    def capture(self, images, field, zernike, status, workspace, stream, seed=None):
+        """Record one reconstruct call on ``stream`` (a non-default torch stream)
+        into the batch's graph; the buffers stay bound to it for launch()."""
+        if stream is None:
+            raise ValueError("capture needs an explicit non-default stream")
+        args = self._args(images, field, zernike, status, workspace, seed)
+        _check("apic_batch_capture", self.lib.apic_batch_capture(self.handle, *args,
+                                                                 _stream(stream)))
+        self._bound = (images, field, zernike, status, workspace, seed)
+
+    def launch(self, stream=None):
+        if self._bound is None:
+            raise RuntimeError("launch before capture")
+        _check("apic_batch_launch", self.lib.apic_batch_launch(self.handle, _stream(stream)))
 
 
 def _batch_args(plan, images, geom=0):
@@ -353,3 +476,128 @@ def fft2(x, inverse=False, stream=None):
     _check("apic_fft2", lib.apic_fft2(x.shape[-1], x.numel() // (x.shape[-1] ** 2), int(inverse),
                                       prec, _ptr(x), _ptr(out), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- surrogate
+class Surrogate:
+    """Device-resident surrogate model: FP32 parameters, input normalisation and
+    Adam state (torch tensors on one device)."""
+
+    def __init__(self, theta, in_mean, in_std, device="cuda"):
+        import torch
+        self.theta = torch.as_tensor(np.asarray(theta, np.float32), device=device).contiguous()
+        self.mean = torch.as_tensor(np.asarray(in_mean, np.float32), device=device).contiguous()
+        self.std = torch.as_tensor(np.asarray(in_std, np.float32), device=device).contiguous()
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.grad = torch.zeros_like(self.theta)
+        self.t = 0
+
+    def model(self):
+        return MlpModel(self.theta.data_ptr(), self.mean.data_ptr(), self.std.data_ptr())
+
+    def forward(self, inputs, stream=None):
+        import torch
+        x = inputs.contiguous().to(torch.float32)
+        out = torch.empty((x.shape[0], MLP_OUTPUTS), dtype=torch.float32, device=x.device)
+        mdl = self.model()
+        _check("apic_mlp_forward", load_library().apic_mlp_forward(
+            ctypes.byref(mdl), x.shape[0], _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def train(self, inputs, targets, order, batch, lr=1e-3, stream=None):
+        """len(order) // batch Adam steps; returns the per-step losses."""
+        import torch
+        x = inputs.contiguous().to(torch.float32)
+        y = targets.contiguous().to(torch.float32)
+        order = torch.as_tensor(order, dtype=torch.int32, device=x.device).contiguous()
+        steps = order.numel() // batch
+        loss = torch.empty(steps, dtype=torch.float32, device=x.device)
+        _check("apic_mlp_train", load_library().apic_mlp_train(
+            _ptr(self.theta), _ptr(self.m), _ptr(self.v), _ptr(self.grad), _ptr(self.mean),
+            _ptr(self.std), x.shape[0], _ptr(x), _ptr(y), _ptr(order), steps, batch, self.t,
+            float(lr), _ptr(loss), _stream(stream)))
+        self.t += steps
+        return loss
+
+    def gradient(self, inputs, targets, order, stream=None):
+        """Loss and gradient over the samples listed in order (no update)."""
+        import torch
+        x = inputs.contiguous().to(torch.float32)
+        y = targets.contiguous().to(torch.float32)
+        order = torch.as_tensor(order, dtype=torch.int32, device=x.device).contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty_like(self.theta)
+        _check("apic_mlp_grad", load_library().apic_mlp_grad(
+            _ptr(self.theta), _ptr(grad), _ptr(self.mean), _ptr(self.std), x.shape[0], _ptr(x),
+            _ptr(y), _ptr(order), order.numel(), _ptr(loss), _stream(stream)))
+        return loss, grad
+
+
+def init_mlp_params(seed=0):
+    """He-style uniform initial parameters (FP32 flat vector); padded input
+    columns of W1 and padded output rows of W3 are zero."""
+    rng = np.random.default_rng(seed)
+    w1 = np.zeros((128, 64))
+    w1[:, :34] = rng.uniform(-1, 1, (128, 34)) * np.sqrt(6.0 / 34)
+    w2 = rng.uniform(-1, 1, (128, 128)) * np.sqrt(6.0 / 128)
+    w3 = np.zeros((16, 128))
+    w3[:12] = rng.uniform(-1, 1, (12, 128)) * np.sqrt(3.0 / 128)
+    parts = [w1, np.zeros(128), w2, np.zeros(128), w3, np.zeros(16)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def bf16_gemm(a_bits, b_bits, stream=None):
+    """c = a b for bfloat16 bit patterns (int16/uint16 tensors), FP32 result."""
+    import torch
+    m, k = a_bits.shape
+    n = b_bits.shape[1]
+    c = torch.empty((m, n), dtype=torch.float32, device=a_bits.device)
+    _check("apic_bf16_gemm", load_library().apic_bf16_gemm(
+        m, n, k, _ptr(a_bits.contiguous()), _ptr(b_bits.contiguous()), _ptr(c), _stream(stream)))
+    return c
+
+
+def estimate_pupil_sur(plan, images, positions, sur, rho_max=0.05, kappa_max=1e6,
+                       resid_max=1.0, workspace=None, stream=None):
+    """Pupil with the surrogate and fallback rule.  Returns (chosen, closed form,
+    surrogate, diag, status), Zernike arrays (T, 15)."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    z, zcf, zsur = (torch.empty((T, 15), dtype=torch.float32, device=dev) for _ in range(3))
+    diag = torch.empty((T, 4), dtype=torch.float32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, 0)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    pos = positions.contiguous().to(torch.float32)
+    mdl = sur.model()
+    _check("apic_estimate_pupil_sur", plan.lib.apic_estimate_pupil_sur(
+        plan.handle, T, descs, _ptr(images), _ptr(pos), ctypes.byref(mdl), float(rho_max),
+        float(kappa_max), float(resid_max), _ptr(z), _ptr(zcf), _ptr(zsur), _ptr(diag),
+        _ptr(status), wp, wb,
+        _stream(stream)))
+    return z, zcf, zsur, diag, status
+
+
+def reconstruct_sur(plan, images, positions, sur, rho_max=0.05, kappa_max=1e6, resid_max=1.0,
+                    workspace=None, stream=None):
+    """Whole method with the surrogate choosing the pupil; (field, zernike, status)."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    nf = n * g.get("upsample", 2)
+    dev = images.device
+    field = torch.empty((T, nf, nf), dtype=torch.complex64, device=dev)
+    zern = torch.empty((T, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, nf * nf)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    pos = positions.contiguous().to(torch.float32)
+    mdl = sur.model()
+    _check("apic_reconstruct_tiles_sur", plan.lib.apic_reconstruct_tiles_sur(
+        plan.handle, T, descs, _ptr(images), _ptr(pos), ctypes.byref(mdl), float(rho_max),
+        float(kappa_max), float(resid_max), _ptr(zern), _ptr(field), _ptr(status), wp, wb,
+        _stream(stream)))
+    return field, zern, status

@@ -15,6 +15,7 @@
 #include "kernels_df.hpp"
 #include "chol.hpp"
 #include "calib.hpp"
+#include "mlp.hpp"
 #include "plan.hpp"
 
 namespace apic {
@@ -75,6 +76,8 @@ struct ProfScope {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ProfScope(int id_, double work_, hipStream_t st_) : id(id_), work(work_), st(st_) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
     (void)hipEventRecord(e0, st);
   }
@@ -174,7 +177,7 @@ apic_status layout_call(const apic_plan *p, int32_t n_tiles, const apic_tile_des
 }
 
 ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, char *ws,
-                    uint32_t *status) {
+                    uint32_t *status, const char *desc_base = nullptr) {
   const GeomPlan &g = p->geoms[r.geom];
   ClassArgs a;
   memset(&a, 0, sizeof(a));
@@ -203,7 +206,7 @@ ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, 
   }
   a.images = images;
   const int64_t T = a.T;
-  char *d = ws + r.desc_at;
+  const char *d = (desc_base ? desc_base : ws) + r.desc_at;
   a.affine = r.affine ? 1 : 0;
   a.img0 = r.img_off[0];
   a.out0 = r.out_off[0];
@@ -434,7 +437,7 @@ apic_status run_output(const ClassArgs &a, const c32 *src, float *field, hipStre
 
 enum Stage : unsigned {
   S_KK = 1, S_PUPIL = 2, S_COEF_IN = 4, S_STITCH = 8, S_SPEC_IN = 16, S_DF = 32, S_SPEC_OUT = 64,
-  S_OUT = 128
+  S_OUT = 128, S_SUR = 256
 };
 
 struct CallIO {
@@ -443,6 +446,8 @@ struct CallIO {
   float *zout = nullptr, *diag = nullptr, *feat = nullptr;
   float *kk_out = nullptr, *spec_out = nullptr, *spec_io = nullptr, *field = nullptr;
   const float *spec_src = nullptr;
+  SurrogateArgs sur{};
+  float *zcf = nullptr, *zsur = nullptr;
 };
 
 template <int N>
@@ -456,6 +461,14 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
   if (st_mask & S_PUPIL) {
     rc = run_pupil(a, io.seed, io.zout, io.diag, io.feat, st);
     if (rc) return rc;
+  }
+  if (st_mask & S_SUR) {
+    hipLaunchKernelGGL(k_surrogate_predict, dim3(blocks_for(a.T, kMlpTile)), dim3(256), 0, st, a,
+                       io.sur);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_surrogate_decide, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, io.sur,
+                       io.zout, io.zcf, io.zsur);
+    APIC_LAUNCHED();
   }
   if (st_mask & S_COEF_IN) {
     hipLaunchKernelGGL(k_coef_load, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, io.zin);
@@ -489,6 +502,17 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
   return APIC_OK;
 }
 
+apic_status run_class(const apic_plan *plan, const ClassRun &r, const ClassArgs &a,
+                      unsigned st_mask, const CallIO &io, hipStream_t st) {
+  switch (a.n) {
+    case 64: return run_class_n<64>(plan, r, a, st_mask, io, st);
+    case 128: return run_class_n<128>(plan, r, a, st_mask, io, st);
+    case 256: return run_class_n<256>(plan, r, a, st_mask, io, st);
+    case 512: return run_class_n<512>(plan, r, a, st_mask, io, st);
+    default: return APIC_EUNSUPPORTED;
+  }
+}
+
 apic_status run_call(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
                      const float *images, uint32_t *status, void *workspace, size_t ws_bytes,
                      void *stream, unsigned st_mask, const CallIO &io) {
@@ -515,13 +539,7 @@ apic_status run_call(const apic_plan *plan, int32_t n_tiles, const apic_tile_des
   if (rc) return rc;
   for (const ClassRun &r : runs) {
     const ClassArgs a = make_args(plan, r, images, ws, status);
-    switch (a.n) {
-      case 64: rc = run_class_n<64>(plan, r, a, st_mask, io, st); break;
-      case 128: rc = run_class_n<128>(plan, r, a, st_mask, io, st); break;
-      case 256: rc = run_class_n<256>(plan, r, a, st_mask, io, st); break;
-      case 512: rc = run_class_n<512>(plan, r, a, st_mask, io, st); break;
-      default: rc = APIC_EUNSUPPORTED;
-    }
+    rc = run_class(plan, r, a, st_mask, io, st);
     if (rc) return rc;
   }
   return APIC_OK;
@@ -561,6 +579,23 @@ apic_status fft2_c(int l, int batch, bool inv, const void *in, void *out, hipStr
 
 }  // namespace
 }  // namespace apic
+
+// A prepared batch: class grouping and descriptor tables resident on the
+// device, side streams and events for running the geometry classes
+// concurrently, and an optional captured graph of one whole reconstruction.
+struct apic_batch {
+  uint32_t magic = 0x42415443u;  // "BATC"
+  apic_plan *plan = nullptr;
+  int32_t n_tiles = 0;
+  std::vector<apic::ClassRun> runs;
+  int64_t ws_bytes = 0;
+  void *d_desc = nullptr;
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 using namespace apic;
 
@@ -789,6 +824,266 @@ apic_status apic_calib_copy(const void *in, void *out, int64_t bytes, void *stre
                      reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(in),
                      reinterpret_cast<float4 *>(out), bytes / 16);
   APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+apic_status apic_mlp_forward(const apic_mlp_model *model, int32_t n, const float *inputs,
+                             float *outputs, void *stream) {
+  if (!model || !model->theta || !model->in_mean || !model->in_std || n < 0) return APIC_EINVAL;
+  if (n == 0) return APIC_OK;
+  if (!inputs || !outputs) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks_for(n, kMlpTile)), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), model->theta, model->in_mean,
+                     model->in_std, n, inputs, outputs);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+static apic_status mlp_train_impl(float *theta, float *m, float *v, float *grad, const float *mean,
+                                  const float *stdv, int32_t n, const float *inputs,
+                                  const float *targets, const int32_t *order, int32_t steps,
+                                  int32_t batch, int32_t t0, float lr, float *loss_out,
+                                  int grad_only, void *stream) {
+  if (!theta || !grad || !mean || !stdv || !inputs || !targets || !order) return APIC_EINVAL;
+  if (!grad_only && (!m || !v)) return APIC_EINVAL;
+  if (n <= 0 || steps <= 0 || batch <= 0 || t0 < 0 || !(lr >= 0.f)) return APIC_EINVAL;
+  MlpTrainArgs a;
+  a.theta = theta;
+  a.m = m;
+  a.v = v;
+  a.grad = grad;
+  a.inputs = inputs;
+  a.targets = targets;
+  a.mean = mean;
+  a.stdv = stdv;
+  a.order = order;
+  a.n = n;
+  a.steps = steps;
+  a.batch = batch;
+  a.t0 = t0;
+  a.lr = lr;
+  a.beta1 = 0.9f;
+  a.beta2 = 0.999f;
+  a.eps = 1e-8f;
+  a.loss_out = loss_out;
+  a.grad_only = grad_only;
+  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), a);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+apic_status apic_mlp_train(float *theta, float *adam_m, float *adam_v, float *grad,
+                           const float *in_mean, const float *in_std, int32_t n,
+                           const float *inputs, const float *targets, const int32_t *order,
+                           int32_t steps, int32_t batch, int32_t t0, float lr, float *loss_out,
+                           void *stream) {
+  return mlp_train_impl(theta, adam_m, adam_v, grad, in_mean, in_std, n, inputs, targets, order,
+                        steps, batch, t0, lr, loss_out, 0, stream);
+}
+
+apic_status apic_mlp_grad(const float *theta, float *grad, const float *in_mean,
+                          const float *in_std, int32_t n, const float *inputs,
+                          const float *targets, const int32_t *order, int32_t batch,
+                          float *loss_out, void *stream) {
+  return mlp_train_impl(const_cast<float *>(theta), nullptr, nullptr, grad, in_mean, in_std, n,
+                        inputs, targets, order, 1, batch, 0, 0.f, loss_out, 1, stream);
+}
+
+apic_status apic_bf16_gemm(int32_t m, int32_t n, int32_t k, const uint16_t *a, const uint16_t *b,
+                           float *c, void *stream) {
+  auto ok = [](int x) { return x >= 16 && x <= 64 && x % 16 == 0; };
+  if (!ok(m) || !ok(n) || !ok(k) || !a || !b || !c) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_bf16_gemm, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), m,
+                     n, k, a, b, c);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+static bool model_ok(const apic_mlp_model *m) {
+  return m && m->theta && m->in_mean && m->in_std;
+}
+
+apic_status apic_estimate_pupil_sur(const apic_plan *plan, int32_t n_tiles,
+                                    const apic_tile_desc *tiles, const float *images,
+                                    const float *positions, const apic_mlp_model *model,
+                                    float rho_max, float kappa_max, float resid_max,
+                                    float *zernike_out, float *zernike_cf_out,
+                                    float *zernike_sur_out,
+                                    float *diag_out, uint32_t *tile_status, void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike_out || !tile_status || !positions || !model_ok(model)))
+    return APIC_EINVAL;
+  CallIO io;
+  io.diag = diag_out;
+  io.zout = zernike_out;  // closed form first, then the surrogate stage's choice
+  io.sur = SurrogateArgs{model ? model->theta : nullptr, model ? model->in_mean : nullptr,
+                         model ? model->in_std : nullptr, positions, rho_max, kappa_max,
+                         resid_max};
+  io.zcf = zernike_cf_out;
+  io.zsur = zernike_sur_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_PUPIL | S_SUR, io);
+}
+
+apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
+                                       const apic_tile_desc *tiles, const float *images,
+                                       const float *positions, const apic_mlp_model *model,
+                                       float rho_max, float kappa_max, float resid_max,
+                                       float *zernike_out, float *field_out,
+                                       uint32_t *tile_status, void *workspace,
+                                       size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !zernike_out || !field_out || !tile_status || !positions ||
+                      !model_ok(model)))
+    return APIC_EINVAL;
+  CallIO io;
+  io.zout = zernike_out;
+  io.field = field_out;
+  io.sur = SurrogateArgs{model ? model->theta : nullptr, model ? model->in_mean : nullptr,
+                         model ? model->in_std : nullptr, positions, rho_max, kappa_max,
+                         resid_max};
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_PUPIL | S_SUR | S_STITCH | S_DF | S_OUT, io);
+}
+
+static bool batch_ok(const apic_batch *b) { return b && b->magic == 0x42415443u && b->plan; }
+
+static void batch_free(apic_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  b->magic = 0;
+  delete b;
+}
+
+apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
+                              apic_batch **out) {
+  if (!out) return APIC_EINVAL;
+  *out = nullptr;
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  apic_batch *b = new (std::nothrow) apic_batch();
+  if (!b) return APIC_ENOMEM;
+  b->plan = plan;
+  b->n_tiles = n_tiles;
+  apic_status rc = layout_call(plan, n_tiles, tiles, b->runs, b->ws_bytes);
+  if (rc == APIC_OK) rc = apic_plan_upload(plan);
+  if (rc == APIC_OK) rc = ensure_twiddles();
+  if (rc != APIC_OK) {
+    batch_free(b);
+    return rc;
+  }
+  // descriptor tables of every class, same offsets as in a workspace
+  int64_t desc_bytes = 256;
+  for (const ClassRun &r : b->runs) desc_bytes = std::max<int64_t>(desc_bytes, r.desc_at + 24 * (int64_t)r.gidx.size());
+  std::vector<char> host(desc_bytes, 0);
+  for (const ClassRun &r : b->runs) {
+    const int64_t T = (int64_t)r.gidx.size();
+    memcpy(host.data() + r.desc_at, r.img_off.data(), 8 * T);
+    memcpy(host.data() + r.desc_at + 8 * T, r.out_off.data(), 8 * T);
+    memcpy(host.data() + r.desc_at + 16 * T, r.gidx.data(), 4 * T);
+    memcpy(host.data() + r.desc_at + 20 * T, r.flags.data(), 4 * T);
+  }
+  bool ok = hipMalloc(&b->d_desc, desc_bytes) == hipSuccess &&
+            hipMemcpy(b->d_desc, host.data(), desc_bytes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (size_t c = 0; ok && c < b->runs.size() && b->runs.size() > 1; ++c) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) b->side.push_back(s);
+    ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->join.push_back(e);
+  }
+  if (!ok) {
+    batch_free(b);
+    return APIC_EHIP;
+  }
+  *out = b;
+  return APIC_OK;
+}
+
+apic_status apic_batch_destroy(apic_batch *batch) {
+  if (!batch) return APIC_OK;
+  if (!batch_ok(batch)) return APIC_EINVAL;
+  batch_free(batch);
+  return APIC_OK;
+}
+
+apic_status apic_batch_workspace_bytes(const apic_batch *batch, size_t *bytes) {
+  if (!batch_ok(batch) || !bytes) return APIC_EINVAL;
+  *bytes = (size_t)batch->ws_bytes;
+  return APIC_OK;
+}
+
+apic_status apic_batch_reconstruct(apic_batch *batch, const float *images,
+                                   const float *zernike_seed, float *zernike_out, float *field_out,
+                                   uint32_t *tile_status, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+  if (!batch_ok(batch)) return APIC_EINVAL;
+  if (batch->n_tiles == 0) return APIC_OK;
+  if (!images || !zernike_out || !field_out || !tile_status) return APIC_EINVAL;
+  if (!workspace || (int64_t)workspace_bytes < batch->ws_bytes) return APIC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return APIC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *ws = reinterpret_cast<char *>(workspace);
+  CallIO io;
+  io.seed = zernike_seed;
+  io.zout = zernike_out;
+  io.field = field_out;
+  const unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(batch->n_tiles, 256)), dim3(256), 0, st,
+                     tile_status, batch->n_tiles, 0u);
+  APIC_LAUNCHED();
+  const char *desc = reinterpret_cast<const char *>(batch->d_desc);
+  if (batch->runs.size() == 1) {
+    const ClassArgs a = make_args(batch->plan, batch->runs[0], images, ws, tile_status, desc);
+    return run_class(batch->plan, batch->runs[0], a, mask, io, st);
+  }
+  APIC_HIP(hipEventRecord(batch->fork, st));
+  for (size_t c = 0; c < batch->runs.size(); ++c) {
+    APIC_HIP(hipStreamWaitEvent(batch->side[c], batch->fork, 0));
+    const ClassArgs a = make_args(batch->plan, batch->runs[c], images, ws, tile_status, desc);
+    const apic_status rc = run_class(batch->plan, batch->runs[c], a, mask, io, batch->side[c]);
+    if (rc) return rc;
+    APIC_HIP(hipEventRecord(batch->join[c], batch->side[c]));
+  }
+  for (size_t c = 0; c < batch->runs.size(); ++c) APIC_HIP(hipStreamWaitEvent(st, batch->join[c], 0));
+  return APIC_OK;
+}
+
+apic_status apic_batch_capture(apic_batch *batch, const float *images, const float *zernike_seed,
+                               float *zernike_out, float *field_out, uint32_t *tile_status,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+  if (!batch_ok(batch) || !stream) return APIC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (batch->exec) {
+    (void)hipGraphExecDestroy(batch->exec);
+    batch->exec = nullptr;
+  }
+  if (batch->graph) {
+    (void)hipGraphDestroy(batch->graph);
+    batch->graph = nullptr;
+  }
+  APIC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const apic_status rc = apic_batch_reconstruct(batch, images, zernike_seed, zernike_out, field_out,
+                                                tile_status, workspace, workspace_bytes, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t end = hipStreamEndCapture(st, &g);
+  if (rc != APIC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (end != hipSuccess || !g) return APIC_EHIP;
+  batch->graph = g;
+  APIC_HIP(hipGraphInstantiate(&batch->exec, g, nullptr, nullptr, 0));
+  return APIC_OK;
+}
+
+apic_status apic_batch_launch(apic_batch *batch, void *stream) {
+  if (!batch_ok(batch) || !batch->exec) return APIC_EINVAL;
+  APIC_HIP(hipGraphLaunch(batch->exec, reinterpret_cast<hipStream_t>(stream)));
   return APIC_OK;
 }
 

@@ -340,6 +340,7 @@ __global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *se
     co[j] = (float)cj;
     if (zout) zout[(int64_t)g * 15 + 3 + j] = (float)cj;
   }
+  co[14] = (float)fmin(kappa, 3.0e38);
   if (zout)
     for (int j = 0; j < 3; ++j) zout[(int64_t)g * 15 + j] = 0.f;
   if (diag) {

@@ -259,6 +259,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);
   L.sums = take(128 * 8);
   L.coef = take((16 + kMaxImg) * 4);
+  L.sur = take(16 * 4);
   L.eps = take(kMaxImg * 4);
   L.stride = o;
   return APIC_OK;
