@@ -16,13 +16,13 @@ shared by the multi-tile workloads uses ``default_rng([2407, 20469])``.
 from .leds import led_ring, led_rings
 from .objects import (gaussian_smooth_periodic, minmax, object_cfg0, object_background,
                       object_blobs)
-from .configs import (OPTICS, Workload, config0, config1, config2_classes, config2_tiles,
+from .configs import (OPTICS, Workload, config0, config1, config2, config2_classes, config2_tiles,
                       field_model_cfg1, pupil_cfg0, small_workload)
 from .imaging import form_images, add_poisson
 
 __all__ = [
     "led_ring", "led_rings", "gaussian_smooth_periodic", "minmax", "object_cfg0",
     "object_background", "object_blobs", "OPTICS", "Workload", "config0", "config1",
-    "config2_classes", "config2_tiles", "field_model_cfg1", "pupil_cfg0", "small_workload",
+    "config2", "config2_classes", "config2_tiles", "field_model_cfg1", "pupil_cfg0", "small_workload",
     "form_images", "add_poisson",
 ]

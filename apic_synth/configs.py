@@ -9,7 +9,7 @@ from typing import Callable, List, Optional
 import numpy as np
 
 from .leds import led_rings
-from .objects import object_cfg0
+from .objects import object_background, object_cfg0
 
 OPTICS = {"dx_um": 0.4, "wavelength_um": 0.52, "na_obj": 0.25}
 
@@ -51,6 +51,9 @@ class Workload:
 
     def object(self, tile):
         rng = np.random.default_rng([self.cfg_id, 0, tile])
+        background = self.extra.get("background")
+        if background is not None and background[tile]:
+            return object_background(rng, self.n)
         return self.obj_fn(rng, self.n)
 
     def geometry_kwargs(self):
@@ -145,3 +148,25 @@ def config2_tiles(n_tiles=4096, seed=2):
     u = (g % side - (side - 1) / 2) / ((side - 1) / 2)
     v = (g // side - (side - 1) / 2) / ((side - 1) / 2)
     return {"n": sizes, "n_bf": nbf, "background": bg, "u": u, "v": v}
+
+
+def config2(n_tiles=4096, photons=1e4, seed=2):
+    """The uneven batch as one Workload per geometry class (in the order of
+    ``config2_classes``), each with the batch-wide indices of its tiles in
+    ``extra["tiles"]`` and its background flags in ``extra["background"]``.
+    True pupils follow the cfg-1 field model at each tile's grid position."""
+    classes = config2_classes()
+    tiles = config2_tiles(n_tiles, seed)
+    c_all, _ = field_model_cfg1(tiles["u"], tiles["v"])
+    out = []
+    for ci, g in enumerate(classes):
+        sel = np.nonzero((tiles["n"] == g["n"]) & (tiles["n_bf"] == g["n_bf"]))[0]
+        if len(sel) == 0:
+            continue
+        out.append(Workload(f"cfg2-{g['n']}-{g['n_bf']}", g["n"], g["k_bf"], g["k_df"],
+                            upsample=2, n_tiles=len(sel), photons=photons, cfg_id=20 + ci,
+                            coeffs=c_all[sel],
+                            positions=np.stack([tiles["u"][sel], tiles["v"][sel]], axis=1),
+                            extra={"tiles": sel, "background": tiles["background"][sel],
+                                   "class": ci}))
+    return out

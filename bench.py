@@ -1,13 +1,21 @@
 """Benchmark of the per-tile APIC reconstruction on one MI355X.
 
-Workload (one step = the whole method over one batch): 1024 tiles of
+Default workload (one step = the whole method over one batch): 1024 tiles of
 256 x 256 on a 32 x 32 field grid, 16 NA-matched images (ring at NA 0.25) and
 32 darkfield images (rings at NA 0.30 and 0.38), Poisson noise at 1e4
 photons, float32 inputs resident in HBM, complex64 output on the 2x grid
-(512 x 512 per tile).  Metric: output Mpx/s of the batched path; the plain
-path (one tile per call, same kernels) is reported beside it.
+(512 x 512 per tile).  Metric: output Mpx/s of the batched path (a prepared
+tile batch, chunk sizes picked by the autotuner); the plain path (one tile
+per call, same kernels) and a graph replay of the batched step are reported
+beside it.
 
-    python bench.py [--steps K] [--warmup W] [--tiles T] [--no-cpu-baseline]
+``--workload cfg2`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
+in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
+background tiles, nine geometry classes run concurrently in chunks that fit
+``--ws-gb`` of workspace.
+
+    python bench.py [--steps K] [--warmup W] [--workload cfg1|cfg2] [--tiles T]
+                    [--no-autotune] [--no-cpu-baseline]
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -70,10 +78,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tiles", type=int, default=1024)
+    ap.add_argument("--workload", choices=["cfg1", "cfg2"], default="cfg1")
+    ap.add_argument("--tiles", type=int, default=None)
+    ap.add_argument("--ws-gb", type=float, default=64.0)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plain-tiles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.tiles is None:
+        args.tiles = 1024 if args.workload == "cfg1" else 4096
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the per-tile reconstruction has no "
               "cross-GPU step in this build (tiles shard across GPUs without communication)",
@@ -87,21 +100,61 @@ def main():
     from paper_2407_20469_amd import apic
 
     dev = torch.device("cuda:0")
-    w = S.config1(n_tiles=args.tiles)
-    log(f"synthesising {w.n_tiles} tiles of {w.n}^2 x {w.n_img} images")
+    if args.workload == "cfg1":
+        ws_list = [S.config1(n_tiles=args.tiles)]
+        order = [np.arange(ws_list[0].n_tiles)]
+    else:
+        ws_list = S.config2(n_tiles=args.tiles or 4096)
+        order = [w.extra["tiles"] for w in ws_list]
+    n_total = sum(w.n_tiles for w in ws_list)
+    # batch order: tile b of the batch is tile `pos` of class `cls`
+    cls_of = np.zeros(n_total, np.int64)
+    pos_of = np.zeros(n_total, np.int64)
+    for ci, idx in enumerate(order):
+        cls_of[idx] = ci
+        pos_of[idx] = np.arange(len(idx))
+    plan = apic.Plan([w.geometry_kwargs() for w in ws_list])
+    plan.upload()
+    descs, n_img_el, n_fld_el = apic.mixed_descs(plan, cls_of)
+    images = torch.empty(n_img_el, dtype=torch.float32, device=dev)
     t0 = time.time()
-    images = synth_batch(w, dev, log=log)
+    for ci, w in enumerate(ws_list):
+        log(f"synthesising class {ci}: {w.n_tiles} tiles of {w.n}^2 x {w.n_img} images")
+        imgs = synth_batch(w, dev, log=log)
+        per = w.n_img * w.n * w.n
+        for p_, b in enumerate(order[ci]):
+            o = descs[int(b)].image_offset
+            images[o:o + per] = imgs[p_].reshape(-1)
+        del imgs
     torch.cuda.synchronize()
     log(f"synth done in {time.time() - t0:.1f} s")
+    mpx_step = sum(w.n_tiles * (w.n * w.upsample) ** 2 for w in ws_list) / 1e6
 
-    plan = apic.Plan(w.geometry_kwargs())
-    plan.upload()
+    field = torch.empty(n_fld_el, dtype=torch.complex64, device=dev)
+    zern = torch.empty((n_total, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((n_total,), dtype=torch.int32, device=dev)
+    batch = apic.Batch(plan, descs)
+    budget = int(args.ws_gb * 2 ** 30)
+    tune = None
+    if not args.no_autotune:
+        full = batch.workspace_bytes
+        cap = min(full, budget)
+        buf = torch.empty(cap + 256, dtype=torch.uint8, device=dev)
+        t0 = time.time()
+        ms_tile = batch.autotune(images, field, zern, status, (buf.data_ptr() + 255) & ~255, cap,
+                                 slack=0.0)
+        del buf
+        tune = [{"geom": c["geom"], "tiles": c["n_tiles"], "chunk": c["chunk"],
+                 "ms_per_tile": float(m)} for c, m in zip(batch.classes(), ms_tile)]
+        log(f"autotune {time.time() - t0:.1f} s: chunks {[c['chunk'] for c in tune]}")
+    elif batch.workspace_bytes > budget:
+        for i, c in enumerate(batch.classes()):
+            batch.set_chunk(i, max(1, budget // (len(ws_list) * c["tile_bytes"])))
     ws = apic.Workspace()
-    nf = w.n * w.upsample
-    mpx_step = w.n_tiles * nf * nf / 1e6
+    log(f"workspace {batch.workspace_bytes / 2 ** 30:.1f} GiB")
 
     for i in range(args.warmup):
-        field, zern, status = apic.reconstruct(plan, images, workspace=ws)
+        batch.reconstruct(images, field, zern, status, ws)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     stream = torch.cuda.current_stream()
@@ -111,7 +164,7 @@ def main():
     torch.cuda.synchronize()
     ev0.record(stream)
     for i in range(args.steps):
-        field, zern, status = apic.reconstruct(plan, images, workspace=ws)
+        batch.reconstruct(images, field, zern, status, ws)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
@@ -121,21 +174,46 @@ def main():
     st = status.cpu().numpy()
     bad = int(((st & (apic.TILE_NONFINITE_INPUT | apic.TILE_NONFINITE_OUT)) != 0).sum())
 
-    # plain path: the same kernels, one tile per call
-    P = min(args.plain_tiles, w.n_tiles)
+    # the same step captured into a graph and replayed
+    gstream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    batch.capture(images, field, zern, status, ws, gstream)
+    with torch.cuda.stream(gstream):
+        batch.launch(gstream)
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(gstream)
+        for i in range(args.steps):
+            batch.launch(gstream)
+        g1.record(gstream)
+    gstream.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    log(f"graph replay: {graph_ms:.1f} ms/step")
+
+    # plain path: the same kernels, one tile per call, first class
+    w0 = ws_list[0]
+    nf0 = w0.n * w0.upsample
+    first = [int(b) for b in order[0][:args.plain_tiles]]
+    P = len(first)
+    per0 = w0.n_img * w0.n * w0.n
+    one = [images[descs[b].image_offset:descs[b].image_offset + per0].view(1, w0.n_img, w0.n, w0.n)
+           for b in first]
     ws1 = apic.Workspace()
-    apic.reconstruct(plan, images[:1], workspace=ws1)
+    plan0 = apic.Plan(w0.geometry_kwargs())
+    apic.reconstruct(plan0, one[0], workspace=ws1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(P):
-        apic.reconstruct(plan, images[t:t + 1], workspace=ws1)
+    for x in one:
+        apic.reconstruct(plan0, x, workspace=ws1)
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / P
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
 
     # executed gram work: live (block pair, E chunk) triples x 16 x 64 x 64 complex MACs
-    steps_tab = plan.query(6).reshape(-1, 4)
-    gram_exec = w.n_tiles * float(steps_tab[:, 3].sum()) * 16 * 64 * 64 * 8.0
+    gram_exec = 0.0
+    for ci, w in enumerate(ws_list):
+        steps_tab = plan.query(6, ci).reshape(-1, 4)
+        gram_exec += w.n_tiles * float(steps_tab[:, 3].sum()) * 16 * 64 * 64 * 8.0
     groups = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
                   "work_per_step": v[2] / args.steps} for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
@@ -146,30 +224,44 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
         if dom == "gram":
             roof["executed_tflops"] = gram_exec / (tot_ms / args.steps * 1e-3) / 1e12
-            if w.n_tiles == 1024:
+            if args.workload == "cfg1" and n_total == 1024:
                 roof["traffic"] = measured_traffic()
     else:
         achieved = work / (tot_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
 
+    if args.workload == "cfg1":
+        w = ws_list[0]
+        config = {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
+                              f"(NA 0.25 / 0.30 / 0.38), Poisson 1e4, 2x complex64 output",
+                  "tiles": w.n_tiles, "n": w.n, "n_bf": w.n_bf, "n_df": w.n_df,
+                  "upsample": w.upsample}
+    else:
+        config = {"workload": f"uneven batch of {n_total} tiles: 128/256/512 px (4:3:1), "
+                              f"8/12/16 NA-matched + 2x darkfield, 40% background, Poisson 1e4, "
+                              f"2x complex64 output",
+                  "tiles": n_total, "classes": [[w.n, w.n_bf, w.n_df, w.n_tiles] for w in ws_list]}
+    config["mode"] = "prepared batch, classes on concurrent streams, autotuned chunks" \
+        if tune else "prepared batch, classes on concurrent streams"
     out = {
         "metric": METRIC, "value": mpx_step / (ms * 1e-3), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
-                               f"(NA 0.25 / 0.30 / 0.38), Poisson 1e4, 2x complex64 output",
-                   "tiles": w.n_tiles, "n": w.n, "n_bf": w.n_bf, "n_df": w.n_df,
-                   "upsample": w.upsample, "mode": "batched (one call per step)"},
-        "plain": {"value": (nf * nf / 1e6) / plain_s, "unit": "Mpx/s", "tiles_timed": P,
-                  "ms_per_tile": plain_s * 1e3},
+        "config": config,
+        "graph": {"value": mpx_step / (graph_ms * 1e-3), "ms_per_step": graph_ms},
+        "plain": {"value": (nf0 * nf0 / 1e6) / plain_s, "unit": "Mpx/s", "tiles_timed": P,
+                  "ms_per_tile": plain_s * 1e3, "class": 0},
+        "autotune": tune,
+        "workspace_gib": batch.workspace_bytes / 2 ** 30,
         "nonfinite_tiles": bad,
         "roofline": roof,
         "kernel_groups": groups,
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on tile 0")
-        out["cpu_baseline"] = cpu_baseline(images[0].cpu().numpy(), w)
+        b0 = int(order[0][0])
+        log(f"cpu baseline: oracle on tile {b0}")
+        out["cpu_baseline"] = cpu_baseline(one[0][0].cpu().numpy(), w0)
     print(json.dumps(out), flush=True)
 
 

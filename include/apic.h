@@ -227,6 +227,31 @@ apic_status apic_batch_capture(apic_batch *batch, const float *images, const flo
                                void *workspace, size_t workspace_bytes, void *stream);
 apic_status apic_batch_launch(apic_batch *batch, void *stream);
 
+/* Classes of a batch, in the order the batch runs them: on entry *n_classes
+ * is the capacity of the (nullable) arrays, on return the class count; per
+ * class its geometry index, tile count, current chunk (tiles per launch
+ * sequence) and workspace bytes per tile. */
+apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int32_t *geom,
+                               int32_t *n_tiles, int32_t *chunk, int64_t *tile_bytes);
+/* Run class `cls` in chunks of `tiles` tiles (<= 0: the whole class at once),
+ * one after another on its stream, reusing one chunk's workspace.  Changes
+ * apic_batch_workspace_bytes and drops a captured graph. */
+apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles);
+/* Autotuner.  For each class, times the method on its first k tiles for
+ * k = 1, 2, 4, ... up to the class size, as long as k tiles' workspace fits
+ * `workspace_bytes` (and stops after a run longer than 2 s), then sets the
+ * class's chunk to the smallest k whose time per tile is within (1 + slack)
+ * of the best; if the classes' chunk blocks together exceed `workspace_bytes`
+ * (they run concurrently), the largest blocks are halved until they fit.
+ * Synchronises the host with `stream` after every run (not
+ * capturable); writes outputs and status of the timed tiles.  `ms_per_tile`
+ * (nullable, one per class) receives the best time.  Changes
+ * apic_batch_workspace_bytes and drops a captured graph. */
+apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *zernike_out,
+                                float *field_out, uint32_t *tile_status, void *workspace,
+                                size_t workspace_bytes, void *stream, double slack,
+                                double *ms_per_tile);
+
 /* ---------------------------------------------------------------- surrogate
  * Learned Zernike surrogate (not part of the paper's method): a perceptron
  * 34 -> 128 -> 128 -> 12 (ReLU) from (tile x, tile y, the 32 features of

@@ -39,7 +39,8 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_mlp_forward", "apic_mlp_train", "apic_mlp_grad", "apic_bf16_gemm",
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
-           "apic_batch_capture", "apic_batch_launch", "apic_version"]
+           "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
+           "apic_batch_autotune", "apic_version"]
 
 PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
@@ -117,6 +118,9 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_reconstruct.argtypes = [P, P, P, P, P, P, P, sz, P]
     lib.apic_batch_capture.argtypes = [P, P, P, P, P, P, P, sz, P]
     lib.apic_batch_launch.argtypes = [P, P]
+    lib.apic_batch_classes.argtypes = [P, ctypes.POINTER(i32), P, P, P, P]
+    lib.apic_batch_set_chunk.argtypes = [P, i32, i32]
+    lib.apic_batch_autotune.argtypes = [P, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
@@ -272,10 +276,7 @@ class Batch:
         self.handle = ctypes.c_void_p()
         _check("apic_batch_create", self.lib.apic_batch_create(
             plan.handle, self.n_tiles, descs, ctypes.byref(self.handle)))
-        b = ctypes.c_size_t()
-        _check("apic_batch_workspace_bytes",
-               self.lib.apic_batch_workspace_bytes(self.handle, ctypes.byref(b)))
-        self.workspace_bytes = b.value
+        self._refresh()
         self._bound = None
         need_img = need_fld = 0
         for d in descs:
@@ -284,6 +285,47 @@ class Batch:
             need_img = max(need_img, d.image_offset + (g["n_bf"] + g["n_df"]) * n * n)
             need_fld = max(need_fld, d.field_offset + nf * nf)
         self.image_elems, self.field_elems = need_img, need_fld
+
+    def _refresh(self):
+        b = ctypes.c_size_t()
+        _check("apic_batch_workspace_bytes",
+               self.lib.apic_batch_workspace_bytes(self.handle, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+
+    def classes(self):
+        """[{geom, n_tiles, chunk, tile_bytes}] in the order the batch runs them."""
+        n = ctypes.c_int32(0)
+        _check("apic_batch_classes", self.lib.apic_batch_classes(self.handle, ctypes.byref(n),
+                                                                 None, None, None, None))
+        cap = n.value
+        g, t, c = (np.zeros(max(cap, 1), np.int32) for _ in range(3))
+        b = np.zeros(max(cap, 1), np.int64)
+        _check("apic_batch_classes", self.lib.apic_batch_classes(
+            self.handle, ctypes.byref(n), g.ctypes.data_as(ctypes.c_void_p),
+            t.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+            b.ctypes.data_as(ctypes.c_void_p)))
+        return [{"geom": int(g[i]), "n_tiles": int(t[i]), "chunk": int(c[i]),
+                 "tile_bytes": int(b[i])} for i in range(cap)]
+
+    def set_chunk(self, cls, tiles):
+        _check("apic_batch_set_chunk", self.lib.apic_batch_set_chunk(self.handle, cls, tiles))
+        self._refresh()
+        self._bound = None
+
+    def autotune(self, images, field, zernike, status, workspace_ptr, workspace_bytes,
+                 slack=0.05, stream=None):
+        """Pick each class's chunk by timing (see apic_batch_autotune); the
+        workspace is a raw 256-B aligned device pointer and its size, the
+        budget the chunks must fit.  Returns the best ms per tile per class."""
+        n = len(self.classes())
+        ms = np.zeros(max(n, 1), np.float64)
+        self._args(images, field, zernike, status, None, None)
+        _check("apic_batch_autotune", self.lib.apic_batch_autotune(
+            self.handle, _ptr(images), _ptr(zernike), _ptr(field), _ptr(status), workspace_ptr,
+            workspace_bytes, _stream(stream), float(slack), ms.ctypes.data_as(ctypes.c_void_p)))
+        self._refresh()
+        self._bound = None
+        return ms[:n]
 
     def close(self):
         if self.handle:
@@ -308,6 +350,8 @@ class Batch:
             raise ValueError("zernike (T, 15) and status (T,) buffers too small")
         if seed is not None and (seed.dtype != torch.float32 or seed.numel() < 15 * self.n_tiles):
             raise ValueError("seed must be float32 (T, 15)")
+        if workspace is None:
+            return None
         wp, wb = workspace.get(self.workspace_bytes, images.device)
         return [_ptr(images), _ptr(seed), _ptr(zernike), _ptr(field), _ptr(status), wp, wb]
 

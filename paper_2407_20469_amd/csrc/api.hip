@@ -513,6 +513,22 @@ apic_status run_class(const apic_plan *plan, const ClassRun &r, const ClassArgs 
   }
 }
 
+// Arguments of tiles [c0, c0 + cn) of a class, sharing the class's workspace
+// block from its start (chunks of one class run in stream order).
+ClassArgs chunk_args(ClassArgs a, int c0, int cn) {
+  if (a.affine) {
+    a.img0 += (int64_t)c0 * a.img_step;
+    a.out0 += (int64_t)c0 * a.out_step;
+    a.g0 += c0 * a.g_step;
+  } else {
+    a.d_img_off += c0;
+    a.d_out_off += c0;
+    a.d_gidx += c0;
+  }
+  a.T = cn;
+  return a;
+}
+
 apic_status run_call(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
                      const float *images, uint32_t *status, void *workspace, size_t ws_bytes,
                      void *stream, unsigned st_mask, const CallIO &io) {
@@ -588,6 +604,8 @@ struct apic_batch {
   apic_plan *plan = nullptr;
   int32_t n_tiles = 0;
   std::vector<apic::ClassRun> runs;
+  std::vector<int32_t> chunk;    // tiles per launch sequence, per class
+  std::vector<int64_t> cls_ws;   // workspace offset of each class's chunk block
   int64_t ws_bytes = 0;
   void *d_desc = nullptr;
   std::vector<hipStream_t> side;
@@ -947,9 +965,44 @@ apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
 
 static bool batch_ok(const apic_batch *b) { return b && b->magic == 0x42415443u && b->plan; }
 
-static void batch_free(apic_batch *b) {
+// Workspace of a batch: one block of chunk x stride bytes per class (classes
+// run concurrently, chunks of a class one after another).
+static void batch_layout(apic_batch *b) {
+  int64_t o = 0;
+  b->cls_ws.assign(b->runs.size(), 0);
+  for (size_t c = 0; c < b->runs.size(); ++c) {
+    b->cls_ws[c] = o;
+    o = align256(o + (int64_t)b->chunk[c] * b->plan->geoms[b->runs[c].geom].lay.stride);
+  }
+  b->ws_bytes = std::max<int64_t>(o, 256);
+}
+
+static void batch_drop_graph(apic_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Enqueue tiles [first, first + count) of class c on stream st, chunk by chunk.
+static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count,
+                                   const float *images, char *ws, uint32_t *status,
+                                   const CallIO &io, hipStream_t st) {
+  const unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT;
+  const ClassRun &r = b->runs[c];
+  ClassArgs a = make_args(b->plan, r, images, ws, status, reinterpret_cast<const char *>(b->d_desc));
+  a.ws = ws + b->cls_ws[c];
+  const int step = std::max(1, b->chunk[c]);
+  for (int c0 = first; c0 < first + count; c0 += step) {
+    const apic_status rc =
+        run_class(b->plan, r, chunk_args(a, c0, std::min(step, first + count - c0)), mask, io, st);
+    if (rc) return rc;
+  }
+  return APIC_OK;
+}
+
+static void batch_free(apic_batch *b) {
+  batch_drop_graph(b);
   for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
@@ -967,7 +1020,10 @@ apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_
   if (!b) return APIC_ENOMEM;
   b->plan = plan;
   b->n_tiles = n_tiles;
-  apic_status rc = layout_call(plan, n_tiles, tiles, b->runs, b->ws_bytes);
+  int64_t plain_bytes = 0;
+  apic_status rc = layout_call(plan, n_tiles, tiles, b->runs, plain_bytes);
+  for (const ClassRun &r : b->runs) b->chunk.push_back((int32_t)r.gidx.size());
+  batch_layout(b);
   if (rc == APIC_OK) rc = apic_plan_upload(plan);
   if (rc == APIC_OK) rc = ensure_twiddles();
   if (rc != APIC_OK) {
@@ -1032,20 +1088,17 @@ apic_status apic_batch_reconstruct(apic_batch *batch, const float *images,
   io.seed = zernike_seed;
   io.zout = zernike_out;
   io.field = field_out;
-  const unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT;
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(batch->n_tiles, 256)), dim3(256), 0, st,
                      tile_status, batch->n_tiles, 0u);
   APIC_LAUNCHED();
-  const char *desc = reinterpret_cast<const char *>(batch->d_desc);
-  if (batch->runs.size() == 1) {
-    const ClassArgs a = make_args(batch->plan, batch->runs[0], images, ws, tile_status, desc);
-    return run_class(batch->plan, batch->runs[0], a, mask, io, st);
-  }
+  if (batch->runs.size() == 1)
+    return batch_run_class(batch, 0, 0, (int)batch->runs[0].gidx.size(), images, ws, tile_status,
+                           io, st);
   APIC_HIP(hipEventRecord(batch->fork, st));
   for (size_t c = 0; c < batch->runs.size(); ++c) {
     APIC_HIP(hipStreamWaitEvent(batch->side[c], batch->fork, 0));
-    const ClassArgs a = make_args(batch->plan, batch->runs[c], images, ws, tile_status, desc);
-    const apic_status rc = run_class(batch->plan, batch->runs[c], a, mask, io, batch->side[c]);
+    const apic_status rc = batch_run_class(batch, c, 0, (int)batch->runs[c].gidx.size(), images,
+                                           ws, tile_status, io, batch->side[c]);
     if (rc) return rc;
     APIC_HIP(hipEventRecord(batch->join[c], batch->side[c]));
   }
@@ -1058,14 +1111,7 @@ apic_status apic_batch_capture(apic_batch *batch, const float *images, const flo
                                void *workspace, size_t workspace_bytes, void *stream) {
   if (!batch_ok(batch) || !stream) return APIC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (batch->exec) {
-    (void)hipGraphExecDestroy(batch->exec);
-    batch->exec = nullptr;
-  }
-  if (batch->graph) {
-    (void)hipGraphDestroy(batch->graph);
-    batch->graph = nullptr;
-  }
+  batch_drop_graph(batch);
   APIC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   const apic_status rc = apic_batch_reconstruct(batch, images, zernike_seed, zernike_out, field_out,
                                                 tile_status, workspace, workspace_bytes, stream);
@@ -1085,6 +1131,131 @@ apic_status apic_batch_launch(apic_batch *batch, void *stream) {
   if (!batch_ok(batch) || !batch->exec) return APIC_EINVAL;
   APIC_HIP(hipGraphLaunch(batch->exec, reinterpret_cast<hipStream_t>(stream)));
   return APIC_OK;
+}
+
+apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int32_t *geom,
+                               int32_t *n_tiles, int32_t *chunk, int64_t *tile_bytes) {
+  if (!batch_ok(batch) || !n_classes) return APIC_EINVAL;
+  const int32_t cap = *n_classes;
+  *n_classes = (int32_t)batch->runs.size();
+  for (int32_t c = 0; c < std::min(cap, *n_classes); ++c) {
+    const ClassRun &r = batch->runs[c];
+    if (geom) geom[c] = r.geom;
+    if (n_tiles) n_tiles[c] = (int32_t)r.gidx.size();
+    if (chunk) chunk[c] = batch->chunk[c];
+    if (tile_bytes) tile_bytes[c] = batch->plan->geoms[r.geom].lay.stride;
+  }
+  return APIC_OK;
+}
+
+apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles) {
+  if (!batch_ok(batch) || cls < 0 || cls >= (int32_t)batch->runs.size()) return APIC_EINVAL;
+  const int32_t T = (int32_t)batch->runs[cls].gidx.size();
+  batch->chunk[cls] = tiles <= 0 ? T : std::min(tiles, T);
+  batch_layout(batch);
+  batch_drop_graph(batch);
+  return APIC_OK;
+}
+
+apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *zernike_out,
+                                float *field_out, uint32_t *tile_status, void *workspace,
+                                size_t workspace_bytes, void *stream, double slack,
+                                double *ms_per_tile) {
+  if (!batch_ok(batch)) return APIC_EINVAL;
+  if (batch->n_tiles == 0) return APIC_OK;
+  if (!images || !zernike_out || !field_out || !tile_status || !workspace) return APIC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return APIC_EINVAL;
+  if (!(slack >= 0.0)) return APIC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  APIC_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) return APIC_EINVAL;
+  char *ws = reinterpret_cast<char *>(workspace);
+  CallIO io;
+  io.zout = zernike_out;
+  io.field = field_out;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  APIC_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return APIC_EHIP;
+  }
+  apic_status rc = APIC_OK;
+  const std::vector<int32_t> saved = batch->chunk;
+  std::vector<int64_t> saved_ws = batch->cls_ws;
+  for (size_t c = 0; c < batch->runs.size() && rc == APIC_OK; ++c) {
+    const int32_t T = (int32_t)batch->runs[c].gidx.size();
+    const int64_t stride = batch->plan->geoms[batch->runs[c].geom].lay.stride;
+    std::vector<int32_t> cand;
+    for (int32_t k = 1; k < T; k *= 2) cand.push_back(k);
+    cand.push_back(T);
+    double best = 1e300;
+    int32_t pick = 0;
+    std::vector<double> per_tile;
+    for (size_t i = 0; i < cand.size() && rc == APIC_OK; ++i) {
+      const int32_t k = cand[i];
+      if ((int64_t)k * stride > (int64_t)workspace_bytes) break;
+      // time tiles [0, k) of the class as one chunk at offset 0 of the workspace
+      batch->chunk[c] = k;
+      batch->cls_ws[c] = 0;
+      float ms = 0.f;
+      for (int rep = 0; rep < (i == 0 ? 2 : 1) && rc == APIC_OK; ++rep) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(batch->n_tiles, 256)), dim3(256), 0, st,
+                           tile_status, batch->n_tiles, 0u);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+          rc = APIC_EHIP;
+          break;
+        }
+        rc = batch_run_class(batch, c, 0, k, images, ws, tile_status, io, st);
+        if (rc == APIC_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                              hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = APIC_EHIP;
+      }
+      per_tile.push_back(ms / k);
+      best = std::min(best, (double)ms / k);
+      if (ms > 2000.f) break;  // longer runs add little to the choice
+    }
+    if (per_tile.empty()) {
+      rc = APIC_EINVAL;  // not even one tile of this class fits the workspace
+      break;
+    }
+    // smallest chunk within (1 + slack) of the best time per tile
+    for (size_t i = 0; i < per_tile.size(); ++i)
+      if (per_tile[i] <= best * (1.0 + slack)) {
+        pick = cand[i];
+        break;
+      }
+    if (ms_per_tile) ms_per_tile[c] = best;
+    batch->chunk[c] = pick;
+    batch->cls_ws = saved_ws;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != APIC_OK) batch->chunk = saved;
+  batch_layout(batch);
+  // the classes run concurrently: halve the largest blocks until they fit together
+  while (rc == APIC_OK && batch->ws_bytes > (int64_t)workspace_bytes) {
+    size_t big = 0;
+    int64_t big_bytes = -1;
+    for (size_t c = 0; c < batch->runs.size(); ++c) {
+      const int64_t b = (int64_t)batch->chunk[c] * batch->plan->geoms[batch->runs[c].geom].lay.stride;
+      if (batch->chunk[c] > 1 && b > big_bytes) {
+        big = c;
+        big_bytes = b;
+      }
+    }
+    if (big_bytes < 0) {
+      rc = APIC_EINVAL;  // one tile per class does not fit
+      batch->chunk = saved;
+      batch_layout(batch);
+      break;
+    }
+    batch->chunk[big] = (batch->chunk[big] + 1) / 2;
+    batch_layout(batch);
+  }
+  batch_drop_graph(batch);
+  return rc;
 }
 
 apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,

@@ -6,8 +6,8 @@
 // conj(L^-1 v) in row n, so the forward substitution costs one extra row of
 // the factorisation.  Right-looking, 64-wide panels; per panel three launches
 // over all tiles of the class:
-//   k_chol_potrf  : factor the 64 x 64 diagonal block in LDS and invert it
-//                   (first panel: also add the ridge to the diagonal);
+//   k_chol_potrf  : factor the 64 x 64 diagonal block in registers and
+//                   invert it in LDS (first panel: also add the ridge);
 //   k_chol_trsm   : panel rows times the inverted block's conjugate transpose
 //                   (64-row blocks, register-tiled like a GEMM);
 //   k_chol_update : trailing lower 64 x 64 tiles minus panel times panel^H.
@@ -30,18 +30,24 @@ struct CholArgs {
 };
 
 // Factor the diagonal block [kb, kb+bs) (lower) and write it back; write its
-// lower-triangular inverse to the tile's inverse block kb / 64.  The factor
-// uses the unscaled update D[r][c] -= D[r][q] conj(D[c][q]) / D[q][q] (one
-// barrier per column: column q is only read in step q) and scales the columns
-// by 1/sqrt(pivot) at the end.  The inverse M = L^-1 is built one column per
-// thread by forward substitution, stored transposed in the unused upper
-// triangle of the same LDS block.
+// lower-triangular inverse to the tile's inverse block kb / 64.
+//
+// Factor: thread (r = tid / 4, s = tid % 4) keeps row r's columns s, s+4, ...
+// in registers.  Step q publishes column q through LDS (double-buffered, one
+// barrier per step) and every owner of a trailing element applies the
+// unscaled update D[r][c] -= D[r][q] conj(D[c][q]) / D[q][q]; the columns are
+// scaled by 1/sqrt(pivot) at the end.  Inverse M = L^-1: four lanes per
+// column q split the sum of M[i][q] = -(sum_{q<=p<i} L[i][p] M[p][q]) / L[i][i]
+// by p mod 4 and combine it with lane shuffles; lane i mod 4 keeps M[i][q]
+// (in the upper triangle of the LDS block, at D[q][i]) since it is the only
+// lane that reads it later.
 __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
   const int t = blockIdx.x, tid = threadIdx.x;
   const int n = c.n, kb = c.kb, ld = a.nu_pad;
   const int bs = min(kCB, n - kb);
   c64 *G = a.at<c64>(t, a.lay.gram);
   __shared__ c64 D[kCB][kCB + 1];
+  __shared__ c64 col[2][kCB];
   __shared__ double piv[kCB], mdiag[kCB];
   __shared__ double red[256];
   __shared__ int fail;
@@ -59,81 +65,123 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     for (int i = tid; i < n; i += 256) G[(int64_t)i * ld + i].x += ridge;
     __syncthreads();
   }
-  for (int e = tid; e < kCB * kCB; e += 256) {
-    const int r = e / kCB, q = e % kCB;
-    D[r][q] = (r < bs && q <= r) ? G[(int64_t)(kb + r) * ld + kb + q] : make_double2(0.0, 0.0);
+  const int r = tid >> 2, s4 = tid & 3;
+  c64 v[kCB / 4];
+  const c64 *grow = G + (int64_t)(kb + min(r, bs - 1)) * ld + kb;
+#pragma unroll
+  for (int j = 0; j < kCB / 4; ++j) {
+    const int cc = s4 + 4 * j;
+    const c64 g = grow[min(cc, bs - 1)];
+    v[j] = (r < bs && cc <= r) ? g : make_double2(0.0, 0.0);
   }
-  __syncthreads();
   for (int q = 0; q < bs; ++q) {
-    double d = D[q][q].x;
-    if (!(d > 0.0)) d = 1e-300;  // flagged below
-    const double inv = 1.0 / d;
-    const int m = bs - q - 1;    // trailing block size
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = q + 1 + e / m, cc = q + 1 + e % m;
-      if (cc <= r) D[r][cc] = csub(D[r][cc], cscale(cmulc(D[r][q], D[cc][q]), inv));
+    c64 *cq = col[q & 1];
+    if ((q & 3) == s4 && r >= q && r < bs) {
+      const int jq = q >> 2;
+      c64 x = v[0];
+#pragma unroll
+      for (int j = 1; j < kCB / 4; ++j)
+        if (j == jq) x = v[j];
+      cq[r] = x;
     }
     __syncthreads();
+    double d = cq[q].x;
+    if (tid == 0) piv[q] = d;
+    if (!(d > 0.0)) d = 1e-300;  // flagged below
+    const double inv = 1.0 / d;
+    if (r > q && r < bs) {
+      const c64 dr = cscale(cq[r], inv);
+#pragma unroll
+      for (int j = 0; j < kCB / 4; ++j) {
+        const int cc = s4 + 4 * j;
+        if (cc > q && cc <= r) v[j] = csub(v[j], cmulc(dr, cq[cc]));
+      }
+    }
   }
+  __syncthreads();
   if (tid < bs) {
-    double d = D[tid][tid].x;
+    double d = piv[tid];
     if (!(d > 0.0)) {
       fail = 1;
       d = 1e-300;
     }
     piv[tid] = sqrt(d);
+    mdiag[tid] = 1.0 / piv[tid];
   }
   __syncthreads();
-  for (int e = tid; e < kCB * kCB; e += 256) {
-    const int r = e / kCB, q = e % kCB;
-    if (r < bs && q < r) D[r][q] = cscale(D[r][q], 1.0 / piv[q]);
+  // scaled factor to LDS (lower triangle) and back to the gram
+  if (r < bs) {
+#pragma unroll
+    for (int j = 0; j < kCB / 4; ++j) {
+      const int cc = s4 + 4 * j;
+      if (cc < r) {
+        const c64 l = cscale(v[j], mdiag[cc]);
+        D[r][cc] = l;
+        G[(int64_t)(kb + r) * ld + kb + cc] = l;
+      } else if (cc == r) {
+        D[r][r] = make_double2(piv[r], 0.0);
+        G[(int64_t)(kb + r) * ld + kb + r] = make_double2(piv[r], 0.0);
+      }
+    }
   }
-  if (tid < bs) D[tid][tid] = make_double2(piv[tid], 0.0);
   __syncthreads();
-  for (int e = tid; e < kCB * kCB; e += 256) {
-    const int r = e / kCB, q = e % kCB;
-    if (r < bs && q <= r) G[(int64_t)(kb + r) * ld + kb + q] = D[r][q];
-  }
-  // column q of M = L^-1 by thread q: M[i][q] = -(sum_{p=q}^{i-1} L[i][p] M[p][q]) / L[i][i],
-  // kept at D[q][i] (upper triangle); M[q][q] = 1 / L[q][q].
-  if (tid < bs) {
-    const int q = tid;
-    mdiag[q] = 1.0 / piv[q];
-    for (int i = q + 1; i < bs; ++i) {
-      c64 s = cscale(D[i][q], mdiag[q]);
-      for (int p = q + 1; p < i; ++p) s = cadd(s, cmul(D[i][p], D[q][p]));
-      D[q][i] = cscale(s, -1.0 / piv[i]);
+  // inverse, column q = tid / 4 split over the four lanes s4 = tid % 4
+  {
+    const int q = r;
+    for (int i = 1; i < bs; ++i) {
+      c64 sum = make_double2(0.0, 0.0);
+      if (q < i) {
+        for (int p = q + ((s4 - q) & 3); p < i; p += 4)
+          sum = cadd(sum, cmul(D[i][p], p == q ? make_double2(mdiag[q], 0.0) : D[q][p]));
+      }
+      sum.x += __shfl_xor(sum.x, 1);
+      sum.y += __shfl_xor(sum.y, 1);
+      sum.x += __shfl_xor(sum.x, 2);
+      sum.y += __shfl_xor(sum.y, 2);
+      if (q < i && (i & 3) == s4) D[q][i] = cscale(sum, -mdiag[i]);
     }
   }
   __syncthreads();
   c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
   for (int e = tid; e < kCB * kCB; e += 256) {
-    const int r = e / kCB, q = e % kCB;
-    c64 v = make_double2(0.0, 0.0);
-    if (r < bs && q < r) v = D[q][r];
-    else if (r < bs && q == r) v = make_double2(mdiag[r], 0.0);
-    linv[e] = v;
+    const int rr = e / kCB, q = e % kCB;
+    c64 val = make_double2(0.0, 0.0);
+    if (rr < bs && q < rr) val = D[q][rr];
+    else if (rr < bs && q == rr) val = make_double2(mdiag[rr], 0.0);
+    linv[e] = val;
   }
   if (tid == 0 && fail) status_or(a, t, APIC_TILE_DF_CHOL_FAIL);
 }
 
 // 64 x 64 register-tiled complex FP64 product over a K range staged in LDS:
 // acc[i][j] += sum_p A(row i, p) conj(B(row j, p)), with the operands given by
-// loader callbacks.  16 x 16 threads, 4 x 4 outputs each.
+// loader callbacks.  16 x 16 threads, 4 x 4 outputs each.  The loaders run
+// along p (16 consecutive elements of a row per 16 lanes, one K chunk ahead
+// in registers); the LDS rows are padded by one element so that the
+// transposing store does not serialise on one bank group.
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm_nc(c64 (&acc)[4][4], int K, LA la, LB lb,
-                                             c64 (&sA)[kCK][kCB], c64 (&sB)[kCK][kCB]) {
+                                             c64 (&sA)[kCK][kCB + 1], c64 (&sB)[kCK][kCB + 1]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int lk = tid & (kCK - 1), lr = tid / kCK;  // loader: element lk of rows lr + 16 m
+  c64 pa[kCB / 16], pb[kCB / 16];
+  auto fetch = [&](int k0) {
+    const bool ok = k0 + lk < K;
+#pragma unroll
+    for (int m = 0; m < kCB / 16; ++m) {
+      pa[m] = ok ? la(lr + 16 * m, k0 + lk) : make_double2(0.0, 0.0);
+      pb[m] = ok ? lb(lr + 16 * m, k0 + lk) : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < K; k0 += kCK) {
 #pragma unroll
-    for (int m = 0; m < (kCK * kCB) / 256; ++m) {
-      const int e = tid + m * 256;
-      const int kk = e / kCB, rr = e % kCB;
-      const bool ok = k0 + kk < K;
-      sA[kk][rr] = ok ? la(rr, k0 + kk) : make_double2(0.0, 0.0);
-      sB[kk][rr] = ok ? lb(rr, k0 + kk) : make_double2(0.0, 0.0);
+    for (int m = 0; m < kCB / 16; ++m) {
+      sA[lk][lr + 16 * m] = pa[m];
+      sB[lk][lr + 16 * m] = pb[m];
     }
     __syncthreads();
+    if (k0 + kCK < K) fetch(k0 + kCK);
 #pragma unroll 4
     for (int kk = 0; kk < kCK; ++kk) {
       c64 av[4], bv[4];
@@ -163,7 +211,7 @@ __global__ __launch_bounds__(256) void k_chol_trsm(ClassArgs a, CholArgs c) {
   const int rbase = r0 + rb * kCB;
   c64 *G = a.at<c64>(t, a.lay.gram);
   const c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
-  __shared__ c64 sA[kCK][kCB], sB[kCK][kCB];
+  __shared__ c64 sA[kCK][kCB + 1], sB[kCK][kCB + 1];
   c64 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -205,7 +253,7 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   const int ib = c0 + I * kCB, jb = c0 + J * kCB;
   if (jb >= n) return;
   c64 *G = a.at<c64>(t, a.lay.gram);
-  __shared__ c64 sA[kCK][kCB], sB[kCK][kCB];
+  __shared__ c64 sA[kCK][kCB + 1], sB[kCK][kCB + 1];
   c64 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)

