@@ -122,7 +122,7 @@ def test_surrogate_gain_on_background_tiles():
     geom = SS.geometry()
     plan = apic.Plan(geom)
     rng = np.random.default_rng(11)
-    n_train, n_eval = 12288, 4096
+    n_train, n_eval = 16384, 4096
     uv_tr = rng.uniform(-1, 1, (n_train, 2))
     bg_tr = rng.uniform(size=n_train) < 0.4
     _log(f"synth {n_train} training tiles")
