@@ -134,7 +134,10 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *          3: darkfield step j's excluded set E     (ky, kx pairs)
  *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs
  *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps
- *          6: per darkfield step (N_u, |Q|, |E|, live gram block-pair chunks) */
+ *          6: per darkfield step (N_u, |Q|, |E|, live gram chunks of all lower
+ *             block pairs, live gram chunks of the diagonal blocks); U and E
+ *             are in the plan's processing order (compact squares), P and Q
+ *             in FFT raster order */
 apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
                             int32_t *out, int64_t cap, int64_t *len);
 

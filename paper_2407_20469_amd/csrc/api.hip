@@ -381,9 +381,13 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       // Hermitian lower triangle
       ProfScope ps(APIC_PROF_GRAM, T * 8.0 * d.ne * nu * (nu + 1) / 2, st);
       const int nb = (d.nu + kGramBlock - 1) / kGramBlock;
-      hipLaunchKernelGGL(k_df_gram, dim3((unsigned)(a.T * (nb * (nb + 1) / 2))), dim3(256), 0,
-                         st, a, s);
+      hipLaunchKernelGGL(k_df_gram<true>, dim3((unsigned)(a.T * nb)), dim3(256), 0, st, a, s);
       APIC_LAUNCHED();
+      if (nb > 1) {
+        hipLaunchKernelGGL(k_df_gram<false>, dim3((unsigned)(a.T * (nb * (nb - 1) / 2))),
+                           dim3(256), 0, st, a, s);
+        APIC_LAUNCHED();
+      }
     }
     {
       // complex Cholesky (4/3) n^3 flops plus the two triangular solves 8 n^2
@@ -737,6 +741,7 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
       v.push_back(d.m);
       v.push_back(d.ne);
       v.push_back((int32_t)std::min<int64_t>(d.gram_live, INT32_MAX));
+      v.push_back((int32_t)std::min<int64_t>(d.gram_live_diag, INT32_MAX));
     }
   } else {
     return APIC_EINVAL;

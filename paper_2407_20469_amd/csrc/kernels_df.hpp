@@ -112,31 +112,52 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
   return phat[fft_pos(ky, n) * n + fft_pos(kx, n)];
 }
 
-// Gram of the darkfield system, 64 x 64 lower-triangle blocks (I >= J) of the
-// N_u x N_u Hermitian matrix; 16 x 16 threads, 4 x 4 complex outputs each.
-// Only the chunks of 16 excluded k whose products can be nonzero for both
-// blocks (plan masks) are visited, in ascending order; the operands
-// P_hat(u + k) of the next chunk are gathered into registers while the
-// current chunk is multiplied from LDS.
+// Gram of the darkfield system in 64 x 64 blocks of the N_u x N_u Hermitian
+// matrix, lower triangle only.  Only the chunks of 16 excluded k whose
+// products can be nonzero for both blocks (plan masks) are visited, in
+// ascending order; the operands P_hat(u + k) of the next chunk are gathered
+// into registers while the current chunk is multiplied from LDS.
+//  * kDiag = false: the blocks below the diagonal (I > J); 16 x 16 threads,
+//    4 x 4 complex outputs each.
+//  * kDiag = true: the diagonal blocks (I = J, one operand).  Only the three
+//    lower 32 x 32 quadrants are formed: waves 0-2 take quadrants (0,0),
+//    (1,0), (1,1) with 8 x 8 lanes of 4 x 4 outputs; wave 3 only gathers.
 constexpr int kGramKC = kEChunk;
 constexpr int kGramMaxChunks = kMaxEChunks;
+template <bool kDiag>
 __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramBlock - 1) / kGramBlock;
-  const int ntri = nb * (nb + 1) / 2;
-  const int t = blockIdx.x / ntri;
-  int rem = blockIdx.x % ntri, I = 0;
-  while (rem > I) {
-    rem -= I + 1;
-    ++I;
+  const int per_tile = kDiag ? nb : nb * (nb - 1) / 2;
+  const int t = blockIdx.x / per_tile;
+  int rem = blockIdx.x % per_tile, I, J;
+  if (kDiag) {
+    I = J = rem;
+  } else {  // strictly lower: I >= 1, J < I
+    I = 1;
+    while (rem >= I) {
+      rem -= I;
+      ++I;
+    }
+    J = rem;
   }
-  const int J = rem;
   const c64 *phat = a.at<c64>(t, a.lay.phat);
   __shared__ c64 sA[kGramKC][kGramBlock];
-  __shared__ c64 sB[kGramKC][kGramBlock];
+  __shared__ c64 sB[kDiag ? 1 : kGramKC][kGramBlock];
   __shared__ uint32_t su[2][kGramBlock];
   __shared__ uint16_t clist[kGramMaxChunks];
   __shared__ int ncl;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // output rows ra + 4 i and columns cb + 4 j of the block
+  int ra, cb;
+  if (kDiag) {
+    const int qr = wv == 0 ? 0 : 1, qc = wv == 2 ? 1 : 0;
+    ra = qr * 32 + (lane >> 3) * 4;
+    cb = qc * 32 + (lane & 7) * 4;
+  } else {
+    ra = (tid >> 4) * 4;
+    cb = (tid & 15) * 4;
+  }
+  const bool active = !kDiag || wv < 3;
   if (tid < kGramBlock) {
     const int ui = I * kGramBlock + tid, uj = J * kGramBlock + tid;
     su[0][tid] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: far outside the grid
@@ -175,7 +196,8 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
         const int ky = kunpack_y(kw), kx = kunpack_x(kw);
         const uint32_t wa = su[0][uu], wb = su[1][uu];
         if (wa != 0x7fff7fffu) pa[m] = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
-        if (wb != 0x7fff7fffu) pb[m] = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
+        if (!kDiag && wb != 0x7fff7fffu)
+          pb[m] = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
       }
     }
   };
@@ -186,42 +208,47 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
     for (int m = 0; m < PER; ++m) {
       const int e = tid + m * 256;
       sA[e / kGramBlock][e % kGramBlock] = pa[m];
-      sB[e / kGramBlock][e % kGramBlock] = pb[m];
+      if (!kDiag) sB[e / kGramBlock][e % kGramBlock] = pb[m];
     }
     __syncthreads();
     if (ci + 1 < n_chunks) gather(clist[ci + 1]);
+    if (active) {
+      const c64 *cols = kDiag ? &sA[0][0] : &sB[0][0];  // one operand on the diagonal
 #pragma unroll 4
-    for (int kk = 0; kk < kGramKC; ++kk) {
-      c64 av[4], bv[4];
+      for (int kk = 0; kk < kGramKC; ++kk) {
+        c64 av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty * 4 + i];
+        for (int i = 0; i < 4; ++i) av[i] = sA[kk][ra + i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx * 4 + j];
+        for (int j = 0; j < 4; ++j) bv[j] = cols[kk * kGramBlock + cb + j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
-          acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
-          acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
-        }
+          for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
+            acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
+            acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
+          }
+      }
     }
     __syncthreads();
   }
+  if (!active) return;
+  // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4
   const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
   const c64 *fpp = a.at<c64>(t, a.lay.fpp);
   c64 *G = a.at<c64>(t, a.lay.gram);
   const int ld = a.nu_pad;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = I * kGramBlock + ty * 4 + i;
+    const int r = I * kGramBlock + ra + i;
     if (r >= s.nu) continue;
-    const uint32_t wr = su[0][ty * 4 + i];
+    const uint32_t wr = su[0][ra + i];
     const int ry = kunpack_y(wr), rx = kunpack_x(wr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = J * kGramBlock + tx * 4 + j;
+      const int c = J * kGramBlock + cb + j;
       if (c >= s.nu) continue;
-      const uint32_t wc = su[1][tx * 4 + j];
+      const uint32_t wc = su[1][cb + j];
       const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
       const c64 tv = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
       G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,

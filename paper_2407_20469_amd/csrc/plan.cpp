@@ -22,6 +22,13 @@ inline int signed_of(int idx, int n) { return idx < n / 2 ? idx : idx - n; }
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
+// Sort key of a signed frequency (ky, kx): the s x s square it falls in
+// (rows of squares, then squares along a row), then raster inside the square.
+int64_t square_key(std::pair<int, int> k, int s) {
+  const int y = k.first + 4096, x = k.second + 4096;  // non-negative
+  return (((int64_t(y / s) * 8192 + x / s) * s + y % s) * s) + x % s;
+}
+
 // Pair-angle bin (8 bins over (0, pi]) of two illumination vectors.
 int angle_bin(int kix, int kiy, int klx, int kly) {
   const double dot = double(kix) * klx + double(kiy) * kly;
@@ -149,6 +156,23 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
           Uc.emplace_back(ky, kx);
         }
       }
+    // unknowns in 8 x 8 squares (raster inside and across squares): a block of
+    // 64 unknowns is spatially compact, so fewer E chunks meet it
+    {
+      std::vector<int> ord(U.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = int(i);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return square_key(Uc[a], 8) < square_key(Uc[b], 8);
+      });
+      std::vector<uint32_t> U2(U.size());
+      std::vector<std::pair<int, int>> Uc2(U.size());
+      for (size_t i = 0; i < ord.size(); ++i) {
+        U2[i] = U[ord[i]];
+        Uc2[i] = Uc[ord[i]];
+      }
+      U.swap(U2);
+      Uc.swap(Uc2);
+    }
     st.nu = int(U.size());
     st.np = int(P.size());
     st.off_u = int64_t(p.coords.size());
@@ -176,6 +200,11 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
         (mex[o] ? E : Q).push_back(pack_k(ky, kx));
       }
     if (int64_t(Q.size() + E.size()) != n_pu) return APIC_EUNSUPPORTED;  // would wrap
+    // excluded k in 4 x 4 squares: a chunk of 16 is spatially compact
+    std::stable_sort(E.begin(), E.end(), [&](uint32_t a, uint32_t b) {
+      return square_key({unpack_ky(a), unpack_kx(a)}, 4) <
+             square_key({unpack_ky(b), unpack_kx(b)}, 4);
+    });
     st.m = int(Q.size());
     st.ne = int(E.size());
     if ((st.ne + kEChunk - 1) / kEChunk > kMaxEChunks) return APIC_EUNSUPPORTED;
@@ -215,10 +244,13 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
       }
       for (int I = 0; I < nub; ++I)
         for (int J = 0; J <= I; ++J)
-          for (int w = 0; w < st.nwe; ++w)
-            st.gram_live += __builtin_popcountll(
+          for (int w = 0; w < st.nwe; ++w) {
+            const int64_t c = __builtin_popcountll(
                 p.masks[st.off_gmask + size_t(I) * st.nwe + w] &
                 p.masks[st.off_gmask + size_t(J) * st.nwe + w]);
+            st.gram_live += c;
+            if (I == J) st.gram_live_diag += c;
+          }
       p.gram_chunk_pairs += st.gram_live;
     }
     for (auto &u : Uc) {

@@ -42,6 +42,7 @@ struct DfStep {
   int32_t nwe = 0, nwq = 0;          // 64-bit words per block
   int64_t off_gmask = 0, off_qmask = 0;
   int64_t gram_live = 0;             // live (I >= J block pair, E chunk) triples
+  int64_t gram_live_diag = 0;        // the I = J part of gram_live
 };
 
 // Per-tile workspace layout (byte offsets from the tile's base).

@@ -55,7 +55,11 @@ def test_plan_sets_equal_oracle_sets(wl):
         for what, key in enumerate(["U", "P", "Q", "E"]):
             got = plan.query(what, 0, j).reshape(-1, 2)
             want = sets[key] if len(sets["U"]) or key in ("U", "P") else np.zeros((0, 2))
-            assert np.array_equal(got, np.asarray(want).reshape(-1, 2)), (j, key)
+            want = np.asarray(want).reshape(-1, 2)
+            # the plan may order U and E for locality: compare as sets, no repeats
+            assert len(got) == len(want), (j, key)
+            assert np.array_equal(got[np.lexsort(got.T[::-1])], want[np.lexsort(want.T[::-1])]), \
+                (j, key)
         known |= sets["U_mask"]
     rows = plan.query(4).reshape(-1, 5)
     want = []
