@@ -90,11 +90,16 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     if (!(d > 0.0)) d = 1e-300;  // flagged below
     const double inv = 1.0 / d;
     if (r > q && r < bs) {
+      // all column values first (one LDS wait), then branch-free updates
+      c64 cv[kCB / 4];
+#pragma unroll
+      for (int j = 0; j < kCB / 4; ++j) cv[j] = cq[s4 + 4 * j];
       const c64 dr = cscale(cq[r], inv);
 #pragma unroll
       for (int j = 0; j < kCB / 4; ++j) {
         const int cc = s4 + 4 * j;
-        if (cc > q && cc <= r) v[j] = csub(v[j], cmulc(dr, cq[cc]));
+        const c64 nv = csub(v[j], cmulc(dr, cv[j]));
+        if (cc > q && cc <= r) v[j] = nv;
       }
     }
   }
@@ -131,8 +136,24 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     for (int i = 1; i < bs; ++i) {
       c64 sum = make_double2(0.0, 0.0);
       if (q < i) {
-        for (int p = q + ((s4 - q) & 3); p < i; p += 4)
-          sum = cadd(sum, cmul(D[i][p], p == q ? make_double2(mdiag[q], 0.0) : D[q][p]));
+        // terms p = q + ((s4 - q) & 3) + 4 m < i, four at a time: loads first
+        const int p0 = q + ((s4 - q) & 3);
+        for (int pb = p0; pb < i; pb += 16) {
+          c64 lv[4], mv[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int p = min(pb + 4 * m, kCB - 1);
+            lv[m] = D[i][p];
+            mv[m] = D[q][p];
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int p = pb + 4 * m;
+            const c64 mm = p == q ? make_double2(mdiag[q], 0.0) : mv[m];
+            const c64 tv = cmul(lv[m], mm);
+            if (p < i) sum = cadd(sum, tv);
+          }
+        }
       }
       sum.x += __shfl_xor(sum.x, 1);
       sum.y += __shfl_xor(sum.y, 1);
