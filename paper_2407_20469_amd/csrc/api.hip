@@ -342,15 +342,14 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.q = a.coords + d.off_q;
     s.e = a.coords + d.off_e;
     s.gmask = a.masks + d.off_gmask;
-    s.qmask = a.masks + d.off_qmask;
     s.nwe = d.nwe;
-    s.nwq = d.nwq;
+    s.qbits = a.masks + d.off_qbits;
     const int64_t pix = (int64_t)a.T * N * N;
     const double nu = d.nu, T = a.T;
     {
-      // P_hat (read O_hat 8 B, write 16 B), 3 FP64 passes (32 B each), image
-      // FFT (read 4 B, write 16 B, then 32 B)
-      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 3 * 32.0 + 20.0 + 32.0), st);
+      // P_hat (read O_hat 8 B, write 16 B), 3 FP64 passes (32 B each, plus
+      // 16 B for P), image FFT (read 4 B, write 16 B, then 32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 3 * 32.0 + 16.0 + 20.0 + 32.0), st);
       hipLaunchKernelGGL(k_df_phat, dim3(blocks_for(pix, 256)), dim3(256), 0, st, a, s);
       APIC_LAUNCHED();
       hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
@@ -370,10 +369,20 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       APIC_LAUNCHED();
     }
     {
-      ProfScope ps(APIC_PROF_DF_RHS, T * (d.m * 48.0 + 8.0 * d.m * nu), st);
-      hipLaunchKernelGGL(k_df_rhs_b, dim3(blocks_for(d.m, 256), a.T), dim3(256), 0, st, a, s);
+      // three FP64 passes: read fimg and fpp, write (48 B); read and read P,
+      // write (48 B); read, write (32 B); then N_u gathers (32 B each)
+      ProfScope ps(APIC_PROF_DF_RHS, (double)pix * 128.0 + T * nu * 32.0, st);
+      hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                         dim3(kFftThreads), 0, st, OpR1<N>{a, s.qbits});
       APIC_LAUNCHED();
-      hipLaunchKernelGGL(k_df_rhs_v, dim3(blocks_for(d.nu, 64), a.T), dim3(256), 0, st, a, s);
+      hipLaunchKernelGGL((k_cols<c64, N, OpR2<N>>), dim3(col_blocks<c64, N>(a.T)),
+                         dim3(kFftThreads), 0, st, OpR2<N>{a});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL((k_rows<c64, N, OpR3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+                         dim3(kFftThreads), 0, st, OpR3<N>{a});
+      APIC_LAUNCHED();
+      hipLaunchKernelGGL(k_df_rhs_gather, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st,
+                         a, s);
       APIC_LAUNCHED();
     }
     {

@@ -120,8 +120,9 @@ struct StepArgs {
   int kx, ky;
   int nu, np, m, ne;
   const uint32_t *u, *p, *q, *e;
-  const uint64_t *gmask, *qmask;  // block-sparsity masks of E and Q chunks
-  int nwe, nwq;                   // mask words per block of 64 unknowns
+  const uint64_t *gmask;          // block-sparsity masks of E chunks
+  int nwe;                        // mask words per block of 64 unknowns
+  const uint64_t *qbits;          // Q membership over the grid (bit y N + x)
 };
 
 __device__ __forceinline__ void status_or(const ClassArgs &a, int t, uint32_t bits) {

@@ -5,16 +5,20 @@
 //   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P              (k_df_phat)
 //   fpp      = fft2(|ifft2 P_hat|^2)        FP64 passes          (OpP*)
 //   fimg     = fft2(I_j)                    FP64 passes          (OpImg*)
-//   b(k)     = conj(fimg(k) - fpp(k)),  k in Q                   (k_df_rhs_b)
+//   b(k)     = conj(fimg(k) - fpp(k)),  k in Q                   (OpR1)
 //   G[u,u']  = sum_{k in Q} P_hat(u+k) conj(P_hat(u'+k)) / N^4   (k_df_gram)
 //            = fpp(u - u') / N^2 - sum_{k in E} P_hat(u+k) conj(P_hat(u'+k)) / N^4
-//   v[u]     = sum_{k in Q} P_hat(u+k) b(k) / N^2                (k_df_rhs_v)
+//   v[u]     = sum_{k in Q} P_hat(u+k) b(k) / N^2                (OpR*, k_df_rhs_gather)
+//            = fft2(p . fft2(b))(u) / N^2,  p = ifft2(P_hat) (normalised)
 //   x        = (G + lambda tr(G)/N_u I)^-1 v   FP64 Cholesky     (chol.hpp)
 //   O_hat(u) = x(u) exp(-j phi_c(u + k_j)),  u in U              (k_chol_back)
 //
 // The gram identity: the sum over every k of P_hat(u+k) conj(P_hat(u'+k)) is
 // the autocorrelation of P_hat at u' - u, which is N^2 fpp(u - u'); Q and E
 // partition P - U, so the Q-sum is that minus the (smaller) E-sum.
+// The right-hand side: with P_hat = fft2(p), sum_k b(k) P_hat(u + k) =
+// sum_x p(x) fft2(b)(x) exp(-2 pi i u.x / N), a forward transform of
+// p . fft2(b); the circular sums equal the linear ones because 4r < N (plan).
 #pragma once
 
 #include "fft.hpp"
@@ -54,13 +58,15 @@ template <int N> struct OpP1 {
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
 };
-// Pass 2 (columns): column IFFT gives N^2 P; |P|^2 = |.|^2 / N^4; column FFT.
+// Pass 2 (columns): column IFFT gives N^2 P; keep P (normalised) for the
+// right-hand side; |P|^2 = |.|^2 / N^4; column FFT.
 template <int N> struct OpP2 {
   static constexpr bool INV1 = true, TWO = true, INV2 = false;
   ClassArgs a;
   __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
-  __device__ void mid(int, int, int, c64 &v) const {
-    constexpr double inv4 = 1.0 / ((double)N * N * (double)N * N);
+  __device__ void mid(int t, int y, int x, c64 &v) const {
+    constexpr double inv2 = 1.0 / ((double)N * N), inv4 = inv2 * inv2;
+    a.at<c64>(t, a.lay.ptil)[y * N + x] = make_double2(v.x * inv2, v.y * inv2);
     v = make_double2((v.x * v.x + v.y * v.y) * inv4, 0.0);
   }
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
@@ -96,15 +102,52 @@ template <int N> struct OpImg2 {
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fimg)[y * N + x] = v; }
 };
 
-// b(k) = conj(fft2(I_j)(k) - fft2(|P|^2)(k)) on Q (Eq. 13, conjugated).
-__global__ __launch_bounds__(256) void k_df_rhs_b(ClassArgs a, StepArgs s) {
+// Right-hand side pass 1 (rows): b(k) = conj(fft2(I_j)(k) - fft2(|P|^2)(k))
+// on Q (Eq. 13, conjugated), zero elsewhere; row FFT.
+template <int N> struct OpR1 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  const uint64_t *qbits;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c64 load(int t, int y, int x) const {
+    const int pix = y * N + x;
+    if (!((qbits[pix >> 6] >> (pix & 63)) & 1u)) return make_double2(0.0, 0.0);
+    return cconj(csub(a.at<c64>(t, a.lay.fimg)[pix], a.at<c64>(t, a.lay.fpp)[pix]));
+  }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+};
+// Pass 2 (columns): column FFT completes fft2(b); times p; column FFT.
+template <int N> struct OpR2 {
+  static constexpr bool INV1 = false, TWO = true, INV2 = false;
+  ClassArgs a;
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  __device__ void mid(int t, int y, int x, c64 &v) const {
+    v = cmul(v, a.at<c64>(t, a.lay.ptil)[y * N + x]);
+  }
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+};
+// Pass 3 (rows): row FFT completes N^2 v over the grid.
+template <int N> struct OpR3 {
+  static constexpr bool INV1 = false, TWO = false, INV2 = false;
+  ClassArgs a;
+  __device__ int rows() const { return N; }
+  __device__ int row_of(int r) const { return r; }
+  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  __device__ void mid(int, int, int, c64 &) const {}
+  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+};
+// conj(v[u]) into row n of the gram storage (the Cholesky's right-hand-side row).
+__global__ __launch_bounds__(256) void k_df_rhs_gather(ClassArgs a, StepArgs s) {
   const int t = blockIdx.y;
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= s.m) return;
-  const uint32_t w = s.q[q];
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= s.nu) return;
+  const uint32_t w = s.u[u];
   const int pos = fft_pos(kunpack_y(w), a.n) * a.n + fft_pos(kunpack_x(w), a.n);
-  const c64 d = csub(a.at<c64>(t, a.lay.fimg)[pos], a.at<c64>(t, a.lay.fpp)[pos]);
-  a.at<c64>(t, a.lay.bvec)[q] = cconj(d);
+  const c64 c = a.at<c64>(t, a.lay.dtmp)[pos];
+  const double inv2 = 1.0 / ((double)a.n * a.n);
+  a.at<c64>(t, a.lay.gram)[(int64_t)s.nu * a.nu_pad + u] = make_double2(c.x * inv2, -c.y * inv2);
 }
 
 __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
@@ -254,56 +297,6 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
       G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,
                                             tv.y * inv2 - acc[i][j].y * inv4);
     }
-  }
-}
-
-// v[u] = N^-2 sum_{k in Q} P_hat(u + k) b(k)   (C^H b), stored as conj(v) in
-// row n of the gram storage (the Cholesky's right-hand-side row).
-// Workgroup = 64 unknowns x 4 lanes over Q.
-__global__ __launch_bounds__(256) void k_df_rhs_v(ClassArgs a, StepArgs s) {
-  const int t = blockIdx.y;
-  const int lu = threadIdx.x & 63, lq = threadIdx.x >> 6;
-  const int u = blockIdx.x * 64 + lu;
-  const c64 *phat = a.at<c64>(t, a.lay.phat);
-  const c64 *b = a.at<c64>(t, a.lay.bvec);
-  __shared__ uint32_t sk[256];
-  __shared__ c64 sb[256];
-  __shared__ c64 red[4][64];
-  int uy = 0, ux = 0;
-  if (u < s.nu) {
-    uy = kunpack_y(s.u[u]);
-    ux = kunpack_x(s.u[u]);
-  }
-  double vx = 0.0, vy = 0.0;
-  const uint64_t *qm = s.qmask + (int64_t)blockIdx.x * s.nwq;
-  for (int q0 = 0; q0 < s.m; q0 += kQChunk) {
-    const int qc = q0 / kQChunk;
-    if (!((qm[qc >> 6] >> (qc & 63)) & 1u)) continue;  // no u + k in P for this block
-    const int q = q0 + threadIdx.x;
-    sk[threadIdx.x] = q < s.m ? s.q[q] : 0u;
-    sb[threadIdx.x] = q < s.m ? b[q] : make_double2(0.0, 0.0);
-    __syncthreads();
-    if (u < s.nu) {
-      const int lim = min(256, s.m - q0);
-      for (int k = lq; k < lim; k += 4) {
-        const uint32_t kw = sk[k];
-        const c64 p = phat_at(phat, a.n, uy + kunpack_y(kw), ux + kunpack_x(kw));
-        const c64 bb = sb[k];
-        vx = fma(p.x, bb.x, fma(-p.y, bb.y, vx));
-        vy = fma(p.x, bb.y, fma(p.y, bb.x, vy));
-      }
-    }
-    __syncthreads();
-  }
-  red[lq][lu] = make_double2(vx, vy);
-  __syncthreads();
-  if (lq == 0 && u < s.nu) {
-    c64 v = red[0][lu];
-    v = cadd(v, red[1][lu]);
-    v = cadd(v, red[2][lu]);
-    v = cadd(v, red[3][lu]);
-    const double inv2 = 1.0 / ((double)a.n * a.n);
-    a.at<c64>(t, a.lay.gram)[(int64_t)s.nu * a.nu_pad + u] = make_double2(v.x * inv2, -v.y * inv2);
   }
 }
 

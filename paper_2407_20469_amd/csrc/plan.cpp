@@ -77,6 +77,10 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   p.ridge_df = g.ridge_darkfield;
   p.log_floor_rel = g.log_floor_rel;
   if (p.r < 2.0) return APIC_EUNSUPPORTED;
+  // C^H b is formed as a circular correlation on the N x N grid; it equals
+  // the linear one when no u + k (u in U, k in Q: within 3r of the darkfield
+  // support's centre) can alias onto P (within r of it), i.e. when 4r < N.
+  if (4.0 * p.r >= n) return APIC_EUNSUPPORTED;
   p.kbf.assign(g.k_bf, g.k_bf + 2 * g.n_bf);
   p.kdf.assign(g.k_df ? g.k_df : g.k_bf, (g.k_df ? g.k_df : g.k_bf) + 2 * g.n_df);
 
@@ -216,13 +220,10 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     {
       std::vector<uint8_t> live(size_t(W) * W);
       const int nub = (st.nu + 63) / 64;
-      const int nec = (st.ne + kEChunk - 1) / kEChunk, nqc = (st.m + kQChunk - 1) / kQChunk;
+      const int nec = (st.ne + kEChunk - 1) / kEChunk;
       st.nwe = (nec + 63) / 64;
-      st.nwq = (nqc + 63) / 64;
       st.off_gmask = int64_t(p.masks.size());
       p.masks.resize(p.masks.size() + size_t(nub) * st.nwe, 0);
-      st.off_qmask = int64_t(p.masks.size());
-      p.masks.resize(p.masks.size() + size_t(nub) * st.nwq, 0);
       for (int b = 0; b < nub; ++b) {
         std::fill(live.begin(), live.end(), 0);
         for (int ui = b * 64; ui < std::min(st.nu, b * 64 + 64); ++ui)
@@ -236,11 +237,6 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
             const int c = e / kEChunk;
             p.masks[st.off_gmask + size_t(b) * st.nwe + c / 64] |= uint64_t(1) << (c % 64);
           }
-        for (int q = 0; q < st.m; ++q)
-          if (is_live(Q[q])) {
-            const int c = q / kQChunk;
-            p.masks[st.off_qmask + size_t(b) * st.nwq + c / 64] |= uint64_t(1) << (c % 64);
-          }
       }
       for (int I = 0; I < nub; ++I)
         for (int J = 0; J <= I; ++J)
@@ -252,6 +248,14 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
             if (I == J) st.gram_live_diag += c;
           }
       p.gram_chunk_pairs += st.gram_live;
+    }
+    // Q membership over the grid
+    st.off_qbits = int64_t(p.masks.size());
+    p.masks.resize(p.masks.size() + size_t(nn + 63) / 64, 0);
+    for (uint32_t w : Q) {
+      const int y = (unpack_ky(w) + n) % n, x = (unpack_kx(w) + n) % n;
+      const int pix = y * n + x;
+      p.masks[st.off_qbits + pix / 64] |= uint64_t(1) << (pix % 64);
     }
     for (auto &u : Uc) {
       const int y = (u.first + n) % n, x = (u.second + n) % n;
@@ -284,7 +288,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.dtmp = take(int64_t(nn) * c64);
   L.fpp = take(int64_t(nn) * c64);
   L.fimg = take(int64_t(nn) * c64);
-  L.bvec = take(std::max<int64_t>(1, p.m_max) * c64);
+  L.ptil = take(int64_t(nn) * c64);
   L.vec = take(int64_t(p.nu_pad) * c64);
   L.gram = take(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256);
   L.linv = take(int64_t(p.nu_pad / kGramBlock) * kGramBlock * kGramBlock * c64);

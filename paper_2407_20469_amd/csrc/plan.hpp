@@ -20,7 +20,6 @@ constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cell
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram / Cholesky padding granularity
 constexpr int kEChunk = 16;         // E rows per gram k-chunk
-constexpr int kQChunk = 256;        // Q rows per C^H b chunk
 constexpr int kMaxEChunks = 4096;   // gram chunk list capacity (65536 rows of E)
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
@@ -37,17 +36,18 @@ struct DfStep {
   int32_t nu = 0, np = 0, m = 0, ne = 0;
   int64_t off_u = 0, off_p = 0, off_q = 0, off_e = 0;  // into GeomPlan::coords
   // Block-sparsity masks (into GeomPlan::masks): for each block of 64
-  // unknowns, one bit per chunk of kEChunk rows of E (gram) / kQChunk rows of
-  // Q (C^H b) that holds a k with u + k in P for some u of the block.
-  int32_t nwe = 0, nwq = 0;          // 64-bit words per block
-  int64_t off_gmask = 0, off_qmask = 0;
+  // unknowns, one bit per chunk of kEChunk rows of E that holds a k with
+  // u + k in P for some u of the block.  Then the membership bitmap of Q over
+  // the N x N grid (FFT order, bit y N + x).
+  int32_t nwe = 0;                   // 64-bit words per block
+  int64_t off_gmask = 0, off_qbits = 0;
   int64_t gram_live = 0;             // live (I >= J block pair, E chunk) triples
   int64_t gram_live_diag = 0;        // the I = J part of gram_live
 };
 
 // Per-tile workspace layout (byte offsets from the tile's base).
 struct TileLayout {
-  int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, fimg = 0, bvec = 0, vec = 0,
+  int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, fimg = 0, ptil = 0, vec = 0,
           gram = 0, linv = 0, part = 0, sums = 0, coef = 0, sur = 0, eps = 0, stride = 0;
 };
 
