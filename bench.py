@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--tiles", type=int, default=None)
     ap.add_argument("--ws-gb", type=float, default=64.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph", dest="graph", action="store_true", default=None)
+    ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--plain-tiles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -146,7 +148,8 @@ def main():
         del buf
         tune = [{"geom": c["geom"], "tiles": c["n_tiles"], "chunk": c["chunk"],
                  "ms_per_tile": float(m)} for c, m in zip(batch.classes(), ms_tile)]
-        log(f"autotune {time.time() - t0:.1f} s: chunks {[c['chunk'] for c in tune]}")
+        log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk) "
+            f"{[(c['geom'], c['tiles'], c['chunk']) for c in tune]}")
     elif batch.workspace_bytes > budget:
         for i, c in enumerate(batch.classes()):
             batch.set_chunk(i, max(1, budget // (len(ws_list) * c["tile_bytes"])))
@@ -174,21 +177,24 @@ def main():
     st = status.cpu().numpy()
     bad = int(((st & (apic.TILE_NONFINITE_INPUT | apic.TILE_NONFINITE_OUT)) != 0).sum())
 
-    # the same step captured into a graph and replayed
-    gstream = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    batch.capture(images, field, zern, status, ws, gstream)
-    with torch.cuda.stream(gstream):
-        batch.launch(gstream)
-        g0 = torch.cuda.Event(enable_timing=True)
-        g1 = torch.cuda.Event(enable_timing=True)
-        g0.record(gstream)
-        for i in range(args.steps):
+    # the same step captured into a graph and replayed (the uneven batch's
+    # chunked 512 px classes enqueue ~10^5 launches: no graph there by default)
+    graph_ms = None
+    if args.graph if args.graph is not None else args.workload == "cfg1":
+        gstream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        batch.capture(images, field, zern, status, ws, gstream)
+        with torch.cuda.stream(gstream):
             batch.launch(gstream)
-        g1.record(gstream)
-    gstream.synchronize()
-    graph_ms = g0.elapsed_time(g1) / args.steps
-    log(f"graph replay: {graph_ms:.1f} ms/step")
+            g0 = torch.cuda.Event(enable_timing=True)
+            g1 = torch.cuda.Event(enable_timing=True)
+            g0.record(gstream)
+            for i in range(args.steps):
+                batch.launch(gstream)
+            g1.record(gstream)
+        gstream.synchronize()
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        log(f"graph replay: {graph_ms:.1f} ms/step")
 
     # plain path: the same kernels, one tile per call, first class
     w0 = ws_list[0]
@@ -251,7 +257,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": config,
-        "graph": {"value": mpx_step / (graph_ms * 1e-3), "ms_per_step": graph_ms},
+        "graph": None if graph_ms is None else {"value": mpx_step / (graph_ms * 1e-3),
+                                                "ms_per_step": graph_ms},
         "plain": {"value": (nf0 * nf0 / 1e6) / plain_s, "unit": "Mpx/s", "tiles_timed": P,
                   "ms_per_tile": plain_s * 1e3, "class": 0},
         "autotune": tune,

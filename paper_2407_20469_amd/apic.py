@@ -75,10 +75,15 @@ _lib = None
 
 
 def load_library(path=LIB_PATH):
-    """Load libapic.so (raises if it has not been built)."""
+    """Load libapic.so (raises if it has not been built).
+
+    torch is imported first: it carries its own HIP runtime, and the library
+    must bind to that same runtime (loading a second one first leaves torch
+    without devices)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"libapic.so not found at {path}: run "
                            "`python -m paper_2407_20469_amd.build` (hipcc, gfx950) first")

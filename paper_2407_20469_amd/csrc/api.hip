@@ -402,17 +402,28 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       // complex Cholesky (4/3) n^3 flops plus the two triangular solves 8 n^2
       ProfScope ps(APIC_PROF_CHOL, T * (4.0 / 3.0 * nu * nu * nu + 8.0 * nu * nu), st);
       const int n = d.nu;
-      for (int kb = 0; kb < n; kb += kCB) {
-        const CholArgs ca{n, kb, a.lay.linv};
-        const int bs = std::min(kCB, n - kb);
-        hipLaunchKernelGGL(k_chol_potrf, dim3(a.T), dim3(256), 0, st, a, ca);
-        APIC_LAUNCHED();
-        const int nrb = (n + 1 - (kb + bs) + kCB - 1) / kCB;
-        if (nrb > 0) {
-          hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)(a.T * nrb)), dim3(256), 0, st, a, ca);
+      for (int kb = 0; kb < n; kb += kCW) {
+        const int pe = std::min(n, kb + kCW);
+        for (int sb = kb; sb < pe; sb += kCB) {
+          const int bs = std::min(kCB, n - sb);
+          const CholArgs ca{n, sb, a.lay.linv, bs, sb + bs, pe};
+          hipLaunchKernelGGL(k_chol_potrf, dim3(a.T), dim3(256), 0, st, a, ca);
           APIC_LAUNCHED();
-          hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(a.T * (nrb * (nrb + 1) / 2))),
-                             dim3(256), 0, st, a, ca);
+          const int nrb = (n + 1 - (sb + bs) + kCB - 1) / kCB;
+          if (nrb > 0) {
+            hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)(a.T * nrb)), dim3(256), 0, st, a, ca);
+            APIC_LAUNCHED();
+          }
+          if (sb + bs < pe) {  // the panel's remaining columns
+            hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(a.T * upd_tiles(ca))), dim3(256), 0,
+                               st, a, ca);
+            APIC_LAUNCHED();
+          }
+        }
+        if (pe < n) {  // the trailing matrix, once per wide panel
+          const CholArgs cu{n, kb, a.lay.linv, pe - kb, pe, n};
+          hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(a.T * upd_tiles(cu))), dim3(256), 0,
+                             st, a, cu);
           APIC_LAUNCHED();
         }
       }
@@ -986,7 +997,8 @@ static void batch_layout(apic_batch *b) {
   b->cls_ws.assign(b->runs.size(), 0);
   for (size_t c = 0; c < b->runs.size(); ++c) {
     b->cls_ws[c] = o;
-    o = align256(o + (int64_t)b->chunk[c] * b->plan->geoms[b->runs[c].geom].lay.stride);
+    o = align256(o + (int64_t)std::max(1, b->chunk[c]) *
+                         b->plan->geoms[b->runs[c].geom].lay.stride);
   }
   b->ws_bytes = std::max<int64_t>(o, 256);
 }
@@ -1006,7 +1018,7 @@ static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count
   const ClassRun &r = b->runs[c];
   ClassArgs a = make_args(b->plan, r, images, ws, status, reinterpret_cast<const char *>(b->d_desc));
   a.ws = ws + b->cls_ws[c];
-  const int step = std::max(1, b->chunk[c]);
+  const int step = std::max(1, b->chunk[c]);  // chunks are >= 1 by construction
   for (int c0 = first; c0 < first + count; c0 += step) {
     const apic_status rc =
         run_class(b->plan, r, chunk_args(a, c0, std::min(step, first + count - c0)), mask, io, st);
@@ -1226,15 +1238,21 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
           rc = APIC_EHIP;
       }
-      per_tile.push_back(ms / k);
-      best = std::min(best, (double)ms / k);
+      const double tile_ms = (double)ms / k;
+      per_tile.push_back(tile_ms);
+      if (tile_ms < best) {
+        best = tile_ms;
+        pick = k;
+      }
       if (ms > 2000.f) break;  // longer runs add little to the choice
     }
+    if (rc != APIC_OK) break;
     if (per_tile.empty()) {
       rc = APIC_EINVAL;  // not even one tile of this class fits the workspace
       break;
     }
-    // smallest chunk within (1 + slack) of the best time per tile
+    // smallest chunk within (1 + slack) of the best time per tile (the best
+    // itself qualifies, so pick >= 1)
     for (size_t i = 0; i < per_tile.size(); ++i)
       if (per_tile[i] <= best * (1.0 + slack)) {
         pick = cand[i];

@@ -4,13 +4,17 @@
 // The right-hand side rides along as row n of the (n+1)-row lower-triangular
 // storage (row n holds conj(v)): factoring [[G, v], [v^H, *]] leaves
 // conj(L^-1 v) in row n, so the forward substitution costs one extra row of
-// the factorisation.  Right-looking, 64-wide panels; per panel three launches
-// over all tiles of the class:
+// the factorisation.  Right-looking with two levels of panels: the trailing
+// matrix is updated once per kCW columns (each update streams the whole
+// trailing triangle, so wider panels move fewer bytes), and inside a wide
+// panel its 64-column sub-panels are factored one after another with
+// launches over all tiles of the class:
 //   k_chol_potrf  : factor the 64 x 64 diagonal block in registers and
 //                   invert it in LDS (first panel: also add the ridge);
 //   k_chol_trsm   : panel rows times the inverted block's conjugate transpose
 //                   (64-row blocks, register-tiled like a GEMM);
-//   k_chol_update : trailing lower 64 x 64 tiles minus panel times panel^H.
+//   k_chol_update : lower 64 x 64 tiles minus panel times panel^H (the rest
+//                   of the wide panel's columns, then the trailing matrix).
 // k_chol_back then solves L^H x = y with one wavefront per tile and scatters
 // x into the tile's spectrum.
 #pragma once
@@ -20,14 +24,31 @@
 
 namespace apic {
 
-constexpr int kCB = 64;   // panel width / tile size
+constexpr int kCB = 64;   // sub-panel width / tile size
+constexpr int kCW = 128;  // wide-panel width (trailing update interval)
 constexpr int kCK = 16;   // k-chunk staged in LDS
 
 struct CholArgs {
   int n;            // system size
-  int kb;           // panel start column
+  int kb;           // panel start column (update: first column of its K range)
   int64_t linv_off; // per-tile byte offset of the 64 x 64 inverse block
+  int kw;           // update: K width (columns kb .. kb + kw - 1)
+  int c0;           // update: first output row and column
+  int cend;         // update: output columns end here (exclusive)
 };
+
+// Output tiles of an update: row blocks from c0 through row n (the right-hand
+// side row), column blocks from c0 up to cend, lower triangle only.
+__host__ __device__ inline int upd_row_blocks(const CholArgs &c) {
+  return (c.n + 1 - c.c0 + kCB - 1) / kCB;
+}
+__host__ __device__ inline int upd_col_blocks(const CholArgs &c) {
+  return ((c.cend < c.n ? c.cend : c.n) - c.c0 + kCB - 1) / kCB;
+}
+__host__ __device__ inline int upd_tiles(const CholArgs &c) {
+  const int nr = upd_row_blocks(c), nc = upd_col_blocks(c);
+  return nc * nr - nc * (nc - 1) / 2;
+}
 
 // Factor the diagonal block [kb, kb+bs) (lower) and write it back; write its
 // lower-triangular inverse to the tile's inverse block kb / 64.
@@ -257,22 +278,23 @@ __global__ __launch_bounds__(256) void k_chol_trsm(ClassArgs a, CholArgs c) {
   }
 }
 
-// Trailing update of the lower tiles of rows [kb+bs, n] x cols [kb+bs, n).
+// Update A[r][q] -= sum_{p in [kb, kb + kw)} L[r][p] conj(L[q][p]) of the lower
+// tiles of rows [c0, n] x columns [c0, min(cend, n)): the trailing matrix
+// after a wide panel, or the rest of the panel's own columns after one of its
+// 64-column sub-panels.  Tiles are enumerated column block by column block.
 __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   const int n = c.n, kb = c.kb, ld = a.nu_pad;
-  const int bs = min(kCB, n - kb);
-  const int c0 = kb + bs;
-  const int nrb = (n + 1 - c0 + kCB - 1) / kCB;
-  const int ntri = nrb * (nrb + 1) / 2;
-  const int t = blockIdx.x / ntri;
-  int rem = blockIdx.x % ntri, I = 0;
-  while (rem > I) {
-    rem -= I + 1;
-    ++I;
+  const int nrb = upd_row_blocks(c);
+  const int per_tile = upd_tiles(c);
+  const int t = blockIdx.x / per_tile;
+  int rem = blockIdx.x % per_tile, J = 0;
+  while (rem >= nrb - J) {
+    rem -= nrb - J;
+    ++J;
   }
-  const int J = rem;
-  const int ib = c0 + I * kCB, jb = c0 + J * kCB;
-  if (jb >= n) return;
+  const int I = J + rem;
+  const int ib = c.c0 + I * kCB, jb = c.c0 + J * kCB;
+  const int qend = min(c.cend, n);
   c64 *G = a.at<c64>(t, a.lay.gram);
   __shared__ c64 sA[kCK][kCB + 1], sB[kCK][kCB + 1];
   c64 acc[4][4];
@@ -286,9 +308,9 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   };
   auto lb = [&](int rr, int p) {
     const int r = jb + rr;
-    return (r < n) ? G[(int64_t)r * ld + kb + p] : make_double2(0.0, 0.0);
+    return (r < qend) ? G[(int64_t)r * ld + kb + p] : make_double2(0.0, 0.0);
   };
-  tile_gemm_nc(acc, bs, la, lb, sA, sB);
+  tile_gemm_nc(acc, c.kw, la, lb, sA, sB);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -297,7 +319,7 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = jb + tx * 4 + j;
-      if (q < n && q <= r) {
+      if (q < qend && q <= r) {
         c64 *gp = G + (int64_t)r * ld + q;
         *gp = csub(*gp, acc[i][j]);
       }
