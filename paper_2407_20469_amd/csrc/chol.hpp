@@ -196,8 +196,10 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
 }
 
 // 64 x 64 register-tiled complex FP64 product over a K range staged in LDS:
-// acc[i][j] += sum_p A(row i, p) conj(B(row j, p)), with the operands given by
-// loader callbacks.  16 x 16 threads, 4 x 4 outputs each.  The loaders run
+// acc[i][j] += sum_p A(row ty + 16 i, p) conj(B(row tx + 16 j, p)), with the
+// operands given by loader callbacks.  16 x 16 threads, 4 x 4 outputs each,
+// 16 apart, so that the lanes reading one LDS row read consecutive elements
+// (no bank conflicts) and write consecutive columns.  The loaders run
 // along p (16 consecutive elements of a row per 16 lanes, one K chunk ahead
 // in registers); the LDS rows are padded by one element so that the
 // transposing store does not serialise on one bank group.
@@ -228,9 +230,9 @@ __device__ __forceinline__ void tile_gemm_nc(c64 (&acc)[4][4], int K, LA la, LB 
     for (int kk = 0; kk < kCK; ++kk) {
       c64 av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty * 4 + i];
+      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx * 4 + j];
+      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx + 16 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -268,11 +270,11 @@ __global__ __launch_bounds__(256) void k_chol_trsm(ClassArgs a, CholArgs c) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = rbase + ty * 4 + i;
+    const int r = rbase + ty + 16 * i;
     if (r > n) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int q = tx * 4 + j;
+      const int q = tx + 16 * j;
       if (q < bs) G[(int64_t)r * ld + kb + q] = acc[i][j];
     }
   }
@@ -314,11 +316,11 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = ib + ty * 4 + i;
+    const int r = ib + ty + 16 * i;
     if (r > n) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int q = jb + tx * 4 + j;
+      const int q = jb + tx + 16 * j;
       if (q < qend && q <= r) {
         c64 *gp = G + (int64_t)r * ld + q;
         *gp = csub(*gp, acc[i][j]);

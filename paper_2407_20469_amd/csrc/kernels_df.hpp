@@ -161,10 +161,11 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
 // ascending order; the operands P_hat(u + k) of the next chunk are gathered
 // into registers while the current chunk is multiplied from LDS.
 //  * kDiag = false: the blocks below the diagonal (I > J); 16 x 16 threads,
-//    4 x 4 complex outputs each.
+//    4 x 4 complex outputs each (rows and columns 16 apart).
 //  * kDiag = true: the diagonal blocks (I = J, one operand).  Only the three
 //    lower 32 x 32 quadrants are formed: waves 0-2 take quadrants (0,0),
-//    (1,0), (1,1) with 8 x 8 lanes of 4 x 4 outputs; wave 3 only gathers.
+//    (1,0), (1,1) with 8 x 8 lanes of 4 x 4 outputs (8 apart); wave 3 only
+//    gathers.
 constexpr int kGramKC = kEChunk;
 constexpr int kGramMaxChunks = kMaxEChunks;
 template <bool kDiag>
@@ -190,15 +191,19 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   __shared__ uint16_t clist[kGramMaxChunks];
   __shared__ int ncl;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // output rows ra + 4 i and columns cb + 4 j of the block
-  int ra, cb;
+  // output rows ra + rs i and columns cb + rs j of the block: lanes that read
+  // one operand row of the LDS stage read consecutive elements (no bank
+  // conflicts) and write consecutive columns of G
+  int ra, cb, rs;
   if (kDiag) {
     const int qr = wv == 0 ? 0 : 1, qc = wv == 2 ? 1 : 0;
-    ra = qr * 32 + (lane >> 3) * 4;
-    cb = qc * 32 + (lane & 7) * 4;
+    ra = qr * 32 + (lane >> 3);
+    cb = qc * 32 + (lane & 7);
+    rs = 8;
   } else {
-    ra = (tid >> 4) * 4;
-    cb = (tid & 15) * 4;
+    ra = tid >> 4;
+    cb = tid & 15;
+    rs = 16;
   }
   const bool active = !kDiag || wv < 3;
   if (tid < kGramBlock) {
@@ -261,9 +266,9 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
       for (int kk = 0; kk < kGramKC; ++kk) {
         c64 av[4], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = sA[kk][ra + i];
+        for (int i = 0; i < 4; ++i) av[i] = sA[kk][ra + rs * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = cols[kk * kGramBlock + cb + j];
+        for (int j = 0; j < 4; ++j) bv[j] = cols[kk * kGramBlock + cb + rs * j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -283,15 +288,15 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   const int ld = a.nu_pad;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = I * kGramBlock + ra + i;
+    const int r = I * kGramBlock + ra + rs * i;
     if (r >= s.nu) continue;
-    const uint32_t wr = su[0][ra + i];
+    const uint32_t wr = su[0][ra + rs * i];
     const int ry = kunpack_y(wr), rx = kunpack_x(wr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = J * kGramBlock + cb + j;
+      const int c = J * kGramBlock + cb + rs * j;
       if (c >= s.nu) continue;
-      const uint32_t wc = su[1][cb + j];
+      const uint32_t wc = su[1][cb + rs * j];
       const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
       const c64 tv = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
       G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,
