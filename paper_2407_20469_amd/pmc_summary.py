@@ -1,15 +1,19 @@
 """Summaries of rocprofv3 output for roofline reporting.
 
     python -m paper_2407_20469_amd.pmc_summary stats <kernel_stats.csv> [top]
+    python -m paper_2407_20469_amd.pmc_summary dispatches <kernel_trace.csv> <regex> <min_grid>
     python -m paper_2407_20469_amd.pmc_summary traffic <fetch_dir> <write_dir> \
         <copy_fetch_dir> <copy_write_dir> <min_grid> [out.json]
 
 `traffic` reads the counter-collection CSVs of four `rocprofv3 --pmc` runs
-(FETCH_SIZE and WRITE_SIZE of the darkfield gram kernel, and the same two
+(FETCH_SIZE and WRITE_SIZE of the darkfield gram kernels, and the same two
 counters of the library's 4 GiB copy probe), scales each counter by the bytes
-the copy is known to move, averages over the gram dispatches whose grid has at
-least `min_grid` work-items, and records the hash of the gram's sources so a
-later change of the kernel invalidates the figure.
+the copy is known to move, and sums the gram dispatches whose grid has at least
+`min_grid` work-items.  One gram "launch" is one darkfield image step of a
+batch: the diagonal-block dispatch plus the below-diagonal dispatch, so the
+figure is the total over both kernels divided by the number of diagonal-block
+dispatches.  The hash of the gram's sources is recorded so a later change of
+the kernel invalidates the figure.
 """
 
 import csv
@@ -42,13 +46,43 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, min_grid):
     cw = [float(r["Counter_Value"]) for r in _counter_rows(cw_dir)]
     sf = COPY_BYTES / 1024.0 / (sum(cf) / len(cf))
     sw = COPY_BYTES / 1024.0 / (sum(cw) / len(cw))
-    f = [float(r["Counter_Value"]) for r in _counter_rows(fetch_dir) if int(r["Grid_Size"]) >= min_grid]
-    w = [float(r["Counter_Value"]) for r in _counter_rows(write_dir) if int(r["Grid_Size"]) >= min_grid]
-    fb = sum(f) / len(f) * 1024.0 * sf
-    wb = sum(w) / len(w) * 1024.0 * sw
-    return {"kernel": "k_df_gram", "fetch_scale": sf, "write_scale": sw, "dispatches": len(f),
-            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-            "bytes_per_launch": fb + wb, "source_sha256": gram_source_hash()}
+    def gram(d):
+        rows = [r for r in _counter_rows(d) if int(r["Grid_Size"]) >= min_grid]
+        steps = sum(1 for r in rows if "k_df_gram<true>" in r["Kernel_Name"])
+        return sum(float(r["Counter_Value"]) for r in rows), steps
+
+    f, steps = gram(fetch_dir)
+    w, steps_w = gram(write_dir)
+    if steps == 0 or steps != steps_w:
+        raise ValueError("the two counter runs must cover the same gram dispatches")
+    fb = f / steps * 1024.0 * sf
+    wb = w / steps * 1024.0 * sw
+    return {"kernel": "k_df_gram (diagonal + below-diagonal blocks)", "fetch_scale": sf,
+            "write_scale": sw, "image_steps": steps, "fetch_bytes_per_launch": fb,
+            "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+            "source_sha256": gram_source_hash()}
+
+
+def dispatches(path, pattern, min_grid):
+    """Per-kernel count, mean and spread of the dispatch durations of the kernels
+    matching `pattern` whose grid has at least `min_grid` work-items (the batched
+    calls, not the single-tile ones)."""
+    import re
+    rx = re.compile(pattern)
+    by = {}
+    for r in csv.DictReader(open(path)):
+        if "Grid_Size" in r:
+            grid = int(r["Grid_Size"])
+        else:
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        if not rx.search(r["Kernel_Name"]) or grid < min_grid:
+            continue
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        by.setdefault(r["Kernel_Name"][:90], []).append(d)
+    out = ["| kernel | dispatches | mean us | min us | max us |", "|---|---:|---:|---:|---:|"]
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+    return "\n".join(out)
 
 
 def stats(path, top=16):
@@ -72,5 +106,7 @@ if __name__ == "__main__":
             with open(sys.argv[7], "w") as fh:
                 fh.write(text + "\n")
         print(text)
+    elif sys.argv[1] == "dispatches":
+        print(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4])))
     elif sys.argv[1] == "hash":
         print(gram_source_hash())
