@@ -101,10 +101,11 @@ template <class C, int L> struct RowShape {
   static constexpr int ROWS = (4 * kFftThreads) / L;  // rows per workgroup
 };
 template <class C, int L> struct ColShape {
-  // Column panel width: 16 columns (128 B of complex64 per row) while the
-  // panel fits in 64 KiB of LDS, fewer for long complex128 columns.
-  static constexpr int NSEQ = (L * 16 * (int)sizeof(C) <= 65536) ? 16
-                              : (L * 8 * (int)sizeof(C) <= 65536) ? 8 : 4;
+  // Column panel width: up to 16 columns, at most 2048 elements (8 per
+  // thread; 32 KiB of complex128), at least 4 columns (64 B of complex128
+  // per row).  Small panels leave LDS for several workgroups per CU, which
+  // hides the strided HBM reads better than wider rows would.
+  static constexpr int NSEQ = (2048 / L >= 16) ? 16 : (2048 / L >= 8) ? 8 : 4;
 };
 
 // Row pass: workgroup = ROWS consecutive rows of one 2D array.  Op provides
