@@ -242,6 +242,15 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
 
+    # HBM-bound groups: algorithmic bytes over their live-timed duration
+    hbm_groups = ("kk", "stitch", "df_fft", "df_rhs", "out")
+    hbm = {k: {"GB/s": prof[k][2] / (prof[k][0] * 1e-3) / 1e9,
+               "frac": prof[k][2] / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+           for k in hbm_groups if k in prof and prof[k][0] > 0}
+    tb = sum(prof[k][2] for k in hbm)
+    tt = sum(prof[k][0] for k in hbm) * 1e-3
+    hbm["all"] = {"GB/s": tb / tt / 1e9, "frac": tb / tt / 1e9 / HBM_PEAK_GBS}
+
     if args.workload == "cfg1":
         w = ws_list[0]
         config = {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
@@ -268,6 +277,7 @@ def main():
         "workspace_gib": batch.workspace_bytes / 2 ** 30,
         "nonfinite_tiles": bad,
         "roofline": roof,
+        "hbm_passes": hbm,
         "kernel_groups": groups,
     }
     if not args.no_cpu_baseline:

@@ -307,8 +307,9 @@ apic_status run_pupil(const ClassArgs &a, const float *seed, float *zout, float 
   return APIC_OK;
 }
 
-apic_status run_stitch(const ClassArgs &a, float *spec_out, hipStream_t st) {
-  ProfScope ps(APIC_PROF_STITCH, (double)a.T * a.n * a.n * 8.0 * (a.n_bf + 1), st);
+apic_status run_stitch(const ClassArgs &a, int64_t n_disk, float *spec_out, hipStream_t st) {
+  // bytes: each KK spectrum read on its support, O_hat written
+  ProfScope ps(APIC_PROF_STITCH, (double)a.T * 8.0 * ((double)a.n_bf * n_disk + a.n * a.n), st);
   hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);
   APIC_LAUNCHED();
   hipLaunchKernelGGL(k_stitch, dim3(blocks_for((int64_t)a.T * a.n * a.n, 256)), dim3(256), 0, st,
@@ -369,9 +370,11 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       APIC_LAUNCHED();
     }
     {
-      // three FP64 passes: read fimg and fpp, write (48 B); read and read P,
-      // write (48 B); read, write (32 B); then N_u gathers (32 B each)
-      ProfScope ps(APIC_PROF_DF_RHS, (double)pix * 128.0 + T * nu * 32.0, st);
+      // three FP64 passes: Q bitmap, fimg and fpp on Q, write (16 B per pixel
+      // + 32 B per Q point); read and read P, write (48 B); read, write (32 B);
+      // then N_u gathers (32 B each)
+      ProfScope ps(APIC_PROF_DF_RHS,
+                   (double)pix * (16.0 + 48.0 + 32.0 + 0.125) + T * (32.0 * d.m + 32.0 * nu), st);
       hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpR1<N>{a, s.qbits});
       APIC_LAUNCHED();
@@ -499,7 +502,7 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
     APIC_LAUNCHED();
   }
   if (st_mask & S_STITCH) {
-    rc = run_stitch(a, io.spec_out, st);
+    rc = run_stitch(a, p->geoms[r.geom].n_disk, io.spec_out, st);
     if (rc) return rc;
   } else if (st_mask & (S_DF | S_SPEC_IN)) {
     hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);

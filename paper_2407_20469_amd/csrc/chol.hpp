@@ -251,7 +251,8 @@ __global__ __launch_bounds__(256) void k_chol_trsm(ClassArgs a, CholArgs c) {
   const int bs = min(kCB, n - kb);
   const int r0 = kb + bs;
   const int nrb = (n + 1 - r0 + kCB - 1) / kCB;
-  const int t = blockIdx.x / nrb, rb = blockIdx.x % nrb;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = bid / nrb, rb = bid % nrb;
   const int rbase = r0 + rb * kCB;
   c64 *G = a.at<c64>(t, a.lay.gram);
   const c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
@@ -288,8 +289,9 @@ __global__ __launch_bounds__(256) void k_chol_update(ClassArgs a, CholArgs c) {
   const int n = c.n, kb = c.kb, ld = a.nu_pad;
   const int nrb = upd_row_blocks(c);
   const int per_tile = upd_tiles(c);
-  const int t = blockIdx.x / per_tile;
-  int rem = blockIdx.x % per_tile, J = 0;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);  // a tile's blocks on one XCD
+  const int t = bid / per_tile;
+  int rem = bid % per_tile, J = 0;
   while (rem >= nrb - J) {
     rem -= nrb - J;
     ++J;

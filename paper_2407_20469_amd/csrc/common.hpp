@@ -125,6 +125,16 @@ struct StepArgs {
   const uint64_t *qbits;          // Q membership over the grid (bit y N + x)
 };
 
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup b on XCD
+// b mod 8), each XCD with its own L2.  Maps the b-th of n workgroups to a work
+// index so that each XCD takes one contiguous range of work items.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  constexpr int kXcd = 8;
+  const int per = n / kXcd;
+  if (b >= per * kXcd) return b;
+  return (b % kXcd) * per + b / kXcd;
+}
+
 __device__ __forceinline__ void status_or(const ClassArgs &a, int t, uint32_t bits) {
   atomicOr(a.status + a.gidx(t), bits);
 }

@@ -147,8 +147,9 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(Op op) {
   constexpr int NSEQ = ColShape<C, L>::NSEQ;
   __shared__ C buf[L * NSEQ];
   constexpr int groups = L / NSEQ;
-  const int arr = blockIdx.x / groups;
-  const int x0 = (blockIdx.x % groups) * NSEQ;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring panels on one XCD
+  const int arr = bid / groups;
+  const int x0 = (bid % groups) * NSEQ;
   for (int e = threadIdx.x; e < L * NSEQ; e += kFftThreads) {
     const int y = e / NSEQ, c = e % NSEQ;
     buf[e] = op.load(arr, y, x0 + c);

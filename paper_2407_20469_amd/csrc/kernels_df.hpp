@@ -172,8 +172,9 @@ template <bool kDiag>
 __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramBlock - 1) / kGramBlock;
   const int per_tile = kDiag ? nb : nb * (nb - 1) / 2;
-  const int t = blockIdx.x / per_tile;
-  int rem = blockIdx.x % per_tile, I, J;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);  // a tile's blocks on one XCD
+  const int t = bid / per_tile;
+  int rem = bid % per_tile, I, J;
   if (kDiag) {
     I = J = rem;
   } else {  // strictly lower: I >= 1, J < I

@@ -73,6 +73,9 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   p.na = g.na_obj;
   p.r = g.na_obj * n * g.dx_um / g.wavelength_um;
   p.r2 = (int64_t)std::floor(p.r * p.r);
+  p.n_disk = 0;
+  for (int y = -n / 2; y < n / 2; ++y)
+    for (int x = -n / 2; x < n / 2; ++x) p.n_disk += int64_t(x) * x + int64_t(y) * y <= p.r2;
   p.ridge_pupil = g.ridge_pupil;
   p.ridge_df = g.ridge_darkfield;
   p.log_floor_rel = g.log_floor_rel;

@@ -55,6 +55,7 @@ struct GeomPlan {
   int n = 0, f = 1, nf = 0, n_bf = 0, n_df = 0;
   double dx = 0, lam = 0, na = 0, r = 0;
   int64_t r2 = 0;                    // floor(r * r): Circ(k) <=> kx^2 + ky^2 <= r2
+  int64_t n_disk = 0;                // grid points inside Circ
   double ridge_pupil = 1e-9, ridge_df = 1e-4, log_floor_rel = 1e-6;
   std::vector<int32_t> kbf, kdf;     // (kx, ky) pairs
   // pupil rows (Eq. 8-10): one row per (pair, K) with K in S_il, K != 0

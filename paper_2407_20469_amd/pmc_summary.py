@@ -2,6 +2,8 @@
 
     python -m paper_2407_20469_amd.pmc_summary stats <kernel_stats.csv> [top]
     python -m paper_2407_20469_amd.pmc_summary dispatches <kernel_trace.csv> <regex> <min_grid>
+    python -m paper_2407_20469_amd.pmc_summary hbm <fetch_dir> <write_dir> \
+        <copy_fetch_dir> <copy_write_dir> <min_grid>
     python -m paper_2407_20469_amd.pmc_summary traffic <fetch_dir> <write_dir> \
         <copy_fetch_dir> <copy_write_dir> <min_grid> [out.json]
 
@@ -85,6 +87,40 @@ def dispatches(path, pattern, min_grid):
     return "\n".join(out)
 
 
+def hbm(fetch_dir, write_dir, cf_dir, cw_dir, min_grid):
+    """Per-kernel HBM bytes (scaled FETCH_SIZE + WRITE_SIZE) and the rate they
+    imply over each dispatch's own duration, for the dispatches with at least
+    `min_grid` work-items; also the total over all of them."""
+    cf = [float(r["Counter_Value"]) for r in _counter_rows(cf_dir)]
+    cw = [float(r["Counter_Value"]) for r in _counter_rows(cw_dir)]
+    sf = COPY_BYTES / 1024.0 / (sum(cf) / len(cf))
+    sw = COPY_BYTES / 1024.0 / (sum(cw) / len(cw))
+    acc = {}
+    for d, scale, key in ((fetch_dir, sf, "fetch"), (write_dir, sw, "write")):
+        for r in _counter_rows(d):
+            if int(r["Grid_Size"]) < min_grid:
+                continue
+            e = acc.setdefault(r["Kernel_Name"][:90], {"fetch": 0.0, "write": 0.0, "ns": 0.0,
+                                                       "n": 0})
+            e[key] += float(r["Counter_Value"]) * 1024.0 * scale
+            if key == "fetch":
+                e["ns"] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                e["n"] += 1
+    out = ["| kernel | dispatches | GB per dispatch (read + write) | mean us | GB/s | of 8 TB/s |",
+           "|---|---:|---:|---:|---:|---:|"]
+    tb = tns = 0.0
+    for k, e in sorted(acc.items(), key=lambda kv: -kv[1]["ns"]):
+        b = e["fetch"] + e["write"]
+        tb += b
+        tns += e["ns"]
+        out.append(f"| `{k}` | {e['n']} | {b / e['n'] / 1e9:.3f} ({e['fetch'] / e['n'] / 1e9:.3f} + "
+                   f"{e['write'] / e['n'] / 1e9:.3f}) | {e['ns'] / e['n'] / 1e3:.1f} | "
+                   f"{b / e['ns']:.0f} | {b / e['ns'] / 8000:.2f} |")
+    out.append(f"| all of the above | | {tb / 1e9:.2f} GB in total | {tns / 1e6:.2f} ms in total | "
+               f"{tb / tns:.0f} | {tb / tns / 8000:.2f} |")
+    return "\n".join(out)
+
+
 def stats(path, top=16):
     rows = list(csv.DictReader(open(path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
@@ -108,5 +144,7 @@ if __name__ == "__main__":
         print(text)
     elif sys.argv[1] == "dispatches":
         print(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4])))
+    elif sys.argv[1] == "hbm":
+        print(hbm(*sys.argv[2:6], int(sys.argv[6])))
     elif sys.argv[1] == "hash":
         print(gram_source_hash())
