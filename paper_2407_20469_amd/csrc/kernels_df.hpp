@@ -150,8 +150,11 @@ __global__ __launch_bounds__(256) void k_df_rhs_gather(ClassArgs a, StepArgs s) 
   a.at<c64>(t, a.lay.gram)[(int64_t)s.nu * a.nu_pad + u] = make_double2(c.x * inv2, -c.y * inv2);
 }
 
+// P_hat(u + k) for u in U, k in E: read with periodic indexing.  u + k lies
+// within 3r of the darkfield support's centre and P within r of it, so a
+// wrapped position (off by a multiple of N > 4r) never falls in P, where
+// P_hat is nonzero: the periodic read equals the bounded one.
 __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
-  if (!in_grid(ky, kx, n)) return make_double2(0.0, 0.0);
   return phat[fft_pos(ky, n) * n + fft_pos(kx, n)];
 }
 
