@@ -215,13 +215,13 @@ def main():
     plain_s = (time.perf_counter() - t0) / P
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
 
-    # executed gram work: live (block pair, E chunk) triples x 16 x 64 x 64 complex MACs,
-    # three quarters of that on the diagonal blocks
+    # executed gram work: live (block pair, E chunk) triples x chunk x block^2 complex MACs
     gram_exec = 0.0
     for ci, w in enumerate(ws_list):
         steps_tab = plan.query(6, ci).reshape(-1, 5).astype(np.float64)
-        live = steps_tab[:, 3].sum() - 0.25 * steps_tab[:, 4].sum()
-        gram_exec += w.n_tiles * live * 16 * 64 * 64 * 8.0
+        sz = plan.sizes(ci)
+        gram_exec += (w.n_tiles * steps_tab[:, 3].sum() * sz["gram_chunk"] * sz["gram_block"] ** 2
+                      * 8.0)
     groups = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
                   "work_per_step": v[2] / args.steps} for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])

@@ -211,7 +211,8 @@ class Plan:
 
     def sizes(self, geom=0):
         v = self.query(5, geom)
-        return dict(zip(["n_pairs", "n_rows", "nu_max", "m_max", "ne_max", "n_active"], v.tolist()))
+        return dict(zip(["n_pairs", "n_rows", "nu_max", "m_max", "ne_max", "n_active", "gram_block",
+                         "gram_chunk"], v.tolist()))
 
     def workspace_bytes(self, descs):
         b = ctypes.c_size_t()

@@ -392,14 +392,10 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       // algorithmic flops of the gram: 8 per complex MAC over the E-sum of the
       // Hermitian lower triangle
       ProfScope ps(APIC_PROF_GRAM, T * 8.0 * d.ne * nu * (nu + 1) / 2, st);
-      const int nb = (d.nu + kGramBlock - 1) / kGramBlock;
-      hipLaunchKernelGGL(k_df_gram<true>, dim3((unsigned)(a.T * nb)), dim3(256), 0, st, a, s);
+      const int nb = (d.nu + kGramUB - 1) / kGramUB;
+      hipLaunchKernelGGL(k_df_gram, dim3((unsigned)(a.T * (nb * (nb + 1) / 2))), dim3(64), 0, st,
+                         a, s);
       APIC_LAUNCHED();
-      if (nb > 1) {
-        hipLaunchKernelGGL(k_df_gram<false>, dim3((unsigned)(a.T * (nb * (nb - 1) / 2))),
-                           dim3(256), 0, st, a, s);
-        APIC_LAUNCHED();
-      }
     }
     {
       // complex Cholesky (4/3) n^3 flops plus the two triangular solves 8 n^2
@@ -757,7 +753,7 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
       v.push_back((int32_t)(g.row_il[i] >> 16));
     }
   } else if (what == 5) {
-    v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active};
+    v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active, kGramUB, kEChunk};
   } else if (what == 6) {
     for (const DfStep &d : g.steps) {
       v.push_back(d.nu);

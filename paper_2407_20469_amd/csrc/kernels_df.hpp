@@ -158,64 +158,45 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
   return phat[fft_pos(ky, n) * n + fft_pos(kx, n)];
 }
 
-// Gram of the darkfield system in 64 x 64 blocks of the N_u x N_u Hermitian
-// matrix, lower triangle only.  Only the chunks of 16 excluded k whose
-// products can be nonzero for both blocks (plan masks) are visited, in
-// ascending order; the operands P_hat(u + k) of the next chunk are gathered
-// into registers while the current chunk is multiplied from LDS.
-//  * kDiag = false: the blocks below the diagonal (I > J); 16 x 16 threads,
-//    4 x 4 complex outputs each (rows and columns 16 apart).
-//  * kDiag = true: the diagonal blocks (I = J, one operand).  Only the three
-//    lower 32 x 32 quadrants are formed: waves 0-2 take quadrants (0,0),
-//    (1,0), (1,1) with 8 x 8 lanes of 4 x 4 outputs (8 apart); wave 3 only
-//    gathers.
+// Gram of the darkfield system in 32 x 32 blocks (I >= J) of the N_u x N_u
+// Hermitian matrix, one wavefront per block: lane (ty, tx) = (lane / 8,
+// lane % 8) holds rows ty + 8 i and columns tx + 8 j, so the lanes reading one
+// LDS row read consecutive elements (no bank conflicts).  Only the chunks of 8
+// excluded k whose products can be nonzero for both blocks (plan masks) are
+// visited, in ascending order; the operands P_hat(u + k) of the next chunk are
+// gathered into registers while the current chunk is multiplied from LDS.  A
+// diagonal block has one operand and is formed whole (its upper half is not
+// read by the Cholesky).  Small blocks and chunks follow the sparsity of the
+// E-sum closely: a product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only
+// when both u + k and u' + k fall in P.
 constexpr int kGramKC = kEChunk;
 constexpr int kGramMaxChunks = kMaxEChunks;
-template <bool kDiag>
-__global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
-  const int nb = (s.nu + kGramBlock - 1) / kGramBlock;
-  const int per_tile = kDiag ? nb : nb * (nb - 1) / 2;
+__global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
+  const int nb = (s.nu + kGramUB - 1) / kGramUB;
+  const int ntri = nb * (nb + 1) / 2;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);  // a tile's blocks on one XCD
-  const int t = bid / per_tile;
-  int rem = bid % per_tile, I, J;
-  if (kDiag) {
-    I = J = rem;
-  } else {  // strictly lower: I >= 1, J < I
-    I = 1;
-    while (rem >= I) {
-      rem -= I;
-      ++I;
-    }
-    J = rem;
+  const int t = bid / ntri;
+  int rem = bid % ntri, I = 0;
+  while (rem > I) {
+    rem -= I + 1;
+    ++I;
   }
+  const int J = rem;
+  const bool diag = I == J;
   const c64 *phat = a.at<c64>(t, a.lay.phat);
-  __shared__ c64 sA[kGramKC][kGramBlock];
-  __shared__ c64 sB[kDiag ? 1 : kGramKC][kGramBlock];
-  __shared__ uint32_t su[2][kGramBlock];
+  __shared__ c64 sA[kGramKC][kGramUB];
+  __shared__ c64 sB[kGramKC][kGramUB];
+  __shared__ uint32_t su[2][kGramUB];
   __shared__ uint16_t clist[kGramMaxChunks];
   __shared__ int ncl;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // output rows ra + rs i and columns cb + rs j of the block: lanes that read
-  // one operand row of the LDS stage read consecutive elements (no bank
-  // conflicts) and write consecutive columns of G
-  int ra, cb, rs;
-  if (kDiag) {
-    const int qr = wv == 0 ? 0 : 1, qc = wv == 2 ? 1 : 0;
-    ra = qr * 32 + (lane >> 3);
-    cb = qc * 32 + (lane & 7);
-    rs = 8;
-  } else {
-    ra = tid >> 4;
-    cb = tid & 15;
-    rs = 16;
+  const int lane = threadIdx.x;
+  const int ty = lane >> 3, tx = lane & 7;
+  if (lane < kGramUB) {
+    const int ui = I * kGramUB + lane, uj = J * kGramUB + lane;
+    su[0][lane] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: outside every support
+    su[1][lane] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
   }
-  const bool active = !kDiag || wv < 3;
-  if (tid < kGramBlock) {
-    const int ui = I * kGramBlock + tid, uj = J * kGramBlock + tid;
-    su[0][tid] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: far outside the grid
-    su[1][tid] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
-  }
-  if (tid == 0) {
+  if (lane == 0) {
     int c = 0;
     const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
     for (int w = 0; w < s.nwe; ++w) {
@@ -233,13 +214,13 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
   __syncthreads();
-  constexpr int PER = (kGramKC * kGramBlock) / 256;
+  constexpr int PER = (kGramKC * kGramUB) / 64;
   c64 pa[PER], pb[PER];
   auto gather = [&](int chunk) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
-      const int e = tid + m * 256;
-      const int kk = e / kGramBlock, uu = e % kGramBlock;
+      const int e = lane + m * 64;
+      const int kk = e / kGramUB, uu = e % kGramUB;
       const int k = chunk * kGramKC + kk;
       pa[m] = make_double2(0.0, 0.0);
       pb[m] = make_double2(0.0, 0.0);
@@ -248,7 +229,9 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
         const int ky = kunpack_y(kw), kx = kunpack_x(kw);
         const uint32_t wa = su[0][uu], wb = su[1][uu];
         if (wa != 0x7fff7fffu) pa[m] = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
-        if (!kDiag && wb != 0x7fff7fffu)
+        if (diag)
+          pb[m] = pa[m];
+        else if (wb != 0x7fff7fffu)
           pb[m] = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
       }
     }
@@ -258,33 +241,29 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   for (int ci = 0; ci < n_chunks; ++ci) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
-      const int e = tid + m * 256;
-      sA[e / kGramBlock][e % kGramBlock] = pa[m];
-      if (!kDiag) sB[e / kGramBlock][e % kGramBlock] = pb[m];
+      const int e = lane + m * 64;
+      sA[e / kGramUB][e % kGramUB] = pa[m];
+      sB[e / kGramUB][e % kGramUB] = pb[m];
     }
     __syncthreads();
     if (ci + 1 < n_chunks) gather(clist[ci + 1]);
-    if (active) {
-      const c64 *cols = kDiag ? &sA[0][0] : &sB[0][0];  // one operand on the diagonal
 #pragma unroll 4
-      for (int kk = 0; kk < kGramKC; ++kk) {
-        c64 av[4], bv[4];
+    for (int kk = 0; kk < kGramKC; ++kk) {
+      c64 av[4], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = sA[kk][ra + rs * i];
+      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty + 8 * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = cols[kk * kGramBlock + cb + rs * j];
+      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx + 8 * j];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
-            acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
-            acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
-          }
-      }
+        for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
+          acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
+          acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
+        }
     }
     __syncthreads();
   }
-  if (!active) return;
   // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4
   const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
   const c64 *fpp = a.at<c64>(t, a.lay.fpp);
@@ -292,15 +271,15 @@ __global__ __launch_bounds__(256) void k_df_gram(ClassArgs a, StepArgs s) {
   const int ld = a.nu_pad;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = I * kGramBlock + ra + rs * i;
+    const int r = I * kGramUB + ty + 8 * i;
     if (r >= s.nu) continue;
-    const uint32_t wr = su[0][ra + rs * i];
+    const uint32_t wr = su[0][ty + 8 * i];
     const int ry = kunpack_y(wr), rx = kunpack_x(wr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = J * kGramBlock + cb + rs * j;
+      const int c = J * kGramUB + tx + 8 * j;
       if (c >= s.nu) continue;
-      const uint32_t wc = su[1][cb + rs * j];
+      const uint32_t wc = su[1][tx + 8 * j];
       const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
       const c64 tv = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
       G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,

@@ -164,7 +164,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
         }
       }
     // unknowns in 8 x 8 squares (raster inside and across squares): a block of
-    // 64 unknowns is spatially compact, so fewer E chunks meet it
+    // 32 unknowns (half a square) is spatially compact, so fewer E chunks meet it
     {
       std::vector<int> ord(U.size());
       for (size_t i = 0; i < ord.size(); ++i) ord[i] = int(i);
@@ -207,7 +207,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
         (mex[o] ? E : Q).push_back(pack_k(ky, kx));
       }
     if (int64_t(Q.size() + E.size()) != n_pu) return APIC_EUNSUPPORTED;  // would wrap
-    // excluded k in 4 x 4 squares: a chunk of 16 is spatially compact
+    // excluded k in 4 x 4 squares: a chunk of 8 (half a square) is spatially compact
     std::stable_sort(E.begin(), E.end(), [&](uint32_t a, uint32_t b) {
       return square_key({unpack_ky(a), unpack_kx(a)}, 4) <
              square_key({unpack_ky(b), unpack_kx(b)}, 4);
@@ -222,14 +222,14 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     // block-sparsity masks: dilate P by each block of unknowns
     {
       std::vector<uint8_t> live(size_t(W) * W);
-      const int nub = (st.nu + 63) / 64;
+      const int nub = (st.nu + kGramUB - 1) / kGramUB;
       const int nec = (st.ne + kEChunk - 1) / kEChunk;
       st.nwe = (nec + 63) / 64;
       st.off_gmask = int64_t(p.masks.size());
       p.masks.resize(p.masks.size() + size_t(nub) * st.nwe, 0);
       for (int b = 0; b < nub; ++b) {
         std::fill(live.begin(), live.end(), 0);
-        for (int ui = b * 64; ui < std::min(st.nu, b * 64 + 64); ++ui)
+        for (int ui = b * kGramUB; ui < std::min(st.nu, (b + 1) * kGramUB); ++ui)
           for (auto &q : Pc)  // k with u + k in P: k = q - u
             live[size_t(q.first - Uc[ui].first + n) * W + (q.second - Uc[ui].second + n)] = 1;
         auto is_live = [&](uint32_t w) {

@@ -18,8 +18,9 @@ constexpr int kNumJ = 12;           // Noll 4..15 carried by the pupil solve
 constexpr int kNumFeat = 32;        // 8 pair-angle bins x 4 radial bands
 constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cells
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
-constexpr int kGramBlock = 64;      // gram / Cholesky padding granularity
-constexpr int kEChunk = 16;         // E rows per gram k-chunk
+constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
+constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
+constexpr int kEChunk = 8;          // E rows per gram k-chunk
 constexpr int kMaxEChunks = 4096;   // gram chunk list capacity (65536 rows of E)
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
@@ -35,11 +36,11 @@ struct DfStep {
   int32_t kx = 0, ky = 0;
   int32_t nu = 0, np = 0, m = 0, ne = 0;
   int64_t off_u = 0, off_p = 0, off_q = 0, off_e = 0;  // into GeomPlan::coords
-  // Block-sparsity masks (into GeomPlan::masks): for each block of 64
+  // Block-sparsity masks (into GeomPlan::masks): for each block of kGramUB
   // unknowns, one bit per chunk of kEChunk rows of E that holds a k with
   // u + k in P for some u of the block.  Then the membership bitmap of Q over
   // the N x N grid (FFT order, bit y N + x).
-  int32_t nwe = 0;                   // 64-bit words per block
+  int32_t nwe = 0;                   // 64-bit words per block of kGramUB unknowns
   int64_t off_gmask = 0, off_qbits = 0;
   int64_t gram_live = 0;             // live (I >= J block pair, E chunk) triples
   int64_t gram_live_diag = 0;        // the I = J part of gram_live
