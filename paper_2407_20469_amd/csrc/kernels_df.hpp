@@ -166,11 +166,11 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
 // visited, in ascending order; the operands P_hat(u + k) of the next chunk are
 // gathered into registers while the current chunk is multiplied from LDS.  A
 // diagonal block has one operand and is formed whole (its upper half is not
-// read by the Cholesky).  Small blocks and chunks follow the sparsity of the
+// read by the Cholesky).  The mask words are walked in order with
+// wave-uniform state, so the chunk list needs no LDS.  Small blocks and chunks follow the sparsity of the
 // E-sum closely: a product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only
 // when both u + k and u' + k fall in P.
 constexpr int kGramKC = kEChunk;
-constexpr int kGramMaxChunks = kMaxEChunks;
 __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramUB - 1) / kGramUB;
   const int ntri = nb * (nb + 1) / 2;
@@ -187,8 +187,6 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   __shared__ c64 sA[kGramKC][kGramUB];
   __shared__ c64 sB[kGramKC][kGramUB];
   __shared__ uint32_t su[2][kGramUB];
-  __shared__ uint16_t clist[kGramMaxChunks];
-  __shared__ int ncl;
   const int lane = threadIdx.x;
   const int ty = lane >> 3, tx = lane & 7;
   if (lane < kGramUB) {
@@ -196,18 +194,19 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     su[0][lane] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: outside every support
     su[1][lane] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
   }
-  if (lane == 0) {
-    int c = 0;
-    const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
-    for (int w = 0; w < s.nwe; ++w) {
-      uint64_t bits = mi[w] & mj[w];
-      while (bits && c < kGramMaxChunks) {
-        clist[c++] = (uint16_t)(w * 64 + __builtin_ctzll(bits));
-        bits &= bits - 1;
-      }
+  // live chunks in ascending order, walked with wave-uniform state
+  const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
+  int mw = 0;
+  uint64_t bits = s.nwe > 0 ? (mi[0] & mj[0]) : 0;
+  auto next_chunk = [&]() -> int {
+    while (bits == 0) {
+      if (++mw >= s.nwe) return -1;
+      bits = mi[mw] & mj[mw];
     }
-    ncl = c;
-  }
+    const int c = mw * 64 + __builtin_ctzll(bits);
+    bits &= bits - 1;
+    return c;
+  };
   c64 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -236,9 +235,9 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
       }
     }
   };
-  const int n_chunks = ncl;
-  if (n_chunks > 0) gather(clist[0]);
-  for (int ci = 0; ci < n_chunks; ++ci) {
+  int cur = next_chunk();
+  if (cur >= 0) gather(cur);
+  while (cur >= 0) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
       const int e = lane + m * 64;
@@ -246,7 +245,8 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
       sB[e / kGramUB][e % kGramUB] = pb[m];
     }
     __syncthreads();
-    if (ci + 1 < n_chunks) gather(clist[ci + 1]);
+    const int nxt = next_chunk();
+    if (nxt >= 0) gather(nxt);
 #pragma unroll 4
     for (int kk = 0; kk < kGramKC; ++kk) {
       c64 av[4], bv[4];
@@ -263,6 +263,7 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
         }
     }
     __syncthreads();
+    cur = nxt;
   }
   // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4
   const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
