@@ -161,15 +161,16 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
 // Gram of the darkfield system in 32 x 32 blocks (I >= J) of the N_u x N_u
 // Hermitian matrix, one wavefront per block: lane (ty, tx) = (lane / 8,
 // lane % 8) holds rows ty + 8 i and columns tx + 8 j, so the lanes reading one
-// LDS row read consecutive elements (no bank conflicts).  Only the chunks of 8
-// excluded k whose products can be nonzero for both blocks (plan masks) are
-// visited, in ascending order; the operands P_hat(u + k) of the next chunk are
-// gathered into registers while the current chunk is multiplied from LDS.  A
-// diagonal block has one operand and is formed whole (its upper half is not
-// read by the Cholesky).  The mask words are walked in order with
-// wave-uniform state, so the chunk list needs no LDS.  Small blocks and chunks follow the sparsity of the
-// E-sum closely: a product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only
-// when both u + k and u' + k fall in P.
+// LDS row read consecutive elements (no bank conflicts).
+//
+// A product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only when both u + k
+// and u' + k fall in P, so the E-sum is sparse.  Small blocks and chunks of
+// kEChunk (2) excluded k follow that sparsity: only the chunks whose products
+// can be nonzero for both blocks (plan masks) are visited, in ascending order,
+// walking the mask words with wave-uniform state.  The operands of the next
+// chunk are gathered into registers while the current chunk is multiplied
+// from LDS.  A diagonal block has one operand and is formed whole (its upper
+// half is not read by the Cholesky).
 constexpr int kGramKC = kEChunk;
 __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramUB - 1) / kGramUB;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
   __syncthreads();
-  constexpr int PER = (kGramKC * kGramUB) / 64;
+  constexpr int NEL = kGramKC * kGramUB, PER = (NEL + 63) / 64;
   c64 pa[PER], pb[PER];
   auto gather = [&](int chunk) {
 #pragma unroll
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
       const int k = chunk * kGramKC + kk;
       pa[m] = make_double2(0.0, 0.0);
       pb[m] = make_double2(0.0, 0.0);
-      if (k < s.ne) {
+      if ((NEL % 64 == 0 || e < NEL) && k < s.ne) {
         const uint32_t kw = s.e[k];
         const int ky = kunpack_y(kw), kx = kunpack_x(kw);
         const uint32_t wa = su[0][uu], wb = su[1][uu];
@@ -241,8 +242,10 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
       const int e = lane + m * 64;
-      sA[e / kGramUB][e % kGramUB] = pa[m];
-      sB[e / kGramUB][e % kGramUB] = pb[m];
+      if (NEL % 64 == 0 || e < NEL) {
+        sA[e / kGramUB][e % kGramUB] = pa[m];
+        sB[e / kGramUB][e % kGramUB] = pb[m];
+      }
     }
     __syncthreads();
     const int nxt = next_chunk();

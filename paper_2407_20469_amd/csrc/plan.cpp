@@ -207,14 +207,13 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
         (mex[o] ? E : Q).push_back(pack_k(ky, kx));
       }
     if (int64_t(Q.size() + E.size()) != n_pu) return APIC_EUNSUPPORTED;  // would wrap
-    // excluded k in 4 x 4 squares: a chunk of 8 (half a square) is spatially compact
+    // excluded k in 2 x 2 squares: a chunk of 2 (half a square) is spatially compact
     std::stable_sort(E.begin(), E.end(), [&](uint32_t a, uint32_t b) {
-      return square_key({unpack_ky(a), unpack_kx(a)}, 4) <
-             square_key({unpack_ky(b), unpack_kx(b)}, 4);
+      return square_key({unpack_ky(a), unpack_kx(a)}, 2) <
+             square_key({unpack_ky(b), unpack_kx(b)}, 2);
     });
     st.m = int(Q.size());
     st.ne = int(E.size());
-    if ((st.ne + kEChunk - 1) / kEChunk > kMaxEChunks) return APIC_EUNSUPPORTED;
     st.off_q = int64_t(p.coords.size());
     p.coords.insert(p.coords.end(), Q.begin(), Q.end());
     st.off_e = int64_t(p.coords.size());

@@ -20,8 +20,7 @@ constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cell
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
 constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
-constexpr int kEChunk = 8;          // E rows per gram k-chunk
-constexpr int kMaxEChunks = 4096;   // gram chunk list capacity (65536 rows of E)
+constexpr int kEChunk = 2;          // E rows per gram k-chunk
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
 // Signed (ky, kx) packed in one word: low half ky, high half kx (int16 each).
