@@ -163,14 +163,51 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
           Uc.emplace_back(ky, kx);
         }
       }
-    // unknowns in 8 x 8 squares (raster inside and across squares): a block of
-    // 32 unknowns (half a square) is spatially compact, so fewer E chunks meet it
+    // Unknowns in bands of equal distance to P, each band ordered by angle
+    // around the support's centre (alternating direction from band to band).
+    // A product of the gram's E-sum is nonzero only if u + k lands in P, i.e.
+    // for unknowns near P; blocks of kGramUB unknowns that are thin across the
+    // P border and long along it therefore meet few E chunks.  Distances come
+    // from a two-pass chamfer transform (steps 1 and sqrt 2) on the grid.
     {
+      std::vector<float> dist(size_t(nn), 1e30f);
+      auto at = [&](int ky, int kx) -> float & { return dist[size_t(ky + n / 2) * n + (kx + n / 2)]; };
+      for (auto &q : Pc) at(q.first, q.second) = 0.f;
+      const float d1 = 1.f, d2 = 1.41421356f;
+      for (int y = -n / 2; y < n / 2; ++y)
+        for (int x = -n / 2; x < n / 2; ++x) {
+          float &v = at(y, x);
+          if (x > -n / 2) v = std::min(v, at(y, x - 1) + d1);
+          if (y > -n / 2) {
+            v = std::min(v, at(y - 1, x) + d1);
+            if (x > -n / 2) v = std::min(v, at(y - 1, x - 1) + d2);
+            if (x < n / 2 - 1) v = std::min(v, at(y - 1, x + 1) + d2);
+          }
+        }
+      for (int y = n / 2 - 1; y >= -n / 2; --y)
+        for (int x = n / 2 - 1; x >= -n / 2; --x) {
+          float &v = at(y, x);
+          if (x < n / 2 - 1) v = std::min(v, at(y, x + 1) + d1);
+          if (y < n / 2 - 1) {
+            v = std::min(v, at(y + 1, x) + d1);
+            if (x < n / 2 - 1) v = std::min(v, at(y + 1, x + 1) + d2);
+            if (x > -n / 2) v = std::min(v, at(y + 1, x - 1) + d2);
+          }
+        }
+      // angle measured from the direction -k_j (away from the known centre), so
+      // the unknown crescent does not straddle the +-pi cut
+      const double kn = std::max(1e-9, std::sqrt(double(st.kx) * st.kx + double(st.ky) * st.ky));
+      const double dx = -st.kx / kn, dy = -st.ky / kn;
+      std::vector<std::pair<int, double>> key(U.size());
+      for (size_t i = 0; i < U.size(); ++i) {
+        const double ry = Uc[i].first + st.ky, rx = Uc[i].second + st.kx;  // from the centre -k_j
+        const double ang = std::atan2(dx * ry - dy * rx, dx * rx + dy * ry);
+        const int band = int(at(Uc[i].first, Uc[i].second) / 4.f);
+        key[i] = {band, (band & 1) ? -ang : ang};
+      }
       std::vector<int> ord(U.size());
       for (size_t i = 0; i < ord.size(); ++i) ord[i] = int(i);
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-        return square_key(Uc[a], 8) < square_key(Uc[b], 8);
-      });
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b]; });
       std::vector<uint32_t> U2(U.size());
       std::vector<std::pair<int, int>> Uc2(U.size());
       for (size_t i = 0; i < ord.size(); ++i) {
