@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["cfg1", "cfg2"], default="cfg1")
     ap.add_argument("--tiles", type=int, default=None)
-    ap.add_argument("--ws-gb", type=float, default=64.0)
+    ap.add_argument("--ws-gb", type=float, default=128.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--graph", dest="graph", action="store_true", default=None)
     ap.add_argument("--no-graph", dest="graph", action="store_false")

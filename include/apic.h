@@ -243,7 +243,8 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
 apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles);
 /* Autotuner.  For each class, times the method on its first k tiles for
  * k = 1, 2, 4, ... up to the class size, as long as k tiles' workspace fits
- * `workspace_bytes` (and stops after a run longer than 2 s), then sets the
+ * `workspace_bytes` (and stops once doubling k gains under 3% past k = 4, or
+ * after a run longer than 10 s), then sets the
  * class's chunk to the smallest k whose time per tile is within (1 + slack)
  * of the best; if the classes' chunk blocks together exceed `workspace_bytes`
  * (they run concurrently), the largest blocks are halved until they fit.

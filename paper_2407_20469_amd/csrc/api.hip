@@ -1238,12 +1238,14 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
           rc = APIC_EHIP;
       }
       const double tile_ms = (double)ms / k;
+      const double prev = per_tile.empty() ? 1e300 : per_tile.back();
       per_tile.push_back(tile_ms);
       if (tile_ms < best) {
         best = tile_ms;
         pick = k;
       }
-      if (ms > 2000.f) break;  // longer runs add little to the choice
+      // stop once doubling the chunk gains under 3% (past 4 tiles), or after 10 s
+      if ((k >= 4 && tile_ms > 0.97 * prev) || ms > 10000.f) break;
     }
     if (rc != APIC_OK) break;
     if (per_tile.empty()) {
