@@ -200,29 +200,32 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
 // operands given by loader callbacks.  16 x 16 threads, 4 x 4 outputs each,
 // 16 apart, so that the lanes reading one LDS row read consecutive elements
 // (no bank conflicts) and write consecutive columns.  The loaders run
-// along p (16 consecutive elements of a row per 16 lanes, one K chunk ahead
+// along p (kCK consecutive elements of a row per kCK lanes, one K chunk ahead
 // in registers); the LDS rows are padded by one element so that the
 // transposing store does not serialise on one bank group.
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm_nc(c64 (&acc)[4][4], int K, LA la, LB lb,
                                              c64 (&sA)[kCK][kCB + 1], c64 (&sB)[kCK][kCB + 1]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int lk = tid & (kCK - 1), lr = tid / kCK;  // loader: element lk of rows lr + 16 m
-  c64 pa[kCB / 16], pb[kCB / 16];
+  // loader: element lk of rows lr + RS m (RS rows per pass, kCB / RS passes)
+  constexpr int RS = 256 / kCK, NP = kCB / RS;
+  static_assert(RS * kCK == 256 && NP * RS == kCB, "loader covers the tile exactly");
+  const int lk = tid % kCK, lr = tid / kCK;
+  c64 pa[NP], pb[NP];
   auto fetch = [&](int k0) {
     const bool ok = k0 + lk < K;
 #pragma unroll
-    for (int m = 0; m < kCB / 16; ++m) {
-      pa[m] = ok ? la(lr + 16 * m, k0 + lk) : make_double2(0.0, 0.0);
-      pb[m] = ok ? lb(lr + 16 * m, k0 + lk) : make_double2(0.0, 0.0);
+    for (int m = 0; m < NP; ++m) {
+      pa[m] = ok ? la(lr + RS * m, k0 + lk) : make_double2(0.0, 0.0);
+      pb[m] = ok ? lb(lr + RS * m, k0 + lk) : make_double2(0.0, 0.0);
     }
   };
   fetch(0);
   for (int k0 = 0; k0 < K; k0 += kCK) {
 #pragma unroll
-    for (int m = 0; m < kCB / 16; ++m) {
-      sA[lk][lr + 16 * m] = pa[m];
-      sB[lk][lr + 16 * m] = pb[m];
+    for (int m = 0; m < NP; ++m) {
+      sA[lk][lr + RS * m] = pa[m];
+      sB[lk][lr + RS * m] = pb[m];
     }
     __syncthreads();
     if (k0 + kCK < K) fetch(k0 + kCK);
