@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
   c64 *G = a.at<c64>(t, a.lay.gram);
   __shared__ c64 D[kCB][kCB + 1];
   __shared__ c64 col[2][kCB];
-  __shared__ double piv[kCB], mdiag[kCB];
+  __shared__ double piv[kCB], mdiag[kCB], pinv[2];
   __shared__ double red[256];
   __shared__ int fail;
   if (tid == 0) fail = 0;
@@ -98,29 +98,46 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
   for (int q = 0; q < bs; ++q) {
     c64 *cq = col[q & 1];
     if ((q & 3) == s4 && r >= q && r < bs) {
-      const int jq = q >> 2;
-      c64 x = v[0];
-#pragma unroll
-      for (int j = 1; j < kCB / 4; ++j)
-        if (j == jq) x = v[j];
+      // v[q / 4] with a wave-uniform index: a scalar branch, not a select chain
+      c64 x;
+      switch (q >> 2) {
+#define APIC_POTRF_CASE(j) \
+  case j:                  \
+    x = v[j];              \
+    break;
+        APIC_POTRF_CASE(0) APIC_POTRF_CASE(1) APIC_POTRF_CASE(2) APIC_POTRF_CASE(3)
+        APIC_POTRF_CASE(4) APIC_POTRF_CASE(5) APIC_POTRF_CASE(6) APIC_POTRF_CASE(7)
+        APIC_POTRF_CASE(8) APIC_POTRF_CASE(9) APIC_POTRF_CASE(10) APIC_POTRF_CASE(11)
+        APIC_POTRF_CASE(12) APIC_POTRF_CASE(13) APIC_POTRF_CASE(14)
+        default:
+          x = v[15];
+#undef APIC_POTRF_CASE
+      }
       cq[r] = x;
+      if (r == q) {  // the pivot's reciprocal, once for everyone
+        const double d = x.x;
+        piv[q] = d;
+        pinv[q & 1] = d > 0.0 ? 1.0 / d : 1e300;  // a failed pivot is flagged below
+      }
     }
     __syncthreads();
-    double d = cq[q].x;
-    if (tid == 0) piv[q] = d;
-    if (!(d > 0.0)) d = 1e-300;  // flagged below
-    const double inv = 1.0 / d;
+    const double inv = pinv[q & 1];
     if (r > q && r < bs) {
-      // all column values first (one LDS wait), then branch-free updates
+      // the column values first (one LDS wait), then branch-free updates; the
+      // groups of four columns entirely at or left of q are skipped (q is
+      // uniform, so the test is a scalar branch)
       c64 cv[kCB / 4];
 #pragma unroll
-      for (int j = 0; j < kCB / 4; ++j) cv[j] = cq[s4 + 4 * j];
+      for (int j = 0; j < kCB / 4; ++j)
+        if (4 * j + 3 > q) cv[j] = cq[s4 + 4 * j];
       const c64 dr = cscale(cq[r], inv);
 #pragma unroll
       for (int j = 0; j < kCB / 4; ++j) {
-        const int cc = s4 + 4 * j;
-        const c64 nv = csub(v[j], cmulc(dr, cv[j]));
-        if (cc > q && cc <= r) v[j] = nv;
+        if (4 * j + 3 > q) {
+          const int cc = s4 + 4 * j;
+          const c64 nv = csub(v[j], cmulc(dr, cv[j]));
+          if (cc > q && cc <= r) v[j] = nv;
+        }
       }
     }
   }
