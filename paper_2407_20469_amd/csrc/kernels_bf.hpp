@@ -149,10 +149,12 @@ __global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float 
   __shared__ float s_beta[256], s_w[256];
   __shared__ int s_cell[256];
   const int tid = threadIdx.x;
-  // entry owned by this thread
+  // entry owned by this thread: two threads per entry (ent = tid % 128), one
+  // for each half of a batch of 256 rows, so all four wavefronts accumulate
+  const int ent = tid & 127, half = tid >> 7;
   int p = 0, q = 0;
-  if (tid < 78) {  // upper-triangle index -> (p, q), p <= q
-    int rem = tid;
+  if (ent < 78) {  // upper-triangle index -> (p, q), p <= q
+    int rem = ent;
     p = 0;
     while (rem >= 12 - p) {
       rem -= 12 - p;
@@ -210,23 +212,43 @@ __global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float 
     s_w[tid] = w;
     s_cell[tid] = cell;
     __syncthreads();
-    if (tid < 78) {
-      for (int r = 0; r < 256; ++r) acc += (double)(s_wa[r][p] * s_a[r][q]);
-    } else if (tid < 90) {
-      const int pp = tid - 78;
-      for (int r = 0; r < 256; ++r) acc += (double)(s_wa[r][pp] * s_beta[r]);
-    } else if (tid == 90) {
-      for (int r = 0; r < 256; ++r) acc += (double)(s_w[r] * s_beta[r] * s_beta[r]);
-    } else if (tid == 91) {
-      for (int r = 0; r < 256; ++r) acc += (double)s_w[r];
-    } else if (tid < kAbEntries) {
-      const int cc = tid - 92;
-      for (int r = 0; r < 256; ++r) acc += (s_cell[r] == cc) ? (double)s_w[r] : 0.0;
+    // rows [128 half, 128 half + 128) of the batch, four independent partial
+    // sums (rows r .. r + 3) so the FP64 adds do not form one long chain
+    double ac[4] = {0.0, 0.0, 0.0, 0.0};
+    const int r0 = half * 128, r1 = r0 + 128;
+    if (ent < 78) {
+      for (int r = r0; r < r1; r += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ac[u] += (double)(s_wa[r + u][p] * s_a[r + u][q]);
+    } else if (ent < 90) {
+      const int pp = ent - 78;
+      for (int r = r0; r < r1; r += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ac[u] += (double)(s_wa[r + u][pp] * s_beta[r + u]);
+    } else if (ent == 90) {
+      for (int r = r0; r < r1; r += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          ac[u] += (double)(s_w[r + u] * s_beta[r + u] * s_beta[r + u]);
+    } else if (ent == 91) {
+      for (int r = r0; r < r1; r += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ac[u] += (double)s_w[r + u];
+    } else if (ent < kAbEntries) {
+      const int cc = ent - 92;
+      for (int r = r0; r < r1; r += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ac[u] += (s_cell[r + u] == cc) ? (double)s_w[r + u] : 0.0;
     }
+    acc += (ac[0] + ac[1]) + (ac[2] + ac[3]);
     __syncthreads();
   }
-  if (tid < kAbEntries)
-    a.at<double>(t, a.lay.part)[(int64_t)chunk * kAbEntries + tid] = acc;
+  // the two halves of each entry, combined in a fixed order
+  __shared__ double s_half[128];
+  if (half == 1) s_half[ent] = acc;
+  __syncthreads();
+  if (half == 0 && ent < kAbEntries)
+    a.at<double>(t, a.lay.part)[(int64_t)chunk * kAbEntries + ent] = acc + s_half[ent];
 }
 
 // Sum the chunk partials of each tile in a fixed order (deterministic).
