@@ -147,9 +147,10 @@ def main():
                                  slack=0.0)
         del buf
         tune = [{"geom": c["geom"], "tiles": c["n_tiles"], "chunk": c["chunk"],
-                 "ms_per_tile": float(m)} for c, m in zip(batch.classes(), ms_tile)]
-        log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk) "
-            f"{[(c['geom'], c['tiles'], c['chunk']) for c in tune]}")
+                 "lanes": c["lanes"], "ms_per_tile": float(m)}
+                for c, m in zip(batch.classes(), ms_tile)]
+        log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk, lanes) "
+            f"{[(c['geom'], c['tiles'], c['chunk'], c['lanes']) for c in tune]}")
     elif batch.workspace_bytes > budget:
         for i, c in enumerate(batch.classes()):
             batch.set_chunk(i, max(1, budget // (len(ws_list) * c["tile_bytes"])))

@@ -234,19 +234,25 @@ apic_status apic_batch_launch(apic_batch *batch, void *stream);
 /* Classes of a batch, in the order the batch runs them: on entry *n_classes
  * is the capacity of the (nullable) arrays, on return the class count; per
  * class its geometry index, tile count, current chunk (tiles per launch
- * sequence) and workspace bytes per tile. */
+ * sequence), lanes and workspace bytes per tile. */
 apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int32_t *geom,
-                               int32_t *n_tiles, int32_t *chunk, int64_t *tile_bytes);
-/* Run class `cls` in chunks of `tiles` tiles (<= 0: the whole class at once),
- * one after another on its stream, reusing one chunk's workspace.  Changes
- * apic_batch_workspace_bytes and drops a captured graph. */
-apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles);
+                               int32_t *n_tiles, int32_t *chunk, int32_t *lanes,
+                               int64_t *tile_bytes);
+/* Run class `cls` in chunks of `tiles` tiles (<= 0: the whole class at once)
+ * on `lanes` (1 or 2) streams: with one lane the chunks run one after another
+ * reusing one chunk's workspace; with two they alternate between the class's
+ * stream and a second default-priority stream, each with its own chunk
+ * workspace, so one chunk's latency-bound kernels (the diagonal Cholesky
+ * factors) overlap the other's.  Changes apic_batch_workspace_bytes and drops
+ * a captured graph. */
+apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, int32_t lanes);
 /* Autotuner.  For each class, times the method on its first k tiles for
  * k = 1, 2, 4, ... up to the class size, as long as k tiles' workspace fits
  * `workspace_bytes` (and stops once doubling k gains under 3% past k = 4, or
  * after a run longer than 10 s), then sets the
  * class's chunk to the smallest k whose time per tile is within (1 + slack)
- * of the best; if the classes' chunk blocks together exceed `workspace_bytes`
+ * of the best, then tries two lanes of half that chunk over the same tiles
+ * (same workspace) and keeps them if 2% faster; if the classes' chunk blocks together exceed `workspace_bytes`
  * (they run concurrently), the largest blocks are halved until they fit.
  * Synchronises the host with `stream` after every run (not
  * capturable); writes outputs and status of the timed tiles.  `ms_per_tile`

@@ -123,8 +123,8 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_reconstruct.argtypes = [P, P, P, P, P, P, P, sz, P]
     lib.apic_batch_capture.argtypes = [P, P, P, P, P, P, P, sz, P]
     lib.apic_batch_launch.argtypes = [P, P]
-    lib.apic_batch_classes.argtypes = [P, ctypes.POINTER(i32), P, P, P, P]
-    lib.apic_batch_set_chunk.argtypes = [P, i32, i32]
+    lib.apic_batch_classes.argtypes = [P, ctypes.POINTER(i32), P, P, P, P, P]
+    lib.apic_batch_set_chunk.argtypes = [P, i32, i32, i32]
     lib.apic_batch_autotune.argtypes = [P, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
@@ -299,22 +299,23 @@ class Batch:
         self.workspace_bytes = b.value
 
     def classes(self):
-        """[{geom, n_tiles, chunk, tile_bytes}] in the order the batch runs them."""
+        """[{geom, n_tiles, chunk, lanes, tile_bytes}] in the order the batch runs them."""
         n = ctypes.c_int32(0)
         _check("apic_batch_classes", self.lib.apic_batch_classes(self.handle, ctypes.byref(n),
-                                                                 None, None, None, None))
+                                                                 None, None, None, None, None))
         cap = n.value
-        g, t, c = (np.zeros(max(cap, 1), np.int32) for _ in range(3))
+        g, t, c, ln = (np.zeros(max(cap, 1), np.int32) for _ in range(4))
         b = np.zeros(max(cap, 1), np.int64)
         _check("apic_batch_classes", self.lib.apic_batch_classes(
             self.handle, ctypes.byref(n), g.ctypes.data_as(ctypes.c_void_p),
             t.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
-            b.ctypes.data_as(ctypes.c_void_p)))
-        return [{"geom": int(g[i]), "n_tiles": int(t[i]), "chunk": int(c[i]),
+            ln.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p)))
+        return [{"geom": int(g[i]), "n_tiles": int(t[i]), "chunk": int(c[i]), "lanes": int(ln[i]),
                  "tile_bytes": int(b[i])} for i in range(cap)]
 
-    def set_chunk(self, cls, tiles):
-        _check("apic_batch_set_chunk", self.lib.apic_batch_set_chunk(self.handle, cls, tiles))
+    def set_chunk(self, cls, tiles, lanes=1):
+        _check("apic_batch_set_chunk", self.lib.apic_batch_set_chunk(self.handle, cls, tiles,
+                                                                     lanes))
         self._refresh()
         self._bound = None
 

@@ -628,7 +628,10 @@ struct apic_batch {
   int32_t n_tiles = 0;
   std::vector<apic::ClassRun> runs;
   std::vector<int32_t> chunk;    // tiles per launch sequence, per class
-  std::vector<int64_t> cls_ws;   // workspace offset of each class's chunk block
+  std::vector<int32_t> lanes;    // chunks of a class in flight at once (1 or 2)
+  std::vector<int64_t> cls_ws;   // workspace offset of each class's chunk blocks
+  std::vector<hipStream_t> lane_stream;         // a class's second lane
+  std::vector<hipEvent_t> lane_fork, lane_join;
   int64_t ws_bytes = 0;
   void *d_desc = nullptr;
   std::vector<hipStream_t> side;
@@ -989,14 +992,15 @@ apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
 
 static bool batch_ok(const apic_batch *b) { return b && b->magic == 0x42415443u && b->plan; }
 
-// Workspace of a batch: one block of chunk x stride bytes per class (classes
-// run concurrently, chunks of a class one after another).
+// Workspace of a batch: one block of lanes x chunk x stride bytes per class
+// (classes run concurrently; a class's chunks alternate between its lanes,
+// each lane with its own chunk block).
 static void batch_layout(apic_batch *b) {
   int64_t o = 0;
   b->cls_ws.assign(b->runs.size(), 0);
   for (size_t c = 0; c < b->runs.size(); ++c) {
     b->cls_ws[c] = o;
-    o = align256(o + (int64_t)std::max(1, b->chunk[c]) *
+    o = align256(o + (int64_t)std::max(1, b->chunk[c]) * b->lanes[c] *
                          b->plan->geoms[b->runs[c].geom].lay.stride);
   }
   b->ws_bytes = std::max<int64_t>(o, 256);
@@ -1018,10 +1022,28 @@ static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count
   ClassArgs a = make_args(b->plan, r, images, ws, status, reinterpret_cast<const char *>(b->d_desc));
   a.ws = ws + b->cls_ws[c];
   const int step = std::max(1, b->chunk[c]);  // chunks are >= 1 by construction
-  for (int c0 = first; c0 < first + count; c0 += step) {
-    const apic_status rc =
-        run_class(b->plan, r, chunk_args(a, c0, std::min(step, first + count - c0)), mask, io, st);
+  // with two lanes, chunk i runs on lane i % 2 in that lane's workspace block:
+  // one chunk's latency-bound kernels overlap the other's throughput-bound ones
+  const bool two = b->lanes[c] == 2 && count > step;
+  const int64_t lane_bytes = (int64_t)step * b->plan->geoms[r.geom].lay.stride;
+  if (two) {
+    APIC_HIP(hipEventRecord(b->lane_fork[c], st));
+    APIC_HIP(hipStreamWaitEvent(b->lane_stream[c], b->lane_fork[c], 0));
+  }
+  int i = 0;
+  for (int c0 = first; c0 < first + count; c0 += step, ++i) {
+    ClassArgs ac = chunk_args(a, c0, std::min(step, first + count - c0));
+    hipStream_t sc = st;
+    if (two && (i & 1)) {
+      ac.ws += lane_bytes;
+      sc = b->lane_stream[c];
+    }
+    const apic_status rc = run_class(b->plan, r, ac, mask, io, sc);
     if (rc) return rc;
+  }
+  if (two) {
+    APIC_HIP(hipEventRecord(b->lane_join[c], b->lane_stream[c]));
+    APIC_HIP(hipStreamWaitEvent(st, b->lane_join[c], 0));
   }
   return APIC_OK;
 }
@@ -1029,6 +1051,9 @@ static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count
 static void batch_free(apic_batch *b) {
   batch_drop_graph(b);
   for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+  for (hipStream_t s : b->lane_stream) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->lane_fork) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->lane_join) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->d_desc) (void)hipFree(b->d_desc);
@@ -1047,7 +1072,10 @@ apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_
   b->n_tiles = n_tiles;
   int64_t plain_bytes = 0;
   apic_status rc = layout_call(plan, n_tiles, tiles, b->runs, plain_bytes);
-  for (const ClassRun &r : b->runs) b->chunk.push_back((int32_t)r.gidx.size());
+  for (const ClassRun &r : b->runs) {
+    b->chunk.push_back((int32_t)r.gidx.size());
+    b->lanes.push_back(1);
+  }
   batch_layout(b);
   if (rc == APIC_OK) rc = apic_plan_upload(plan);
   if (rc == APIC_OK) rc = ensure_twiddles();
@@ -1076,6 +1104,16 @@ apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_
     if (ok) b->side.push_back(s);
     ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     if (ok) b->join.push_back(e);
+  }
+  for (size_t c = 0; ok && c < b->runs.size(); ++c) {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) b->lane_stream.push_back(s);
+    ok = ok && hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->lane_fork.push_back(e0);
+    ok = ok && hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->lane_join.push_back(e1);
   }
   if (!ok) {
     batch_free(b);
@@ -1159,7 +1197,8 @@ apic_status apic_batch_launch(apic_batch *batch, void *stream) {
 }
 
 apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int32_t *geom,
-                               int32_t *n_tiles, int32_t *chunk, int64_t *tile_bytes) {
+                               int32_t *n_tiles, int32_t *chunk, int32_t *lanes,
+                               int64_t *tile_bytes) {
   if (!batch_ok(batch) || !n_classes) return APIC_EINVAL;
   const int32_t cap = *n_classes;
   *n_classes = (int32_t)batch->runs.size();
@@ -1168,15 +1207,18 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
     if (geom) geom[c] = r.geom;
     if (n_tiles) n_tiles[c] = (int32_t)r.gidx.size();
     if (chunk) chunk[c] = batch->chunk[c];
+    if (lanes) lanes[c] = batch->lanes[c];
     if (tile_bytes) tile_bytes[c] = batch->plan->geoms[r.geom].lay.stride;
   }
   return APIC_OK;
 }
 
-apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles) {
+apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, int32_t lanes) {
   if (!batch_ok(batch) || cls < 0 || cls >= (int32_t)batch->runs.size()) return APIC_EINVAL;
+  if (lanes != 1 && lanes != 2) return APIC_EINVAL;
   const int32_t T = (int32_t)batch->runs[cls].gidx.size();
   batch->chunk[cls] = tiles <= 0 ? T : std::min(tiles, T);
+  batch->lanes[cls] = lanes;
   batch_layout(batch);
   batch_drop_graph(batch);
   return APIC_OK;
@@ -1206,8 +1248,22 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
     return APIC_EHIP;
   }
   apic_status rc = APIC_OK;
-  const std::vector<int32_t> saved = batch->chunk;
+  const std::vector<int32_t> saved = batch->chunk, saved_lanes = batch->lanes;
   std::vector<int64_t> saved_ws = batch->cls_ws;
+  // time tiles [0, count) of class c with the current chunk and lanes, from
+  // offset 0 of the workspace
+  auto time_class = [&](size_t c, int count, float &ms) -> apic_status {
+    batch->cls_ws[c] = 0;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(batch->n_tiles, 256)), dim3(256), 0, st,
+                       tile_status, batch->n_tiles, 0u);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e0, st) != hipSuccess) return APIC_EHIP;
+    const apic_status r = batch_run_class(batch, c, 0, count, images, ws, tile_status, io, st);
+    if (r != APIC_OK) return r;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return APIC_EHIP;
+    return APIC_OK;
+  };
   for (size_t c = 0; c < batch->runs.size() && rc == APIC_OK; ++c) {
     const int32_t T = (int32_t)batch->runs[c].gidx.size();
     const int64_t stride = batch->plan->geoms[batch->runs[c].geom].lay.stride;
@@ -1220,23 +1276,11 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
     for (size_t i = 0; i < cand.size() && rc == APIC_OK; ++i) {
       const int32_t k = cand[i];
       if ((int64_t)k * stride > (int64_t)workspace_bytes) break;
-      // time tiles [0, k) of the class as one chunk at offset 0 of the workspace
+      // tiles [0, k) of the class as one chunk (one lane)
       batch->chunk[c] = k;
-      batch->cls_ws[c] = 0;
+      batch->lanes[c] = 1;
       float ms = 0.f;
-      for (int rep = 0; rep < (i == 0 ? 2 : 1) && rc == APIC_OK; ++rep) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(batch->n_tiles, 256)), dim3(256), 0, st,
-                           tile_status, batch->n_tiles, 0u);
-        if (hipGetLastError() != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
-          rc = APIC_EHIP;
-          break;
-        }
-        rc = batch_run_class(batch, c, 0, k, images, ws, tile_status, io, st);
-        if (rc == APIC_OK && (hipEventRecord(e1, st) != hipSuccess ||
-                              hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = APIC_EHIP;
-      }
+      for (int rep = 0; rep < (i == 0 ? 2 : 1) && rc == APIC_OK; ++rep) rc = time_class(c, k, ms);
       const double tile_ms = (double)ms / k;
       const double prev = per_tile.empty() ? 1e300 : per_tile.back();
       per_tile.push_back(tile_ms);
@@ -1261,18 +1305,40 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
       }
     if (ms_per_tile) ms_per_tile[c] = best;
     batch->chunk[c] = pick;
+    batch->lanes[c] = 1;
+    // two lanes of half the chunk (same workspace): one chunk's latency-bound
+    // kernels run beside the other's; kept if 2% faster over the same tiles
+    if (pick >= 2) {
+      const int span = std::min(T, 2 * pick);
+      float ms1 = 0.f, ms2 = 0.f;
+      rc = time_class(c, span, ms1);
+      if (rc == APIC_OK) {
+        batch->chunk[c] = (pick + 1) / 2;
+        batch->lanes[c] = 2;
+        rc = time_class(c, span, ms2);
+      }
+      if (rc == APIC_OK && !(ms2 < 0.98f * ms1)) {
+        batch->chunk[c] = pick;
+        batch->lanes[c] = 1;
+      }
+      if (rc == APIC_OK && ms_per_tile) ms_per_tile[c] = std::min(ms1, ms2) / span;
+    }
     batch->cls_ws = saved_ws;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc != APIC_OK) batch->chunk = saved;
+  if (rc != APIC_OK) {
+    batch->chunk = saved;
+    batch->lanes = saved_lanes;
+  }
   batch_layout(batch);
   // the classes run concurrently: halve the largest blocks until they fit together
   while (rc == APIC_OK && batch->ws_bytes > (int64_t)workspace_bytes) {
     size_t big = 0;
     int64_t big_bytes = -1;
     for (size_t c = 0; c < batch->runs.size(); ++c) {
-      const int64_t b = (int64_t)batch->chunk[c] * batch->plan->geoms[batch->runs[c].geom].lay.stride;
+      const int64_t b = (int64_t)batch->chunk[c] * batch->lanes[c] *
+                        batch->plan->geoms[batch->runs[c].geom].lay.stride;
       if (batch->chunk[c] > 1 && b > big_bytes) {
         big = c;
         big_bytes = b;
@@ -1281,6 +1347,7 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
     if (big_bytes < 0) {
       rc = APIC_EINVAL;  // one tile per class does not fit
       batch->chunk = saved;
+      batch->lanes = saved_lanes;
       batch_layout(batch);
       break;
     }

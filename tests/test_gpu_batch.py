@@ -160,6 +160,15 @@ def test_chunked_and_autotuned_batch_match_plain(uneven):
     assert np.array_equal(field.cpu().numpy(), ref_f)
     assert np.array_equal(zern.cpu().numpy(), ref_z)
     assert np.array_equal(status.cpu().numpy(), ref_s)
+    # one-tile chunks on two lanes (two streams per class, two chunk workspaces)
+    for i in range(len(classes)):
+        batch.set_chunk(i, 1, lanes=2)
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    assert np.array_equal(field.cpu().numpy(), ref_f)
+    assert np.array_equal(zern.cpu().numpy(), ref_z)
+    assert np.array_equal(status.cpu().numpy(), ref_s)
     # autotune within the whole-batch workspace, then run with the chosen chunks
     buf = torch.empty(full_ws + 256, dtype=torch.uint8, device=DEV)
     wp = (buf.data_ptr() + 255) & ~255
