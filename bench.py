@@ -144,7 +144,7 @@ def main():
         buf = torch.empty(cap + 256, dtype=torch.uint8, device=dev)
         t0 = time.time()
         ms_tile = batch.autotune(images, field, zern, status, (buf.data_ptr() + 255) & ~255, cap,
-                                 slack=0.0)
+                                 slack=0.0, log=log)
         del buf
         tune = [{"geom": c["geom"], "tiles": c["n_tiles"], "chunk": c["chunk"],
                  "lanes": c["lanes"], "ms_per_tile": float(m)}

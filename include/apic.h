@@ -246,8 +246,9 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
  * factors) overlap the other's.  Changes apic_batch_workspace_bytes and drops
  * a captured graph. */
 apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, int32_t lanes);
-/* Autotuner.  For each class, times the method on its first k tiles for
- * k = 1, 2, 4, ... up to the class size, as long as k tiles' workspace fits
+/* Autotuner.  For class `cls` (all classes when cls < 0), times the method
+ * on its first k tiles for k = 1, 2, 4, ... up to the class size, as long as
+ * k tiles' workspace fits
  * `workspace_bytes` (and stops once doubling k gains under 3% past k = 4, or
  * after a run longer than 10 s), then sets the
  * class's chunk to the smallest k whose time per tile is within (1 + slack)
@@ -256,12 +257,16 @@ apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, 
  * (they run concurrently), the largest blocks are halved until they fit.
  * Synchronises the host with `stream` after every run (not
  * capturable); writes outputs and status of the timed tiles.  `ms_per_tile`
- * (nullable, one per class) receives the best time.  Changes
+ * (nullable, one per class, indexed by class) receives the best time.  Changes
  * apic_batch_workspace_bytes and drops a captured graph. */
-apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *zernike_out,
-                                float *field_out, uint32_t *tile_status, void *workspace,
-                                size_t workspace_bytes, void *stream, double slack,
-                                double *ms_per_tile);
+apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *images,
+                                float *zernike_out, float *field_out, uint32_t *tile_status,
+                                void *workspace, size_t workspace_bytes, void *stream,
+                                double slack, double *ms_per_tile);
+/* Halve the largest classes' chunks until the classes' blocks together fit
+ * `workspace_bytes` (done by apic_batch_autotune when cls < 0; call it after
+ * tuning classes one by one).  APIC_EINVAL if one tile per class does not fit. */
+apic_status apic_batch_fit(apic_batch *batch, size_t workspace_bytes);
 
 /* ---------------------------------------------------------------- surrogate
  * Learned Zernike surrogate (not part of the paper's method): a perceptron

@@ -40,7 +40,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
-           "apic_batch_autotune", "apic_version"]
+           "apic_batch_autotune", "apic_batch_fit", "apic_version"]
 
 PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
@@ -125,7 +125,8 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_launch.argtypes = [P, P]
     lib.apic_batch_classes.argtypes = [P, ctypes.POINTER(i32), P, P, P, P, P]
     lib.apic_batch_set_chunk.argtypes = [P, i32, i32, i32]
-    lib.apic_batch_autotune.argtypes = [P, P, P, P, P, P, sz, P, ctypes.c_double, P]
+    lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
+    lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
@@ -320,19 +321,27 @@ class Batch:
         self._bound = None
 
     def autotune(self, images, field, zernike, status, workspace_ptr, workspace_bytes,
-                 slack=0.05, stream=None):
-        """Pick each class's chunk by timing (see apic_batch_autotune); the
-        workspace is a raw 256-B aligned device pointer and its size, the
-        budget the chunks must fit.  Returns the best ms per tile per class."""
-        n = len(self.classes())
-        ms = np.zeros(max(n, 1), np.float64)
+                 slack=0.05, stream=None, log=None):
+        """Pick each class's chunk and lanes by timing (see apic_batch_autotune),
+        one class per call so that `log` (optional) reports progress, then fit
+        the classes into the budget.  The workspace is a raw 256-B aligned
+        device pointer and its size.  Returns the best ms per tile per class."""
+        classes = self.classes()
+        ms = np.zeros(max(len(classes), 1), np.float64)
         self._args(images, field, zernike, status, None, None)
-        _check("apic_batch_autotune", self.lib.apic_batch_autotune(
-            self.handle, _ptr(images), _ptr(zernike), _ptr(field), _ptr(status), workspace_ptr,
-            workspace_bytes, _stream(stream), float(slack), ms.ctypes.data_as(ctypes.c_void_p)))
+        for ci, c in enumerate(classes):
+            _check("apic_batch_autotune", self.lib.apic_batch_autotune(
+                self.handle, ci, _ptr(images), _ptr(zernike), _ptr(field), _ptr(status),
+                workspace_ptr, workspace_bytes, _stream(stream), float(slack),
+                ms.ctypes.data_as(ctypes.c_void_p)))
+            if log:
+                t = self.classes()[ci]
+                log(f"autotune class {ci} (geometry {t['geom']}, {t['n_tiles']} tiles): chunk "
+                    f"{t['chunk']}, lanes {t['lanes']}, {ms[ci]:.3f} ms per tile")
+        _check("apic_batch_fit", self.lib.apic_batch_fit(self.handle, workspace_bytes))
         self._refresh()
         self._bound = None
-        return ms[:n]
+        return ms[:len(classes)]
 
     def close(self):
         if self.handle:

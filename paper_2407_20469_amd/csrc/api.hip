@@ -1224,11 +1224,39 @@ apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, 
   return APIC_OK;
 }
 
-apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *zernike_out,
-                                float *field_out, uint32_t *tile_status, void *workspace,
-                                size_t workspace_bytes, void *stream, double slack,
-                                double *ms_per_tile) {
+apic_status apic_batch_fit(apic_batch *batch, size_t workspace_bytes) {
   if (!batch_ok(batch)) return APIC_EINVAL;
+  // the classes run concurrently: halve the largest blocks until they fit together
+  const std::vector<int32_t> saved = batch->chunk;
+  batch_layout(batch);
+  while (batch->ws_bytes > (int64_t)workspace_bytes) {
+    size_t big = 0;
+    int64_t big_bytes = -1;
+    for (size_t c = 0; c < batch->runs.size(); ++c) {
+      const int64_t b = (int64_t)batch->chunk[c] * batch->lanes[c] *
+                        batch->plan->geoms[batch->runs[c].geom].lay.stride;
+      if (batch->chunk[c] > 1 && b > big_bytes) {
+        big = c;
+        big_bytes = b;
+      }
+    }
+    if (big_bytes < 0) {  // one tile per class does not fit
+      batch->chunk = saved;
+      batch_layout(batch);
+      return APIC_EINVAL;
+    }
+    batch->chunk[big] = (batch->chunk[big] + 1) / 2;
+    batch_layout(batch);
+  }
+  batch_drop_graph(batch);
+  return APIC_OK;
+}
+
+apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *images,
+                                float *zernike_out, float *field_out, uint32_t *tile_status,
+                                void *workspace, size_t workspace_bytes, void *stream,
+                                double slack, double *ms_per_tile) {
+  if (!batch_ok(batch) || cls >= (int32_t)batch->runs.size()) return APIC_EINVAL;
   if (batch->n_tiles == 0) return APIC_OK;
   if (!images || !zernike_out || !field_out || !tile_status || !workspace) return APIC_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return APIC_EINVAL;
@@ -1265,6 +1293,7 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
     return APIC_OK;
   };
   for (size_t c = 0; c < batch->runs.size() && rc == APIC_OK; ++c) {
+    if (cls >= 0 && (int32_t)c != cls) continue;
     const int32_t T = (int32_t)batch->runs[c].gidx.size();
     const int64_t stride = batch->plan->geoms[batch->runs[c].geom].lay.stride;
     std::vector<int32_t> cand;
@@ -1330,32 +1359,13 @@ apic_status apic_batch_autotune(apic_batch *batch, const float *images, float *z
   if (rc != APIC_OK) {
     batch->chunk = saved;
     batch->lanes = saved_lanes;
+    batch_layout(batch);
+    batch_drop_graph(batch);
+    return rc;
   }
   batch_layout(batch);
-  // the classes run concurrently: halve the largest blocks until they fit together
-  while (rc == APIC_OK && batch->ws_bytes > (int64_t)workspace_bytes) {
-    size_t big = 0;
-    int64_t big_bytes = -1;
-    for (size_t c = 0; c < batch->runs.size(); ++c) {
-      const int64_t b = (int64_t)batch->chunk[c] * batch->lanes[c] *
-                        batch->plan->geoms[batch->runs[c].geom].lay.stride;
-      if (batch->chunk[c] > 1 && b > big_bytes) {
-        big = c;
-        big_bytes = b;
-      }
-    }
-    if (big_bytes < 0) {
-      rc = APIC_EINVAL;  // one tile per class does not fit
-      batch->chunk = saved;
-      batch->lanes = saved_lanes;
-      batch_layout(batch);
-      break;
-    }
-    batch->chunk[big] = (batch->chunk[big] + 1) / 2;
-    batch_layout(batch);
-  }
   batch_drop_graph(batch);
-  return rc;
+  return cls < 0 ? apic_batch_fit(batch, workspace_bytes) : APIC_OK;
 }
 
 apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precision,
