@@ -11,11 +11,9 @@
 (FETCH_SIZE and WRITE_SIZE of the darkfield gram kernels, and the same two
 counters of the library's 4 GiB copy probe), scales each counter by the bytes
 the copy is known to move, and sums the gram dispatches whose grid has at least
-`min_grid` work-items.  One gram "launch" is one darkfield image step of a
-batch: the diagonal-block dispatch plus the below-diagonal dispatch, so the
-figure is the total over both kernels divided by the number of diagonal-block
-dispatches.  The hash of the gram's sources is recorded so a later change of
-the kernel invalidates the figure.
+`min_grid` work-items.  One gram launch is one darkfield image step of a
+batch (one `k_df_gram` dispatch).  The hash of the gram's sources is recorded
+so a later change of the kernel invalidates the figure.
 """
 
 import csv
@@ -49,9 +47,9 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, min_grid):
     sf = COPY_BYTES / 1024.0 / (sum(cf) / len(cf))
     sw = COPY_BYTES / 1024.0 / (sum(cw) / len(cw))
     def gram(d):
-        rows = [r for r in _counter_rows(d) if int(r["Grid_Size"]) >= min_grid]
-        steps = sum(1 for r in rows if "k_df_gram<true>" in r["Kernel_Name"])
-        return sum(float(r["Counter_Value"]) for r in rows), steps
+        rows = [r for r in _counter_rows(d)
+                if int(r["Grid_Size"]) >= min_grid and "k_df_gram" in r["Kernel_Name"]]
+        return sum(float(r["Counter_Value"]) for r in rows), len(rows)
 
     f, steps = gram(fetch_dir)
     w, steps_w = gram(write_dir)
@@ -59,7 +57,7 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, min_grid):
         raise ValueError("the two counter runs must cover the same gram dispatches")
     fb = f / steps * 1024.0 * sf
     wb = w / steps * 1024.0 * sw
-    return {"kernel": "k_df_gram (diagonal + below-diagonal blocks)", "fetch_scale": sf,
+    return {"kernel": "k_df_gram", "fetch_scale": sf,
             "write_scale": sw, "image_steps": steps, "fetch_bytes_per_launch": fb,
             "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
             "source_sha256": gram_source_hash()}
