@@ -12,6 +12,7 @@ closed-form solution", arXiv 2407.20469):
   correction + stitch .. Sec. 2.3 text after Eq. 10   (stitch.py)
   darkfield extension .. Sec. 2.3, Eq. 11-13          (darkfield.py)
   upsampled output ..... Sec. 2.3, end of brightfield part (output.py)
+  background test ...... Sec. 3.2, variance threshold (background.py)
   surrogate MLP twin ... not in the paper             (mlp.py)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
@@ -36,6 +37,7 @@ from .aberration import aberration_sums, solve_aberration, estimate_pupil, pupil
 from .stitch import stitch_brightfield
 from .darkfield import darkfield_sets, extend_darkfield
 from .output import upsampled_field
+from .background import background_stat, is_background
 from .pipeline import Geometry, reconstruct
 
 __all__ = [
