@@ -78,6 +78,8 @@ typedef enum {
 #define APIC_TILE_NONFINITE_OUT   0x080u /* NaN/Inf in the pupil coefficients         */
 #define APIC_TILE_SURROGATE_USED  0x100u /* the surrogate's coefficients were used    */
 #define APIC_TILE_FALLBACK_USED   0x200u /* the closed form replaced the surrogate    */
+#define APIC_TILE_BACKGROUND      0x400u /* not reconstructed: background statistic
+                                            under the threshold (slide stream)       */
 
 /* Tile flags (apic_tile_desc.flags). */
 #define APIC_TILE_SKIP_DARKFIELD 0x1  /* stop after the brightfield stitch */
@@ -164,6 +166,20 @@ apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
                                 const float *zernike_seed, float *zernike_out, float *diag_out,
                                 float *features_out, uint32_t *tile_status, void *workspace,
                                 size_t workspace_bytes, void *stream);
+
+/* Background statistic of each tile (Sec. 3.2, reconstruction time of the
+ * slide: patches whose low-resolution images vary less than a threshold are
+ * treated as empty glass and skipped).  The paper gives neither the exact
+ * statistic nor the threshold; here it is the mean over the tile's NA-matched
+ * images of var(I_i) / mean(I_i)^2 (population variance over the N x N
+ * pixels, FP64 accumulation), which does not depend on LED brightness or
+ * exposure.  stat_out float [T] (device, batch order).  `images` must be
+ * 16-byte aligned and every image_offset a multiple of 4 (else APIC_EINVAL).
+ * The workspace (apic_workspace_bytes) only holds descriptor lists. */
+apic_status apic_background_stat(const apic_plan *plan, int32_t n_tiles,
+                                 const apic_tile_desc *tiles, const float *images,
+                                 float *stat_out, void *workspace, size_t workspace_bytes,
+                                 void *stream);
 
 /* KK spectra of the NA-matched images (Eq. 4-7), complex [T][n_bf][N][N]
  * contiguous per tile at spectra_out + t * n_bf * N * N (single geometry). */
@@ -338,6 +354,48 @@ apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
                                        float *zernike_out, float *field_out,
                                        uint32_t *tile_status, void *workspace,
                                        size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------- slide stream
+ * Whole-slide scanning (Sec. 2.5 and 3.2: a slide is scanned tile by tile and
+ * each patch is reconstructed independently; background patches are skipped):
+ * tiles of one geometry whose images live in HOST memory are reconstructed in
+ * chunks through device staging buffers.  apic_streamer_create allocates, for
+ * each of `n_buffers` (2..4) default-priority streams, device room for `chunk`
+ * tiles of geometry `geom` (image stacks, fields, coefficients, status,
+ * statistic) plus that chunk's workspace, and pinned host staging for the
+ * small per-tile arrays; apic_streamer_device_bytes reports the device total;
+ * apic_streamer_destroy frees everything.  The streamer keeps a pointer to its
+ * plan: destroy it first.  One streamer runs one apic_streamer_run at a time. */
+typedef struct apic_streamer apic_streamer;
+apic_status apic_streamer_create(apic_plan *plan, int32_t geom, int32_t chunk, int32_t n_buffers,
+                                 apic_streamer **out);
+apic_status apic_streamer_destroy(apic_streamer *streamer);
+apic_status apic_streamer_device_bytes(const apic_streamer *streamer, size_t *bytes);
+/* Reconstruct n_tiles tiles from host memory; returns when every tile is done.
+ *   host_images[t]  float [n_bf + n_df][N][N] of tile t (host; pinned memory,
+ *                   e.g. hipHostMalloc, for asynchronous full-speed copies;
+ *                   tiles may share one buffer)
+ *   host_fields[t]  complex64 [fN][fN] output of tile t (host, pinned)
+ *   positions       float [T][2] (host) tile coordinates for the surrogate;
+ *                   needed when model is not NULL
+ *   zernike_out     float [T][15], tile_status uint32 [T], bg_stat_out float
+ *                   [T] (nullable): host arrays
+ * Chunk c (tiles c*chunk ...) runs on buffer c mod n_buffers: copy in,
+ * apic_background_stat, the method on the chunk's tiles whose statistic is
+ * >= bg_threshold, copy out.  The host enqueues chunk c's copy-in and
+ * statistic, then waits for chunk c-1's statistic (a few bytes) and enqueues
+ * its method, so copies overlap the kernels of the chunks in flight.  A tile
+ * under the threshold (bg_threshold <= 0 disables the test) gets status
+ * APIC_TILE_BACKGROUND and zero coefficients; its field buffer is not
+ * written.  With `model` the pupil stage is apic_reconstruct_tiles_sur's
+ * (rho_max, kappa_max, resid_max as there), else apic_reconstruct_tiles's;
+ * results are those calls' on the same tiles.  Not capturable.  On an error
+ * return every stream has been drained; outputs are then incomplete. */
+apic_status apic_streamer_run(apic_streamer *streamer, int32_t n_tiles,
+                              const float *const *host_images, float *const *host_fields,
+                              const float *positions, const apic_mlp_model *model, float rho_max,
+                              float kappa_max, float resid_max, float bg_threshold,
+                              float *zernike_out, uint32_t *tile_status, float *bg_stat_out);
 
 /* Opt-in profiling of kernel groups (for benchmarks).  apic_profile(1) clears
  * and enables recording: every later launch of a group records a HIP event

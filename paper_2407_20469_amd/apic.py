@@ -29,6 +29,7 @@ TILE_SEEDED = 0x040
 TILE_NONFINITE_OUT = 0x080
 TILE_SURROGATE_USED = 0x100
 TILE_FALLBACK_USED = 0x200
+TILE_BACKGROUND = 0x400
 MLP_PARAMS, MLP_INPUTS, MLP_OUTPUTS = 26896, 34, 12
 TILE_SKIP_DARKFIELD = 0x1
 
@@ -40,7 +41,9 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
-           "apic_batch_autotune", "apic_batch_fit", "apic_version"]
+           "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
+           "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
+           "apic_streamer_run", "apic_version"]
 
 PROF_GROUPS = ["kk", "pupil", "stitch", "df_fft", "df_rhs", "gram", "chol", "out"]
 
@@ -127,6 +130,12 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_set_chunk.argtypes = [P, i32, i32, i32]
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
+    lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
+    lib.apic_streamer_create.argtypes = [P, i32, i32, i32, ctypes.POINTER(P)]
+    lib.apic_streamer_destroy.argtypes = [P]
+    lib.apic_streamer_device_bytes.argtypes = [P, ctypes.POINTER(sz)]
+    lib.apic_streamer_run.argtypes = [P, i32, P, P, P, ctypes.POINTER(MlpModel), f32, f32, f32,
+                                      f32, P, P, P]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
@@ -442,6 +451,88 @@ def estimate_pupil(plan, images, seed=None, workspace=None, stream=None):
         plan.handle, T, descs, _ptr(images), _ptr(seed), _ptr(zern), _ptr(diag), _ptr(feat),
         _ptr(status), wp, wb, _stream(stream)))
     return zern, diag, feat, status
+
+
+def background_stat(plan, images, workspace=None, stream=None):
+    """Background statistic of each tile (float32 tensor (T,)): mean over the
+    NA-matched images of var(I) / mean(I)^2."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    out = torch.empty((T,), dtype=torch.float32, device=images.device)
+    descs = tile_descs(T, n_img, n, 0)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), images.device)
+    _check("apic_background_stat", plan.lib.apic_background_stat(
+        plan.handle, T, descs, _ptr(images), _ptr(out), wp, wb, _stream(stream)))
+    return out
+
+
+class Streamer:
+    """Slide stream: tiles of geometry ``geom`` whose image stacks are in host
+    memory, reconstructed in chunks of ``chunk`` tiles through ``n_buffers``
+    device staging buffers, each on its own stream (see apic_streamer_run)."""
+
+    def __init__(self, plan, geom=0, chunk=8, n_buffers=3):
+        self.plan = plan
+        self.lib = plan.lib
+        self.geom = plan.geoms[geom]
+        h = ctypes.c_void_p()
+        _check("apic_streamer_create", self.lib.apic_streamer_create(
+            plan.handle, geom, chunk, n_buffers, ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def device_bytes(self):
+        b = ctypes.c_size_t()
+        _check("apic_streamer_device_bytes",
+               self.lib.apic_streamer_device_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.apic_streamer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, host_images, host_fields, positions=None, sur=None, rho_max=0.05,
+            kappa_max=1e6, resid_max=1.0, bg_threshold=0.0):
+        """host_images / host_fields: sequences of CPU tensors (pinned for
+        asynchronous copies), one per tile; the fields are complex64 (fN, fN).
+        Returns (zernike (T, 15), status (T,), background statistic (T,)) as
+        NumPy arrays."""
+        T = len(host_images)
+        if len(host_fields) != T:
+            raise ValueError("one field buffer per tile")
+        n, nf = self.geom["n"], self.geom["n"] * self.geom.get("upsample", 2)
+        n_img = self.geom["n_bf"] + self.geom["n_df"]
+        for x in host_images:
+            if x.is_cuda or x.numel() != n_img * n * n or not x.is_contiguous():
+                raise ValueError("each image stack is a contiguous host tensor (n_img, N, N)")
+        for f in host_fields:
+            if f.is_cuda or f.numel() * f.element_size() != 8 * nf * nf or not f.is_contiguous():
+                raise ValueError("each field is a contiguous host complex64 (fN, fN)")
+        imgs = (ctypes.c_void_p * T)(*[x.data_ptr() for x in host_images])
+        flds = (ctypes.c_void_p * T)(*[f.data_ptr() for f in host_fields])
+        z = np.zeros((T, 15), np.float32)
+        st = np.zeros(T, np.uint32)
+        bg = np.zeros(T, np.float32)
+        pos = None
+        mdl = None
+        if sur is not None:
+            pos = np.ascontiguousarray(np.asarray(positions, np.float32).reshape(T, 2))
+            mdl = sur.model()
+        _check("apic_streamer_run", self.lib.apic_streamer_run(
+            self.handle, T, imgs, flds,
+            None if pos is None else pos.ctypes.data_as(ctypes.c_void_p),
+            None if mdl is None else ctypes.byref(mdl), float(rho_max), float(kappa_max),
+            float(resid_max), float(bg_threshold), z.ctypes.data_as(ctypes.c_void_p),
+            st.ctypes.data_as(ctypes.c_void_p), bg.ctypes.data_as(ctypes.c_void_p)))
+        return z, st, bg
 
 
 def kk_spectra(plan, images, workspace=None, stream=None):

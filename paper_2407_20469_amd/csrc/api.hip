@@ -460,7 +460,7 @@ apic_status run_output(const ClassArgs &a, const c32 *src, float *field, hipStre
 
 enum Stage : unsigned {
   S_KK = 1, S_PUPIL = 2, S_COEF_IN = 4, S_STITCH = 8, S_SPEC_IN = 16, S_DF = 32, S_SPEC_OUT = 64,
-  S_OUT = 128, S_SUR = 256
+  S_OUT = 128, S_SUR = 256, S_BG = 512
 };
 
 struct CallIO {
@@ -471,12 +471,17 @@ struct CallIO {
   const float *spec_src = nullptr;
   SurrogateArgs sur{};
   float *zcf = nullptr, *zsur = nullptr;
+  float *bg_out = nullptr;
 };
 
 template <int N>
 apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &a, unsigned st_mask,
                         const CallIO &io, hipStream_t st) {
   apic_status rc = APIC_OK;
+  if (st_mask & S_BG) {
+    hipLaunchKernelGGL(k_bg_stat, dim3(a.T), dim3(kBgThreads), 0, st, a, io.bg_out);
+    APIC_LAUNCHED();
+  }
   if (st_mask & S_KK) {
     rc = run_kk<N>(a, reinterpret_cast<c32 *>(io.kk_out), st);
     if (rc) return rc;
@@ -803,6 +808,21 @@ apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
   io.feat = features_out;
   return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
                   S_KK | S_PUPIL, io);
+}
+
+apic_status apic_background_stat(const apic_plan *plan, int32_t n_tiles,
+                                 const apic_tile_desc *tiles, const float *images,
+                                 float *stat_out, void *workspace, size_t workspace_bytes,
+                                 void *stream) {
+  if (n_tiles > 0 && (!images || !stat_out)) return APIC_EINVAL;
+  // the statistic streams the images with 16-byte loads
+  if ((reinterpret_cast<uintptr_t>(images) & 15) != 0) return APIC_EINVAL;
+  for (int32_t t = 0; t < n_tiles; ++t)
+    if (tiles && (tiles[t].image_offset & 3) != 0) return APIC_EINVAL;
+  CallIO io;
+  io.bg_out = stat_out;
+  return run_call(plan, n_tiles, tiles, images, nullptr, workspace, workspace_bytes, stream, S_BG,
+                  io);
 }
 
 apic_status apic_kk_spectra(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,
@@ -1381,3 +1401,265 @@ apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precisi
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ slide stream
+// Tiles whose images live in host memory go through `nbuf` device staging
+// buffers, one default-priority stream each.  Chunk c uses buffer c % nbuf:
+// copy in, background statistic, the method on the chunk's non-background
+// tiles, copy out.  The host enqueues chunk c's copy-in before it waits for
+// chunk c - 1's statistic and enqueues that chunk's method, so one chunk's
+// copies run under the earlier chunks' kernels.
+struct apic_streamer {
+  uint32_t magic = 0x5354524du;  // "STRM"
+  apic_plan *plan = nullptr;
+  int geom = 0, chunk = 0, nbuf = 0;
+  int64_t img_elems = 0;   // floats per tile image stack
+  int64_t fld_elems = 0;   // complex elements per tile field
+  size_t ws_bytes = 0;     // workspace of one chunk
+  struct Buf {
+    hipStream_t s = nullptr;
+    hipEvent_t stat_ready = nullptr, done = nullptr;
+    void *dev = nullptr;     // one allocation: images, field, workspace, small arrays
+    void *host = nullptr;    // pinned staging of the small per-tile arrays
+    float *d_img = nullptr, *d_field = nullptr, *d_z = nullptr, *d_pos = nullptr, *d_bg = nullptr;
+    uint32_t *d_status = nullptr;
+    char *d_ws = nullptr;
+    float *h_bg = nullptr, *h_z = nullptr, *h_pos = nullptr;
+    uint32_t *h_status = nullptr;
+    int first = 0, count = 0;
+    std::vector<int> live;   // slots of the chunk's reconstructed tiles
+    bool pending = false;    // results not yet copied to the caller's arrays
+  };
+  std::vector<Buf> bufs;
+  size_t dev_bytes = 0;
+};
+
+static bool streamer_ok(const apic_streamer *s) {
+  return s && s->magic == 0x5354524du && s->plan;
+}
+
+static void streamer_free(apic_streamer *s) {
+  for (apic_streamer::Buf &b : s->bufs) {
+    if (b.s) (void)hipStreamSynchronize(b.s);
+    if (b.s) (void)hipStreamDestroy(b.s);
+    if (b.stat_ready) (void)hipEventDestroy(b.stat_ready);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.host) (void)hipHostFree(b.host);
+  }
+  s->magic = 0;
+  delete s;
+}
+
+// Descriptors of the given staging slots (slot i holds the chunk's i-th tile).
+static std::vector<apic_tile_desc> slot_descs(const apic_streamer *s, const std::vector<int> &slots) {
+  std::vector<apic_tile_desc> d(slots.size());
+  for (size_t k = 0; k < slots.size(); ++k) {
+    d[k].geom = s->geom;
+    d[k].flags = 0;
+    d[k].image_offset = (int64_t)slots[k] * s->img_elems;
+    d[k].field_offset = (int64_t)slots[k] * s->fld_elems;
+    d[k].pos_x = d[k].pos_y = 0.f;
+  }
+  return d;
+}
+
+apic_status apic_streamer_create(apic_plan *plan, int32_t geom, int32_t chunk, int32_t n_buffers,
+                                 apic_streamer **out) {
+  if (!out) return APIC_EINVAL;
+  *out = nullptr;
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  if (geom < 0 || geom >= (int32_t)plan->geoms.size() || chunk < 1 || n_buffers < 2 ||
+      n_buffers > 4)
+    return APIC_EINVAL;
+  apic_status rc = apic_plan_upload(plan);
+  if (rc) return rc;
+  rc = ensure_twiddles();
+  if (rc) return rc;
+  apic_streamer *s = new (std::nothrow) apic_streamer();
+  if (!s) return APIC_ENOMEM;
+  const GeomPlan &g = plan->geoms[geom];
+  s->plan = plan;
+  s->geom = geom;
+  s->chunk = chunk;
+  s->nbuf = n_buffers;
+  s->img_elems = (int64_t)(g.n_bf + g.n_df) * g.n * g.n;
+  s->fld_elems = (int64_t)g.nf * g.nf;
+  std::vector<int> all(chunk);
+  for (int i = 0; i < chunk; ++i) all[i] = i;
+  // the whole chunk's layout (descriptor lists included) bounds every subset's
+  const std::vector<apic_tile_desc> d = slot_descs(s, all);
+  std::vector<ClassRun> runs;
+  int64_t need = 0;
+  rc = layout_call(plan, chunk, d.data(), runs, need);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  s->ws_bytes = (size_t)align256(need);
+  const int64_t img_b = align256(4 * s->img_elems * chunk);
+  const int64_t fld_b = align256(8 * s->fld_elems * chunk);
+  const int64_t small_b = align256(4 * (int64_t)chunk * (15 + 2 + 1 + 1));
+  const size_t per = (size_t)(img_b + fld_b + (int64_t)s->ws_bytes + small_b);
+  s->dev_bytes = per * n_buffers;
+  s->bufs.resize(n_buffers);
+  bool ok = true;
+  for (apic_streamer::Buf &b : s->bufs) {
+    ok = ok && hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b.stat_ready, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess &&
+         hipMalloc(&b.dev, per) == hipSuccess &&
+         hipHostMalloc(&b.host, (size_t)small_b, hipHostMallocDefault) == hipSuccess;
+    if (!ok) break;
+    char *p = reinterpret_cast<char *>(b.dev);
+    b.d_img = reinterpret_cast<float *>(p);
+    b.d_field = reinterpret_cast<float *>(p + img_b);
+    b.d_ws = p + img_b + fld_b;
+    float *sm = reinterpret_cast<float *>(b.d_ws + s->ws_bytes);
+    b.d_z = sm;
+    b.d_pos = sm + 15 * chunk;
+    b.d_bg = sm + 17 * chunk;
+    b.d_status = reinterpret_cast<uint32_t *>(sm + 18 * chunk);
+    float *hs = reinterpret_cast<float *>(b.host);
+    b.h_z = hs;
+    b.h_pos = hs + 15 * chunk;
+    b.h_bg = hs + 17 * chunk;
+    b.h_status = reinterpret_cast<uint32_t *>(hs + 18 * chunk);
+  }
+  if (!ok) {
+    streamer_free(s);
+    return APIC_EHIP;
+  }
+  *out = s;
+  return APIC_OK;
+}
+
+apic_status apic_streamer_destroy(apic_streamer *s) {
+  if (!s) return APIC_OK;
+  if (!streamer_ok(s)) return APIC_EINVAL;
+  streamer_free(s);
+  return APIC_OK;
+}
+
+apic_status apic_streamer_device_bytes(const apic_streamer *s, size_t *bytes) {
+  if (!streamer_ok(s) || !bytes) return APIC_EINVAL;
+  *bytes = s->dev_bytes;
+  return APIC_OK;
+}
+
+apic_status apic_streamer_run(apic_streamer *s, int32_t n_tiles, const float *const *host_images,
+                              float *const *host_fields, const float *positions,
+                              const apic_mlp_model *model, float rho_max, float kappa_max,
+                              float resid_max, float bg_threshold, float *zernike_out,
+                              uint32_t *tile_status, float *bg_stat_out) {
+  if (!streamer_ok(s) || n_tiles < 0) return APIC_EINVAL;
+  if (n_tiles == 0) return APIC_OK;
+  if (!host_images || !host_fields || !zernike_out || !tile_status) return APIC_EINVAL;
+  if (model && (!model_ok(model) || !positions)) return APIC_EINVAL;
+  for (int32_t t = 0; t < n_tiles; ++t)
+    if (!host_images[t] || !host_fields[t]) return APIC_EINVAL;
+  const size_t img_bytes = 4 * (size_t)s->img_elems, fld_bytes = 8 * (size_t)s->fld_elems;
+  unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT;
+  CallIO io;
+  if (model) {
+    mask |= S_SUR;
+    io.sur = SurrogateArgs{model->theta, model->in_mean, model->in_std, nullptr, rho_max,
+                           kappa_max, resid_max};
+  }
+  const int nch = (n_tiles + s->chunk - 1) / s->chunk;
+
+  // copy in + statistic of chunk c
+  auto stage_in = [&](int c) -> apic_status {
+    apic_streamer::Buf &b = s->bufs[c % s->nbuf];
+    b.first = c * s->chunk;
+    b.count = std::min(s->chunk, n_tiles - b.first);
+    for (int i = 0; i < b.count; ++i)
+      APIC_HIP(hipMemcpyAsync(b.d_img + (int64_t)i * s->img_elems, host_images[b.first + i],
+                              img_bytes, hipMemcpyHostToDevice, b.s));
+    std::vector<int> all(b.count);
+    for (int i = 0; i < b.count; ++i) all[i] = i;
+    const std::vector<apic_tile_desc> d = slot_descs(s, all);
+    CallIO bio;
+    bio.bg_out = b.d_bg;
+    apic_status rc = run_call(s->plan, b.count, d.data(), b.d_img, nullptr, b.d_ws, s->ws_bytes,
+                              b.s, S_BG, bio);
+    if (rc) return rc;
+    APIC_HIP(hipMemcpyAsync(b.h_bg, b.d_bg, 4 * (size_t)b.count, hipMemcpyDeviceToHost, b.s));
+    APIC_HIP(hipEventRecord(b.stat_ready, b.s));
+    return APIC_OK;
+  };
+  // background decision, method and copy out of chunk c
+  auto run_chunk = [&](int c) -> apic_status {
+    apic_streamer::Buf &b = s->bufs[c % s->nbuf];
+    APIC_HIP(hipEventSynchronize(b.stat_ready));
+    b.live.clear();
+    for (int i = 0; i < b.count; ++i) {
+      const int t = b.first + i;
+      const float st = b.h_bg[i];
+      if (bg_stat_out) bg_stat_out[t] = st;
+      if (bg_threshold > 0.f && st < bg_threshold) {
+        tile_status[t] = APIC_TILE_BACKGROUND;
+        for (int j = 0; j < 15; ++j) zernike_out[15 * (int64_t)t + j] = 0.f;
+      } else {
+        b.live.push_back(i);
+      }
+    }
+    if (!b.live.empty()) {
+      const std::vector<apic_tile_desc> d = slot_descs(s, b.live);
+      CallIO cio = io;
+      cio.zout = b.d_z;
+      cio.field = b.d_field;
+      if (model) {
+        for (size_t k = 0; k < b.live.size(); ++k) {
+          b.h_pos[2 * k] = positions[2 * (int64_t)(b.first + b.live[k])];
+          b.h_pos[2 * k + 1] = positions[2 * (int64_t)(b.first + b.live[k]) + 1];
+        }
+        APIC_HIP(hipMemcpyAsync(b.d_pos, b.h_pos, 8 * b.live.size(), hipMemcpyHostToDevice, b.s));
+        cio.sur.positions = b.d_pos;
+      }
+      apic_status rc = run_call(s->plan, (int32_t)b.live.size(), d.data(), b.d_img, b.d_status,
+                                b.d_ws, s->ws_bytes, b.s, mask, cio);
+      if (rc) return rc;
+      for (size_t k = 0; k < b.live.size(); ++k)
+        APIC_HIP(hipMemcpyAsync(host_fields[b.first + b.live[k]],
+                                b.d_field + 2 * (int64_t)b.live[k] * s->fld_elems, fld_bytes,
+                                hipMemcpyDeviceToHost, b.s));
+      APIC_HIP(hipMemcpyAsync(b.h_z, b.d_z, 60 * b.live.size(), hipMemcpyDeviceToHost, b.s));
+      APIC_HIP(hipMemcpyAsync(b.h_status, b.d_status, 4 * b.live.size(), hipMemcpyDeviceToHost,
+                              b.s));
+    }
+    APIC_HIP(hipEventRecord(b.done, b.s));
+    b.pending = true;
+    return APIC_OK;
+  };
+  // results of the chunk last run on buffer b into the caller's arrays
+  auto harvest = [&](apic_streamer::Buf &b) -> apic_status {
+    if (!b.pending) return APIC_OK;
+    APIC_HIP(hipEventSynchronize(b.done));
+    for (size_t k = 0; k < b.live.size(); ++k) {
+      const int64_t t = b.first + b.live[k];
+      for (int j = 0; j < 15; ++j) zernike_out[15 * t + j] = b.h_z[15 * k + j];
+      tile_status[t] = b.h_status[k];
+    }
+    b.pending = false;
+    return APIC_OK;
+  };
+
+  apic_status rc = APIC_OK;
+  for (int c = 0; c <= nch && rc == APIC_OK; ++c) {
+    if (c < nch) {
+      rc = harvest(s->bufs[c % s->nbuf]);
+      if (rc == APIC_OK) rc = stage_in(c);
+    }
+    if (rc == APIC_OK && c >= 1) rc = run_chunk(c - 1);
+  }
+  for (apic_streamer::Buf &b : s->bufs) {
+    if (rc != APIC_OK) {
+      (void)hipStreamSynchronize(b.s);  // host buffers may still be in flight
+      b.pending = false;
+    } else {
+      rc = harvest(b);
+    }
+  }
+  return rc;
+}

@@ -51,6 +51,51 @@ __global__ __launch_bounds__(256) void k_image_stats(ClassArgs a) {
   }
 }
 
+// Background statistic of each tile (Sec. 3.2: patches whose low-resolution
+// images barely vary are empty glass and are not reconstructed): the mean over
+// the NA-matched images of var(I_i) / mean(I_i)^2, population variance over the
+// N x N pixels, accumulated in FP64 around the image's first pixel.  One
+// workgroup per tile streams its NA-matched images once with 16-byte loads.
+constexpr int kBgThreads = 512;
+__global__ __launch_bounds__(kBgThreads) void k_bg_stat(ClassArgs a, float *stat_out) {
+  const int t = blockIdx.x;
+  const int nn = a.n * a.n;
+  __shared__ double red[2][kBgThreads / 64];
+  double acc = 0.0;
+  for (int i = 0; i < a.n_bf; ++i) {
+    const float *img = a.image(t, i);
+    const double x0 = img[0];
+    const float4 *v4 = reinterpret_cast<const float4 *>(img);
+    double s = 0.0, q = 0.0;
+    for (int p = threadIdx.x; p < nn / 4; p += kBgThreads) {
+      const float4 v = v4[p];
+      const double d0 = v.x - x0, d1 = v.y - x0, d2 = v.z - x0, d3 = v.w - x0;
+      s += (d0 + d1) + (d2 + d3);
+      q += (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o);
+      q += __shfl_xor(q, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = s;
+      red[1][threadIdx.x >> 6] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ts = 0.0, tq = 0.0;
+      for (int w = 0; w < kBgThreads / 64; ++w) {
+        ts += red[0][w];
+        tq += red[1][w];
+      }
+      const double md = ts / nn, mean = x0 + md;
+      acc += (tq / nn - md * md) / (mean * mean);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stat_out[a.gidx(t)] = (float)(acc / a.n_bf);
+}
+
 // ---------------------------------------------------------------- KK passes
 // Pass 1 (rows): L = log(max(I, eps)), row FFT.
 template <int N> struct OpKK1 {

@@ -116,6 +116,20 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     # empty batch is a no-op
     assert lib.apic_reconstruct_tiles(plan.handle, 0, None, None, None, None, None, None, None, 0,
                                       None) == apic.APIC_OK
+    # background statistic: image offsets must allow 16-byte loads
+    descs = apic.tile_descs(2, 16, 64, 0)
+    descs[1].image_offset += 2
+    rc = lib.apic_background_stat(plan.handle, 2, descs, fake, fake, fake, need, None)
+    assert rc == apic.APIC_EINVAL
+    # streamer: chunk >= 1, 2..4 buffers, geometry in range, null output handle
+    h = ctypes.c_void_p()
+    for geom, chunk, nbuf in ((0, 0, 3), (0, 4, 1), (0, 4, 5), (1, 4, 3), (-1, 4, 3)):
+        rc = lib.apic_streamer_create(plan.handle, geom, chunk, nbuf, ctypes.byref(h))
+        assert rc == apic.APIC_EINVAL and not h.value
+    assert lib.apic_streamer_create(plan.handle, 0, 4, 3, None) == apic.APIC_EINVAL
+    rc = lib.apic_streamer_run(ctypes.cast(junk, ctypes.c_void_p), 1, None, None, None, None,
+                               0.05, 1e6, 1.0, 0.0, None, None, None)
+    assert rc == apic.APIC_EINVAL
 
 
 def test_workspace_grows_with_tiles_and_mixed_classes():
