@@ -64,22 +64,23 @@ def _minmax(x):
 
 
 def make_tiles(uv, background, seed, device, max_abs=0.3, photons=1e4, chunk=256, bg_lo=0.005,
-               bg_hi=0.02):
-    """float32 images (T, 16, 128, 128) on device and true coefficients (T, 15)."""
-    geom = geometry()
+               bg_hi=0.02, n=N):
+    """float32 images (T, 16, n, n) on device (default n = 128) and true
+    coefficients (T, 15)."""
+    geom = geometry(n)
     r = geom["na_obj"] * geom["n"] * geom["dx_um"] / geom["wavelength_um"]
     a = field_coeffs(max_abs)
     c_true = pupil_at(a, np.asarray(uv, np.float64))
     T = len(uv)
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
-    out = torch.empty((T, N_BF, N, N), dtype=torch.float32, device=device)
+    out = torch.empty((T, N_BF, n, n), dtype=torch.float32, device=device)
     bg = torch.as_tensor(np.asarray(background, bool), device=device)
     for s in range(0, T, chunk):
         e = min(T, s + chunk)
         m = e - s
-        u0 = torch.rand((m, N, N), generator=gen, device=device, dtype=torch.float64)
-        g0 = torch.randn((m, N, N), generator=gen, device=device, dtype=torch.float64)
+        u0 = torch.rand((m, n, n), generator=gen, device=device, dtype=torch.float64)
+        g0 = torch.randn((m, n, n), generator=gen, device=device, dtype=torch.float64)
         lvl = bg_lo + (bg_hi - bg_lo) * torch.rand((m, 1, 1), generator=gen, device=device,
                                                    dtype=torch.float64)
         sm_u, sm_g = _smooth(u0, 2.0), _smooth(g0, 2.0)

@@ -44,3 +44,24 @@ def test_poisson_noise_scale():
     noisy = S.add_poisson(img, 1e4, seed=3)
     assert abs(noisy.mean().item() - 2.0) < 1e-3
     assert abs(noisy.var().item() - 2.0 / 1e4) < 2e-5
+
+
+def test_slide_mask_and_scan_order():
+    """The slide grid of 512 px tiles at 0.4 um is 122 x 371, the mask covers
+    30% of it, the scan visits mask tiles in raster order, and the pool
+    indices cycle through the tissue tiles with about 15% glass."""
+    from apic_synth import slide
+    assert slide.slide_grid() == (122, 371)
+    m = slide.slide_mask()
+    assert m.shape == (122, 371)
+    assert abs(m.mean() - 0.30) < 1e-3
+    idx, src = slide.scan_order(m, 400, 16, 4)
+    assert np.all(np.diff(idx) > 0) and np.all(m.ravel()[idx])
+    assert idx[0] == np.flatnonzero(m.ravel())[0]
+    glass = src >= 16
+    assert 0.08 < glass.mean() < 0.22
+    assert np.array_equal(src[~glass], np.arange((~glass).sum()) % 16)
+    assert np.all(src[glass] < 20)
+    w = slide.pool_workload(16, 4)
+    assert (w.n, w.n_bf, w.n_df, w.n_tiles) == (512, 16, 32, 20)
+    assert np.abs(w.coeffs).max() <= 1.5 + 1e-9
