@@ -9,6 +9,7 @@ closed-form solution", arXiv 2407.20469):
   forward model ........ Sec. 2.2, Eq. 1-3            (forward.py)
   Kramers-Kronig ....... Sec. 2.3, Eq. 4-7            (kk.py)
   aberration solve ..... Sec. 2.3, Eq. 8-10           (aberration.py)
+  pixel-domain Eq. 10 .. Sec. 2.3, Eq. 10 per pixel   (pupil_pixel.py)
   correction + stitch .. Sec. 2.3 text after Eq. 10   (stitch.py)
   darkfield extension .. Sec. 2.3, Eq. 11-13          (darkfield.py)
   upsampled output ..... Sec. 2.3, end of brightfield part (output.py)
@@ -38,6 +39,7 @@ from .stitch import stitch_brightfield
 from .darkfield import darkfield_sets, extend_darkfield
 from .output import upsampled_field
 from .background import background_stat, is_background
+from .pupil_pixel import solve_pixel_pupil
 from .pipeline import Geometry, reconstruct
 
 __all__ = [
