@@ -80,6 +80,8 @@ typedef enum {
 #define APIC_TILE_FALLBACK_USED   0x200u /* the closed form replaced the surrogate    */
 #define APIC_TILE_BACKGROUND      0x400u /* not reconstructed: background statistic
                                             under the threshold (slide stream)       */
+#define APIC_TILE_PIXEL_NOT_CONVERGED 0x800u /* pixel-domain pupil solve stopped at
+                                                max_iter before its tolerance        */
 
 /* Tile flags (apic_tile_desc.flags). */
 #define APIC_TILE_SKIP_DARKFIELD 0x1  /* stop after the brightfield stitch */
@@ -166,6 +168,29 @@ apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
                                 const float *zernike_seed, float *zernike_out, float *diag_out,
                                 float *features_out, uint32_t *tile_status, void *workspace,
                                 size_t workspace_bytes, void *stream);
+
+/* Eq. 10 as the paper writes it: one unknown per pupil pixel.  phi(k) for
+ * every integer k with kx^2 + ky^2 <= r^2, rows phi(K+K_i) - phi(K+K_l) -
+ * phi(K_i) + phi(K_l) = beta over the same pairs, K, phase differences and
+ * weights as apic_estimate_pupil.  The paper names no solver; phi is the
+ * minimum-norm weighted least-squares solution (no piston, tip or tilt, nor
+ * any other component the rows cannot see), computed per tile by conjugate
+ * gradients on the normal equations from phi = 0, stopped when the residual
+ * norm falls under tol (0 < tol < 1) times its first value or after max_iter
+ * iterations (status APIC_TILE_PIXEL_NOT_CONVERGED).
+ *   phi_out      float [T][N][N] in FFT order, 0 outside the pupil
+ *                (contiguous per tile at phi_out + t * N * N)
+ *   zernike_out  float [T][15]: least-squares fit of Noll Z_1..Z_15 to phi
+ *                over the pupil pixels, c_1..c_3 reported as 0
+ *   iters_out    int32 [T] or NULL: iterations taken
+ * Single-geometry plans with at most 7936 pupil pixels (N <= 256 at these
+ * optics); APIC_EUNSUPPORTED otherwise. */
+apic_status apic_estimate_pupil_pixel(const apic_plan *plan, int32_t n_tiles,
+                                      const apic_tile_desc *tiles, const float *images,
+                                      double tol, int32_t max_iter, float *phi_out,
+                                      float *zernike_out, int32_t *iters_out,
+                                      uint32_t *tile_status, void *workspace,
+                                      size_t workspace_bytes, void *stream);
 
 /* Background statistic of each tile (Sec. 3.2, reconstruction time of the
  * slide: patches whose low-resolution images vary less than a threshold are

@@ -30,6 +30,7 @@ TILE_NONFINITE_OUT = 0x080
 TILE_SURROGATE_USED = 0x100
 TILE_FALLBACK_USED = 0x200
 TILE_BACKGROUND = 0x400
+TILE_PIXEL_NOT_CONVERGED = 0x800
 MLP_PARAMS, MLP_INPUTS, MLP_OUTPUTS = 26896, 34, 12
 TILE_SKIP_DARKFIELD = 0x1
 
@@ -42,6 +43,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
            "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
+           "apic_estimate_pupil_pixel",
            "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
            "apic_streamer_run", "apic_version"]
 
@@ -131,6 +133,8 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
+    lib.apic_estimate_pupil_pixel.argtypes = [P, i32, ctypes.POINTER(TileDesc), P,
+                                              ctypes.c_double, i32, P, P, P, P, P, sz, P]
     lib.apic_streamer_create.argtypes = [P, i32, i32, i32, ctypes.POINTER(P)]
     lib.apic_streamer_destroy.argtypes = [P]
     lib.apic_streamer_device_bytes.argtypes = [P, ctypes.POINTER(sz)]
@@ -451,6 +455,25 @@ def estimate_pupil(plan, images, seed=None, workspace=None, stream=None):
         plan.handle, T, descs, _ptr(images), _ptr(seed), _ptr(zern), _ptr(diag), _ptr(feat),
         _ptr(status), wp, wb, _stream(stream)))
     return zern, diag, feat, status
+
+
+def estimate_pupil_pixel(plan, images, tol=1e-10, max_iter=1000, workspace=None, stream=None):
+    """Eq. 10 with one unknown per pupil pixel.  Returns (phi (T, N, N) float32
+    in FFT order, zernike summary (T, 15), iterations (T,), status (T,))."""
+    import torch
+    g, n, n_img, T = _batch_args(plan, images)
+    dev = images.device
+    phi = torch.empty((T, n, n), dtype=torch.float32, device=dev)
+    zern = torch.empty((T, 15), dtype=torch.float32, device=dev)
+    iters = torch.empty((T,), dtype=torch.int32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    descs = tile_descs(T, n_img, n, 0)
+    ws = workspace or Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), dev)
+    _check("apic_estimate_pupil_pixel", plan.lib.apic_estimate_pupil_pixel(
+        plan.handle, T, descs, _ptr(images), float(tol), int(max_iter), _ptr(phi), _ptr(zern),
+        _ptr(iters), _ptr(status), wp, wb, _stream(stream)))
+    return phi, zern, iters, status
 
 
 def background_stat(plan, images, workspace=None, stream=None):

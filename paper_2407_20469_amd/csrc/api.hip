@@ -13,6 +13,7 @@
 #include "fft.hpp"
 #include "kernels_bf.hpp"
 #include "kernels_df.hpp"
+#include "kernels_pix.hpp"
 #include "chol.hpp"
 #include "calib.hpp"
 #include "mlp.hpp"
@@ -107,7 +108,8 @@ template <class T> apic_status upload_vec(const std::vector<T> &v, void **dst) {
 }
 
 void free_geom(GeomPlan &g) {
-  void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords, &g.d_masks};
+  void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords, &g.d_masks,
+                   &g.d_pix_tab, &g.d_pix_ginv};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -190,6 +192,7 @@ ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, 
   a.r2 = (int)g.r2;
   a.r = (float)g.r;
   a.inv_r = (float)(1.0 / g.r);
+  a.r_d = g.r;
   a.log_floor_rel = (float)g.log_floor_rel;
   a.n_rows = g.n_rows;
   a.n_chunks = g.n_chunks;
@@ -226,6 +229,9 @@ ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, 
   a.known_at = (const int16_t *)g.d_known_at;
   a.coords = (const uint32_t *)g.d_coords;
   a.masks = (const uint64_t *)g.d_masks;
+  a.n_pix = g.pix_ok ? g.n_pix : 0;
+  a.pix_tab = (const uint32_t *)g.d_pix_tab;
+  a.pix_ginv = (const double *)g.d_pix_ginv;
   return a;
 }
 
@@ -460,7 +466,7 @@ apic_status run_output(const ClassArgs &a, const c32 *src, float *field, hipStre
 
 enum Stage : unsigned {
   S_KK = 1, S_PUPIL = 2, S_COEF_IN = 4, S_STITCH = 8, S_SPEC_IN = 16, S_DF = 32, S_SPEC_OUT = 64,
-  S_OUT = 128, S_SUR = 256, S_BG = 512
+  S_OUT = 128, S_SUR = 256, S_BG = 512, S_PIX = 1024
 };
 
 struct CallIO {
@@ -472,6 +478,10 @@ struct CallIO {
   SurrogateArgs sur{};
   float *zcf = nullptr, *zsur = nullptr;
   float *bg_out = nullptr;
+  float *phi_out = nullptr;
+  int32_t *pix_iters = nullptr;
+  double pix_tol = 1e-10;
+  int pix_max_iter = 1000;
 };
 
 template <int N>
@@ -489,6 +499,14 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
   if (st_mask & S_PUPIL) {
     rc = run_pupil(a, io.seed, io.zout, io.diag, io.feat, st);
     if (rc) return rc;
+  }
+  if (st_mask & S_PIX) {
+    if (a.n_pix == 0) return APIC_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_pix_rows, dim3(a.T * a.n_chunks), dim3(256), 0, st, a);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_pix_cg, dim3(a.T), dim3(kPixThreads), 0, st, a, io.pix_tol,
+                       io.pix_max_iter, io.phi_out, io.zout, io.pix_iters);
+    APIC_LAUNCHED();
   }
   if (st_mask & S_SUR) {
     hipLaunchKernelGGL(k_surrogate_predict, dim3(blocks_for(a.T, kMlpTile)), dim3(256), 0, st, a,
@@ -714,7 +732,8 @@ apic_status apic_plan_upload(apic_plan *plan) {
     apic_status rc;
     if ((rc = upload_vec(g.row_il, &g.d_row_il)) || (rc = upload_vec(g.row_k, &g.d_row_k)) ||
         (rc = upload_vec(g.known_at, &g.d_known_at)) || (rc = upload_vec(g.coords, &g.d_coords)) ||
-        (rc = upload_vec(g.masks, &g.d_masks))) {
+        (rc = upload_vec(g.masks, &g.d_masks)) || (rc = upload_vec(g.pix_tab, &g.d_pix_tab)) ||
+        (rc = upload_vec(g.pix_ginv, &g.d_pix_ginv))) {
       for (GeomPlan &h : plan->geoms) free_geom(h);
       return rc;
     }
@@ -823,6 +842,27 @@ apic_status apic_background_stat(const apic_plan *plan, int32_t n_tiles,
   io.bg_out = stat_out;
   return run_call(plan, n_tiles, tiles, images, nullptr, workspace, workspace_bytes, stream, S_BG,
                   io);
+}
+
+apic_status apic_estimate_pupil_pixel(const apic_plan *plan, int32_t n_tiles,
+                                      const apic_tile_desc *tiles, const float *images,
+                                      double tol, int32_t max_iter, float *phi_out,
+                                      float *zernike_out, int32_t *iters_out,
+                                      uint32_t *tile_status, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+  if (n_tiles > 0 && (!images || !phi_out || !zernike_out || !tile_status)) return APIC_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0) || max_iter < 1) return APIC_EINVAL;
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  if (plan->geoms.size() != 1) return APIC_EUNSUPPORTED;
+  if (!plan->geoms[0].pix_ok) return APIC_EUNSUPPORTED;
+  CallIO io;
+  io.phi_out = phi_out;
+  io.zout = zernike_out;
+  io.pix_iters = iters_out;
+  io.pix_tol = tol;
+  io.pix_max_iter = max_iter;
+  return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
+                  S_KK | S_PIX, io);
 }
 
 apic_status apic_kk_spectra(const apic_plan *plan, int32_t n_tiles, const apic_tile_desc *tiles,

@@ -72,6 +72,7 @@ struct ClassArgs {
   int n, nf, n_bf, n_df, n_img, T;
   int r2;                 // Circ(k) <=> kx^2 + ky^2 <= r2
   float r, inv_r;
+  double r_d;             // pupil radius in double precision
   float log_floor_rel;
   int n_rows, n_chunks, nu_pad;
   double ridge_pupil, ridge_df;
@@ -93,6 +94,9 @@ struct ClassArgs {
   const int16_t *known_at;        // N*N
   const uint32_t *coords;         // darkfield coordinate lists
   const uint64_t *masks;          // darkfield block-sparsity masks
+  int n_pix;                      // pupil pixels of the pixel-domain solve (0: unsupported)
+  const uint32_t *pix_tab;        // pixel k, per-row pixel pairs, LED pixels
+  const double *pix_ginv;         // inverse Gram matrix of Z_1..Z_15 over the pixels
 
   __device__ __forceinline__ char *tile(int t) const { return ws + (int64_t)t * stride; }
   template <class T> __device__ __forceinline__ T *at(int t, int64_t off) const {

@@ -52,6 +52,84 @@ int radial_band(int ky, int kx, double r) {
 
 }  // namespace
 
+// Orthonormal Noll Z_1..Z_15 at (X, Y) = k / r, Cartesian form (host, double).
+static void zernike15_host(double X, double Y, double z[15]) {
+  const double r2 = X * X + Y * Y;
+  const double c2 = X * X - Y * Y, s2 = 2.0 * X * Y;
+  const double c3 = X * c2 - Y * s2, s3 = X * s2 + Y * c2;
+  const double c4 = X * c3 - Y * s3, s4 = X * s3 + Y * c3;
+  const double k3 = std::sqrt(3.0), k5 = std::sqrt(5.0), k6 = std::sqrt(6.0), k8 = std::sqrt(8.0),
+               k10 = std::sqrt(10.0);
+  z[0] = 1.0;
+  z[1] = 2.0 * X;
+  z[2] = 2.0 * Y;
+  z[3] = k3 * (2.0 * r2 - 1.0);
+  z[4] = k6 * s2;
+  z[5] = k6 * c2;
+  z[6] = k8 * (3.0 * r2 - 2.0) * Y;
+  z[7] = k8 * (3.0 * r2 - 2.0) * X;
+  z[8] = k8 * s3;
+  z[9] = k8 * c3;
+  z[10] = k5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
+  z[11] = k10 * (4.0 * r2 - 3.0) * c2;
+  z[12] = k10 * (4.0 * r2 - 3.0) * s2;
+  z[13] = k10 * c4;
+  z[14] = k10 * s4;
+}
+
+// Pixel tables of the pixel-domain pupil solve (see GeomPlan).
+static void build_pixel_tables(GeomPlan &p, int n_bf) {
+  const int n = p.n, h = n / 2;
+  std::vector<int32_t> at(size_t(n) * n, -1);  // centred layout
+  std::vector<uint32_t> pix;
+  for (int ky = -h; ky < h; ++ky)
+    for (int kx = -h; kx < h; ++kx)
+      if (int64_t(kx) * kx + int64_t(ky) * ky <= p.r2) {
+        at[size_t(ky + h) * n + (kx + h)] = int32_t(pix.size());
+        pix.push_back(pack_k(ky, kx));
+      }
+  p.n_pix = int(pix.size());
+  p.pix_ok = p.n_pix <= kPixMax && p.n_rows > 0;
+  p.pix_tab.clear();
+  p.pix_ginv.clear();
+  if (!p.pix_ok) return;
+  auto idx = [&](int ky, int kx) { return uint32_t(at[size_t(ky + h) * n + (kx + h)]); };
+  p.pix_tab = pix;
+  for (int rI = 0; rI < p.n_rows; ++rI) {
+    const int i = p.row_il[rI] & 0xff, l = (p.row_il[rI] >> 8) & 0xff;
+    const int Ky = unpack_ky(p.row_k[rI]), Kx = unpack_kx(p.row_k[rI]);
+    const uint32_t a = idx(Ky + p.kbf[2 * i + 1], Kx + p.kbf[2 * i]);
+    const uint32_t b = idx(Ky + p.kbf[2 * l + 1], Kx + p.kbf[2 * l]);
+    p.pix_tab.push_back(a | (b << 16));
+  }
+  for (int i = 0; i < n_bf; ++i) p.pix_tab.push_back(idx(p.kbf[2 * i + 1], p.kbf[2 * i]));
+  // Gram matrix of Z_1..Z_15 over the pixels and its inverse (Gauss-Jordan)
+  double G[15][30] = {};
+  for (uint32_t w : pix) {
+    double z[15];
+    zernike15_host(unpack_kx(w) / p.r, unpack_ky(w) / p.r, z);
+    for (int a = 0; a < 15; ++a)
+      for (int b = 0; b < 15; ++b) G[a][b] += z[a] * z[b];
+  }
+  for (int a = 0; a < 15; ++a) G[a][15 + a] = 1.0;
+  for (int c = 0; c < 15; ++c) {
+    int piv = c;
+    for (int a = c + 1; a < 15; ++a)
+      if (std::fabs(G[a][c]) > std::fabs(G[piv][c])) piv = a;
+    if (piv != c)
+      for (int b = 0; b < 30; ++b) std::swap(G[c][b], G[piv][b]);
+    const double d = 1.0 / G[c][c];
+    for (int b = 0; b < 30; ++b) G[c][b] *= d;
+    for (int a = 0; a < 15; ++a) {
+      if (a == c) continue;
+      const double f = G[a][c];
+      for (int b = 0; b < 30; ++b) G[a][b] -= f * G[c][b];
+    }
+  }
+  for (int a = 0; a < 15; ++a)
+    for (int b = 0; b < 15; ++b) p.pix_ginv.push_back(G[a][15 + b]);
+}
+
 apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   if (!is_pow2_size(g.n)) return APIC_EUNSUPPORTED;
   if (g.upsample != 1 && g.upsample != 2) return APIC_EUNSUPPORTED;
@@ -123,6 +201,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   }
   p.n_rows = int(p.row_k.size());
   p.n_chunks = std::max(1, (p.n_rows + kAbChunk - 1) / kAbChunk);
+  build_pixel_tables(p, g.n_bf);
 
   // ---- darkfield sets (Eq. 11-13)
   const int nn = n * n;
@@ -329,7 +408,11 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.fimg = take(int64_t(nn) * c64);
   L.ptil = take(int64_t(nn) * c64);
   L.vec = take(int64_t(p.nu_pad) * c64);
-  L.gram = take(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256);
+  // the gram block also serves the pixel-domain pupil solve (a separate call):
+  // per-row weights and phases (float) and two double vectors over the pixels
+  const int64_t pix_need =
+      p.pix_ok ? 2 * align256(int64_t(p.n_rows) * 4) + 2 * align256(int64_t(p.n_pix) * 8) : 0;
+  L.gram = take(std::max<int64_t>(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256, pix_need));
   L.linv = take(int64_t(p.nu_pad / kGramBlock) * kGramBlock * kGramBlock * c64);
   L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);
   L.sums = take(128 * 8);

@@ -21,6 +21,7 @@ constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
 constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
 constexpr int kEChunk = 2;          // E rows per gram k-chunk
+constexpr int kPixMax = 7936;       // pupil pixels of the pixel-domain solve (LDS bound)
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
 // Signed (ky, kx) packed in one word: low half ky, high half kx (int16 each).
@@ -62,6 +63,16 @@ struct GeomPlan {
   int n_pairs = 0, n_rows = 0, n_chunks = 0;
   std::vector<uint32_t> row_il;      // i | l << 8 | feature cell << 16
   std::vector<uint32_t> row_k;       // packed K
+  // pupil pixels (Eq. 10 with one unknown per pixel), raster order over the
+  // disk (ky ascending, then kx): built when n_pix <= kPixMax.  pix_tab holds
+  // the pixels' packed k, then per pupil row the pixel indices of K + K_i
+  // (low half) and K + K_l (high half), then the pixel index of each
+  // NA-matched k_i.  pix_ginv is the inverse Gram matrix of Noll Z_1..Z_15 over
+  // the pixels (15 x 15, row-major), for the Zernike summary.
+  int n_pix = 0;
+  bool pix_ok = false;
+  std::vector<uint32_t> pix_tab;
+  std::vector<double> pix_ginv;
   // darkfield (Eq. 11-13)
   std::vector<int16_t> known_at;     // N*N in FFT order: -1 brightfield, j solved at step j,
                                      // 32767 never known
@@ -73,7 +84,7 @@ struct GeomPlan {
   TileLayout lay;
   // device copies (owned; filled by upload)
   void *d_row_il = nullptr, *d_row_k = nullptr, *d_known_at = nullptr, *d_coords = nullptr,
-       *d_masks = nullptr;
+       *d_masks = nullptr, *d_pix_tab = nullptr, *d_pix_ginv = nullptr;
 };
 
 // Build the host tables of one geometry; returns APIC_OK or an error code.

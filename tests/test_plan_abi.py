@@ -121,6 +121,18 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     descs[1].image_offset += 2
     rc = lib.apic_background_stat(plan.handle, 2, descs, fake, fake, fake, need, None)
     assert rc == apic.APIC_EINVAL
+    # pixel-domain pupil solve: bad tolerance / iteration cap; too many pupil pixels
+    rc = lib.apic_estimate_pupil_pixel(plan.handle, 2, descs, fake, 0.0, 100, fake, fake, None,
+                                       fake, fake, need, None)
+    assert rc == apic.APIC_EINVAL
+    rc = lib.apic_estimate_pupil_pixel(plan.handle, 2, descs, fake, 1e-10, 0, fake, fake, None,
+                                       fake, fake, need, None)
+    assert rc == apic.APIC_EINVAL
+    big = S.small_workload(n=512, n_df=0)
+    plan512 = apic.Plan(big.geometry_kwargs())
+    rc = lib.apic_estimate_pupil_pixel(plan512.handle, 2, descs, fake, 1e-10, 100, fake, fake,
+                                       None, fake, fake, need, None)
+    assert rc == apic.APIC_EUNSUPPORTED
     # streamer: chunk >= 1, 2..4 buffers, geometry in range, null output handle
     h = ctypes.c_void_p()
     for geom, chunk, nbuf in ((0, 0, 3), (0, 4, 1), (0, 4, 5), (1, 4, 3), (-1, 4, 3)):
