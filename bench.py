@@ -81,6 +81,39 @@ def cpu_baseline(images_host, w):
             "sample": f"1 tile of the workload (tile 0), full-Q FP64 oracle, {dt:.1f} s"}
 
 
+def pixel_pupil_timing(plan, images, w, chunk=128):
+    """The pixel-domain pupil solve (Eq. 10, one unknown per pupil pixel) and
+    the Zernike-basis solve over every tile of a single-class workload whose
+    image stacks are contiguous in ``images``, in calls of ``chunk`` tiles;
+    HIP events on the launch stream.  KK is included in both."""
+    import numpy as np
+    import torch
+    from paper_2407_20469_amd import apic
+    per = w.n_img * w.n * w.n
+    T = w.n_tiles
+    views = [images[c0 * per:(c0 + min(chunk, T - c0)) * per].view(-1, w.n_img, w.n, w.n)
+             for c0 in range(0, T, chunk)]
+    ws = apic.Workspace()
+    apic.estimate_pupil_pixel(plan, views[0], workspace=ws)
+    apic.estimate_pupil(plan, views[0], workspace=ws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    out = [apic.estimate_pupil_pixel(plan, v, workspace=ws) for v in views]
+    ev[1].record()
+    for v in views:
+        apic.estimate_pupil(plan, v, workspace=ws)
+    ev[2].record()
+    torch.cuda.synchronize()
+    its = np.concatenate([o[2].cpu().numpy() for o in out])
+    st = np.concatenate([o[3].cpu().numpy() for o in out])
+    return {"tiles": T, "chunk": chunk, "ms": ev[0].elapsed_time(ev[1]),
+            "ms_zernike_basis": ev[1].elapsed_time(ev[2]),
+            "mean_iterations": float(its.mean()), "max_iterations": int(its.max()),
+            "not_converged": int(((st & apic.TILE_PIXEL_NOT_CONVERGED) != 0).sum()),
+            "pixels": int(plan.sizes()["n_pix"]), "rows": int(plan.sizes()["n_rows"])}
+
+
 def train_slide_surrogate(dev, n_train=512, seed=41):
     """Surrogate for the 512 px slide geometry, trained on the GPU on the
     closed-form pupil estimates of brightfield-only content tiles at random
@@ -360,6 +393,13 @@ def main():
     plain_s = (time.perf_counter() - t0) / P
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
 
+    pixel = None
+    if args.workload == "cfg1":
+        pixel = pixel_pupil_timing(plan0, images, w0)
+        log(f"pixel-domain pupil solve: {pixel['ms']:.1f} ms for {pixel['tiles']} tiles "
+            f"(mean {pixel['mean_iterations']:.0f} iterations); Zernike basis "
+            f"{pixel['ms_zernike_basis']:.1f} ms")
+
     # executed gram work: live (block pair, E chunk) triples x chunk x block^2 complex MACs
     gram_exec = 0.0
     for ci, w in enumerate(ws_list):
@@ -424,6 +464,7 @@ def main():
         "roofline": roof,
         "hbm_passes": hbm,
         "kernel_groups": groups,
+        "pixel_pupil": pixel,
     }
     if not args.no_cpu_baseline:
         b0 = int(order[0][0])

@@ -138,7 +138,7 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *          3: darkfield step j's excluded set E     (ky, kx pairs)
  *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs
  *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps,
- *             unknowns per gram block, E rows per gram chunk
+ *             unknowns per gram block, E rows per gram chunk, pupil pixels
  *          6: per darkfield step (N_u, |Q|, |E|, live gram chunks of all lower
  *             block pairs, live gram chunks of the diagonal blocks); U and E
  *             are in the plan's processing order (compact squares), P and Q

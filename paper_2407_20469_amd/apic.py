@@ -226,7 +226,7 @@ class Plan:
     def sizes(self, geom=0):
         v = self.query(5, geom)
         return dict(zip(["n_pairs", "n_rows", "nu_max", "m_max", "ne_max", "n_active", "gram_block",
-                         "gram_chunk"], v.tolist()))
+                         "gram_chunk", "n_pix"], v.tolist()))
 
     def workspace_bytes(self, descs):
         b = ctypes.c_size_t()

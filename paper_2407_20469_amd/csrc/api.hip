@@ -780,7 +780,8 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
       v.push_back((int32_t)(g.row_il[i] >> 16));
     }
   } else if (what == 5) {
-    v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active, kGramUB, kEChunk};
+    v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active, kGramUB, kEChunk,
+         g.n_pix};
   } else if (what == 6) {
     for (const DfStep &d : g.steps) {
       v.push_back(d.nu);
