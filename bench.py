@@ -81,7 +81,7 @@ def cpu_baseline(images_host, w):
             "sample": f"1 tile of the workload (tile 0), full-Q FP64 oracle, {dt:.1f} s"}
 
 
-def pixel_pupil_timing(plan, images, w, chunk=128):
+def pixel_pupil_timing(plan, images, w, chunk=512):
     """The pixel-domain pupil solve (Eq. 10, one unknown per pupil pixel) and
     the Zernike-basis solve over every tile of a single-class workload whose
     image stacks are contiguous in ``images``, in calls of ``chunk`` tiles;

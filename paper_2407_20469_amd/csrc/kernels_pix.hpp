@@ -13,6 +13,8 @@
 namespace apic {
 
 constexpr int kPixThreads = 1024;
+constexpr int kPixWaves = kPixThreads / 64;
+constexpr int kPixUnroll = 4;   // 64-row blocks whose loads a wavefront issues together
 
 __device__ __forceinline__ int pix_pad_f(int n) { return (n + 63) & ~63; }  // 256-byte runs of floats
 __device__ __forceinline__ int pix_pad_d(int n) { return (n + 31) & ~31; }  // of doubles
@@ -71,9 +73,11 @@ __global__ __launch_bounds__(kPixThreads) void k_pix_cg(ClassArgs a, double tol,
   __shared__ double sp[kPixMax], sz[kPixMax];
   __shared__ double red[kPixThreads / 64];
   __shared__ double bc;
+  __shared__ int sled[kMaxBf];
   const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int np = a.n_pix, nr = a.n_rows;
-  const uint32_t *pk = a.pix_tab, *rab = a.pix_tab + np, *led = a.pix_tab + np + nr;
+  const uint32_t *pk = a.pix_tab, *rab = a.pix_tab + np;
+  if (tid < a.n_bf) sled[tid] = (int)a.pix_tab[np + nr + tid];  // LED pixels
   const float *wrow = a.at<float>(t, a.lay.gram);
   const float *brow = wrow + pix_pad_f(nr);
   double *x = reinterpret_cast<double *>(a.tile(t) + a.lay.gram) + pix_pad_f(nr);
@@ -94,40 +98,88 @@ __global__ __launch_bounds__(kPixThreads) void k_pix_cg(ClassArgs a, double tol,
     return out;
   };
 
-  // sz = D^T W beta (rhs) or sz = D^T W D sp
+  // sz = D^T W beta (rhs) or sz = D^T W D sp.  Wavefront v walks rows
+  // [v * per, (v + 1) * per) 64 at a time (coalesced), issuing kPixUnroll
+  // blocks' loads before their LDS work.  Rows are grouped by pair, so the
+  // pair's two LED-pixel terms are summed in registers while the pair lasts
+  // and flushed (one wavefront sum, two atomics) when it changes.
+  auto wave_sum = [&](double v) -> double {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  };
   auto row_pass = [&](bool rhs) {
     for (int j = tid; j < np; j += kPixThreads) sz[j] = 0.0;
     __syncthreads();
-    for (int r0 = 0; r0 < nr; r0 += kPixThreads) {
-      if (r0 + (tid & ~63) >= nr) continue;  // whole wavefront past the end
-      const int row = r0 + tid;
-      double y = 0.0;
-      uint32_t il = 0xffffffffu;
-      if (row < nr) {
-        il = a.row_il[row] & 0xffffu;
-        const uint32_t ab = rab[row];
-        const int pa = ab & 0xffff, pb = ab >> 16;
-        const double w = wrow[row];
-        if (rhs) {
-          y = w * (double)brow[row];
-        } else {
-          const int pc = led[il & 0xff], pd = led[il >> 8];
-          y = w * ((sp[pa] - sp[pb]) - (sp[pc] - sp[pd]));
+    const int per = (nr + kPixWaves - 1) / kPixWaves;
+    const int beg = (tid >> 6) * per, end = min(nr, beg + per);
+    uint32_t cur = 0xffffffffu;  // pair being summed (wavefront-uniform)
+    double dcur = 0.0;           // sp[LED i] - sp[LED l] of that pair
+    double acc = 0.0;
+    for (int s0 = beg; s0 < end; s0 += 64 * kPixUnroll) {
+      uint32_t il[kPixUnroll], ab[kPixUnroll];
+      float wv[kPixUnroll], bv[kPixUnroll];
+#pragma unroll
+      for (int u = 0; u < kPixUnroll; ++u) {
+        const int row = s0 + u * 64 + lane;
+        il[u] = 0xffffffffu;
+        ab[u] = 0u;
+        wv[u] = 0.f;
+        bv[u] = 0.f;
+        if (row < end) {
+          il[u] = a.row_il[row] & 0xffffu;
+          ab[u] = rab[row];
+          wv[u] = wrow[row];
+          if (rhs) bv[u] = brow[row];
         }
-        atomicAdd(&sz[pa], y);
-        atomicAdd(&sz[pb], -y);
       }
-      // the K_i / K_l terms hit two LED pixels per pair: summed over the
-      // wavefront's rows of lane 0's pair, one update per wavefront
-      const uint32_t il0 = __shfl(il, 0);
-      double s = il == il0 ? y : 0.0;
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+#pragma unroll
+      for (int u = 0; u < kPixUnroll; ++u) {
+        if (s0 + u * 64 >= end) break;  // wavefront-uniform
+        const bool live = il[u] != 0xffffffffu;
+        const int pa = ab[u] & 0xffff, pb = ab[u] >> 16;
+        if (__all(!live || il[u] == cur)) {
+          if (live) {
+            const double y = rhs ? (double)wv[u] * (double)bv[u]
+                                 : (double)wv[u] * ((sp[pa] - sp[pb]) - dcur);
+            atomicAdd(&sz[pa], y);
+            atomicAdd(&sz[pb], -y);
+            acc += y;
+          }
+          continue;
+        }
+        // the pair changes inside this block: flush the running sum, then
+        // continue with the pair of the block's last live row
+        double y = 0.0;
+        if (live) {
+          y = rhs ? (double)wv[u] * (double)bv[u]
+                  : (double)wv[u] * ((sp[pa] - sp[pb]) - (sp[sled[il[u] & 0xff]] - sp[sled[il[u] >> 8]]));
+          atomicAdd(&sz[pa], y);
+          atomicAdd(&sz[pb], -y);
+        }
+        if (cur != 0xffffffffu) {
+          const double sum = wave_sum(acc);
+          if (lane == 0) {
+            atomicAdd(&sz[sled[cur & 0xff]], -sum);
+            atomicAdd(&sz[sled[cur >> 8]], sum);
+          }
+        }
+        const int last = min(63, end - 1 - (s0 + u * 64));
+        cur = __shfl(il[u], last);
+        dcur = rhs ? 0.0 : sp[sled[cur & 0xff]] - sp[sled[cur >> 8]];
+        acc = 0.0;
+        if (live && il[u] == cur) {
+          acc = y;
+        } else if (live) {
+          atomicAdd(&sz[sled[il[u] & 0xff]], -y);
+          atomicAdd(&sz[sled[il[u] >> 8]], y);
+        }
+      }
+    }
+    if (cur != 0xffffffffu) {
+      const double sum = wave_sum(acc);
       if (lane == 0) {
-        atomicAdd(&sz[led[il0 & 0xff]], -s);
-        atomicAdd(&sz[led[il0 >> 8]], s);
-      } else if (row < nr && il != il0) {
-        atomicAdd(&sz[led[il & 0xff]], -y);
-        atomicAdd(&sz[led[il >> 8]], y);
+        atomicAdd(&sz[sled[cur & 0xff]], -sum);
+        atomicAdd(&sz[sled[cur >> 8]], sum);
       }
     }
     __syncthreads();
