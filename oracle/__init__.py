@@ -14,6 +14,7 @@ closed-form solution", arXiv 2407.20469):
   darkfield extension .. Sec. 2.3, Eq. 11-13          (darkfield.py)
   upsampled output ..... Sec. 2.3, end of brightfield part (output.py)
   background test ...... Sec. 3.2, variance threshold (background.py)
+  patch assembly ....... Sec. 2.5, overlap blending  (assemble.py)
   surrogate MLP twin ... not in the paper             (mlp.py)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
