@@ -10,8 +10,9 @@ Readings taken (the paper describes the blend only in words):
   each tile's DC phase independently), so tiles are first brought to a common
   phase: with C_tu = sum over the overlap of F_t conj(F_u), the phases theta
   maximise sum_tu Re(C_tu exp(-j (theta_t - theta_u))), i.e. exp(j theta) is
-  the leading eigenvector of the Hermitian matrix C (angular synchronisation),
-  with theta_0 = 0;
+  the leading eigenvector of the Hermitian matrix C (angular synchronisation).
+  Each connected group of overlapping tiles is synchronised on its own, its
+  lowest-numbered tile at phase 0 (a tile with no neighbour keeps phase 0);
 * the blend is a normalised weighted sum: canvas(p) = sum_t w_t(p) F_t(p)
   exp(-j theta_t) / sum_t w_t(p), zero where no tile covers p, with the
   separable ramp w(y, x) = ramp(y) ramp(x), ramp(v) = min(1, (v + 1/2) / R,
@@ -42,11 +43,30 @@ def overlap_matrix(fields, pos, min_overlap=1):
 
 
 def synchronise_phases(C):
-    """theta (T,) from the leading eigenvector of C, rotated so theta_0 = 0."""
-    ev, V = np.linalg.eigh(C)
-    v = V[:, -1]
-    v = v * np.exp(-1j * np.angle(v[0]))
-    return np.angle(v)
+    """theta (T,): per connected group of C's graph, the phases of the leading
+    eigenvector of the group's block, rotated so its first tile is at 0."""
+    T = C.shape[0]
+    theta = np.zeros(T)
+    seen = np.zeros(T, bool)
+    for s in range(T):
+        if seen[s]:
+            continue
+        group, stack = [], [s]
+        seen[s] = True
+        while stack:
+            t = stack.pop()
+            group.append(t)
+            for u in np.nonzero(C[t] != 0)[0]:
+                if not seen[u]:
+                    seen[u] = True
+                    stack.append(u)
+        group = sorted(group)
+        if len(group) == 1:
+            continue
+        ev, V = np.linalg.eigh(C[np.ix_(group, group)])
+        v = V[:, -1]
+        theta[group] = np.angle(v * np.exp(-1j * np.angle(v[0])))
+    return theta
 
 
 def ramp(n, width):

@@ -47,6 +47,23 @@ def test_cut_tiles_reassemble_exactly(width):
     assert np.abs(out - ref).max() < 1e-12
 
 
+def test_separate_groups_synchronise_on_their_own():
+    """Two 2 x 2 groups far apart: each group's phases come back relative to
+    its own first tile."""
+    n, stride = 16, 12
+    field = _field((100, 100), seed=8)
+    pos = np.array([[0, 0], [0, stride], [stride, 0], [stride, stride],
+                    [60, 60], [60, 60 + stride], [60 + stride, 60], [60 + stride, 60 + stride]])
+    tiles = np.stack([field[y:y + n, x:x + n] for y, x in pos])
+    phases = np.random.default_rng(2).uniform(-np.pi, np.pi, len(pos))
+    theta = oa.synchronise_phases(oa.overlap_matrix(tiles * np.exp(1j * phases)[:, None, None], pos))
+    for g in (range(0, 4), range(4, 8)):
+        g = list(g)
+        d = np.angle(np.exp(1j * (theta[g] - (phases[g] - phases[g[0]]))))
+        assert np.abs(d).max() < 1e-12
+    assert theta[0] == 0 and theta[4] == 0
+
+
 def test_single_tile_and_uncovered_canvas():
     n = 16
     tile = _field((n, n), seed=3)[None]
