@@ -309,6 +309,39 @@ apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *ima
  * tuning classes one by one).  APIC_EINVAL if one tile per class does not fit. */
 apic_status apic_batch_fit(apic_batch *batch, size_t workspace_bytes);
 
+/* ---------------------------------------------------------- patch assembly
+ * Tiles placed at known canvas positions with blended overlaps (Sec. 2.5:
+ * adjacent scans keep overlapping regions, blended to hide the seams; a tile
+ * with no neighbour is placed by its scan position).  Registration by image
+ * features is not done here: positions are given.
+ *   fields  complex64 [T][n][n] (device), tile t at fields + 2 * t * n * n
+ *           (e.g. the fN x fN fields of a single-geometry reconstruction)
+ *   pos     int32 [T][2] (host): canvas row and column of each tile's [0][0]
+ * Every reconstructed tile carries its own constant phase (KK fixes each
+ * tile's DC phase), so tiles are brought to a common phase first.
+ * apic_assemble_phases: C_tu = sum over the overlap of F_t conj(F_u) for every
+ * pair sharing at least min_overlap rows and columns (FP64 sums on the
+ * GPU); then, on the host, theta = the phases of the leading eigenvector of
+ * C (angular synchronisation) per connected group of overlapping tiles, the
+ * group's lowest-numbered tile at 0 (a tile with no neighbour gets 0).
+ * theta_out float [T] (host).  Synchronises the host with `stream`.
+ * apic_blend: canvas(p) = sum_t w_t(p) F_t(p) exp(-j theta_t) / sum_t w_t(p)
+ * (0 where no tile covers p), w = ramp(y) ramp(x) over each tile, ramp(v) =
+ * min(1, (v + 1/2) / R, (n - v - 1/2) / R), R = ramp_width >= 1; theta host
+ * [T] or NULL (all 0); canvas complex64 [canvas_h][canvas_w] (device); tiles
+ * may reach outside the canvas.  Both calls upload small host-built lists to
+ * the workspace (apic_assemble_workspace_bytes, 256-byte aligned) with
+ * blocking copies after draining `stream`, so they are not capturable. */
+apic_status apic_assemble_workspace_bytes(int32_t n_tiles, int32_t n, const int32_t *pos,
+                                          int32_t min_overlap, int32_t canvas_h,
+                                          int32_t canvas_w, size_t *bytes);
+apic_status apic_assemble_phases(int32_t n_tiles, int32_t n, const float *fields,
+                                 const int32_t *pos, int32_t min_overlap, float *theta_out,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+apic_status apic_blend(int32_t n_tiles, int32_t n, const float *fields, const int32_t *pos,
+                       const float *theta, float ramp_width, float *canvas, int32_t canvas_h,
+                       int32_t canvas_w, void *workspace, size_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------- surrogate
  * Learned Zernike surrogate (not part of the paper's method): a perceptron
  * 34 -> 128 -> 128 -> 12 (ReLU) from (tile x, tile y, the 32 features of

@@ -43,7 +43,8 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
            "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
-           "apic_estimate_pupil_pixel",
+           "apic_estimate_pupil_pixel", "apic_assemble_workspace_bytes",
+           "apic_assemble_phases", "apic_blend",
            "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
            "apic_streamer_run", "apic_version"]
 
@@ -133,6 +134,10 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
+    lib.apic_assemble_workspace_bytes.argtypes = [i32, i32, P, i32, i32, i32,
+                                                  ctypes.POINTER(sz)]
+    lib.apic_assemble_phases.argtypes = [i32, i32, P, P, i32, P, P, sz, P]
+    lib.apic_blend.argtypes = [i32, i32, P, P, P, ctypes.c_float, P, i32, i32, P, sz, P]
     lib.apic_estimate_pupil_pixel.argtypes = [P, i32, ctypes.POINTER(TileDesc), P,
                                               ctypes.c_double, i32, P, P, P, P, P, sz, P]
     lib.apic_streamer_create.argtypes = [P, i32, i32, i32, ctypes.POINTER(P)]
@@ -474,6 +479,38 @@ def estimate_pupil_pixel(plan, images, tol=1e-10, max_iter=1000, workspace=None,
         plan.handle, T, descs, _ptr(images), float(tol), int(max_iter), _ptr(phi), _ptr(zern),
         _ptr(iters), _ptr(status), wp, wb, _stream(stream)))
     return phi, zern, iters, status
+
+
+def assemble(fields, positions, canvas_shape, ramp_width, min_overlap=1, align_phases=True,
+             workspace=None, stream=None):
+    """Blend tiles (complex64 CUDA tensor (T, n, n)) placed at integer canvas
+    positions (T, 2) (row, column) into a complex64 canvas; the tiles are first
+    brought to a common constant phase unless ``align_phases`` is False.
+    Returns (canvas, theta)."""
+    import torch
+    lib = load_library()
+    f = fields.contiguous()
+    if f.dtype != torch.complex64 or not f.is_cuda or f.dim() != 3 or f.shape[1] != f.shape[2]:
+        raise ValueError("fields must be a complex64 CUDA tensor (T, n, n)")
+    T, n = f.shape[0], f.shape[1]
+    pos = np.ascontiguousarray(np.asarray(positions, np.int32).reshape(T, 2))
+    H, W = int(canvas_shape[0]), int(canvas_shape[1])
+    pp = pos.ctypes.data_as(ctypes.c_void_p)
+    b = ctypes.c_size_t()
+    _check("apic_assemble_workspace_bytes", lib.apic_assemble_workspace_bytes(
+        T, n, pp, int(min_overlap), H, W, ctypes.byref(b)))
+    ws = workspace or Workspace()
+    wp, wb = ws.get(b.value, f.device)
+    theta = np.zeros(T, np.float32)
+    if align_phases:
+        _check("apic_assemble_phases", lib.apic_assemble_phases(
+            T, n, _ptr(f), pp, int(min_overlap), theta.ctypes.data_as(ctypes.c_void_p), wp, wb,
+            _stream(stream)))
+    canvas = torch.empty((H, W), dtype=torch.complex64, device=f.device)
+    _check("apic_blend", lib.apic_blend(
+        T, n, _ptr(f), pp, theta.ctypes.data_as(ctypes.c_void_p), float(ramp_width),
+        _ptr(canvas), H, W, wp, wb, _stream(stream)))
+    return canvas, theta
 
 
 def background_stat(plan, images, workspace=None, stream=None):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <complex>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -14,6 +15,7 @@
 #include "kernels_bf.hpp"
 #include "kernels_df.hpp"
 #include "kernels_pix.hpp"
+#include "kernels_asm.hpp"
 #include "chol.hpp"
 #include "calib.hpp"
 #include "mlp.hpp"
@@ -1703,4 +1705,209 @@ apic_status apic_streamer_run(apic_streamer *s, int32_t n_tiles, const float *co
     }
   }
   return rc;
+}
+
+// ------------------------------------------------------------ patch assembly
+namespace {
+
+bool asm_args_ok(int32_t T, int32_t n, const int32_t *pos) {
+  return T >= 0 && n >= 1 && n <= 4096 && (T == 0 || pos);
+}
+
+// Overlapping pairs (t < u) with at least min_ov rows and columns in common.
+std::vector<apic::AsmPair> asm_pairs(int32_t T, int32_t n, const int32_t *pos, int32_t min_ov) {
+  std::vector<apic::AsmPair> out;
+  for (int t = 0; t < T; ++t)
+    for (int u = t + 1; u < T; ++u) {
+      const int y0 = std::max(pos[2 * t], pos[2 * u]), y1 = std::min(pos[2 * t], pos[2 * u]) + n;
+      const int x0 = std::max(pos[2 * t + 1], pos[2 * u + 1]),
+                x1 = std::min(pos[2 * t + 1], pos[2 * u + 1]) + n;
+      if (y1 - y0 >= min_ov && x1 - x0 >= min_ov) out.push_back({t, u, y0, y1, x0, x1});
+    }
+  return out;
+}
+
+// Per canvas block (kAsmBlock square, row-major) the tiles that cover part of it.
+void asm_blocks(int32_t T, int32_t n, const int32_t *pos, int32_t H, int32_t W,
+                std::vector<int32_t> &start, std::vector<int32_t> &tiles) {
+  const int bh = (H + apic::kAsmBlock - 1) / apic::kAsmBlock;
+  const int bw = (W + apic::kAsmBlock - 1) / apic::kAsmBlock;
+  std::vector<std::vector<int32_t>> lists((size_t)bh * bw);
+  for (int t = 0; t < T; ++t) {
+    const int y0 = std::max(0, pos[2 * t]), y1 = std::min(H, pos[2 * t] + n);
+    const int x0 = std::max(0, pos[2 * t + 1]), x1 = std::min(W, pos[2 * t + 1] + n);
+    if (y0 >= y1 || x0 >= x1) continue;
+    for (int by = y0 / apic::kAsmBlock; by <= (y1 - 1) / apic::kAsmBlock; ++by)
+      for (int bx = x0 / apic::kAsmBlock; bx <= (x1 - 1) / apic::kAsmBlock; ++bx)
+        lists[(size_t)by * bw + bx].push_back(t);
+  }
+  start.assign(lists.size() + 1, 0);
+  tiles.clear();
+  for (size_t b = 0; b < lists.size(); ++b) {
+    tiles.insert(tiles.end(), lists[b].begin(), lists[b].end());
+    start[b + 1] = (int32_t)tiles.size();
+  }
+}
+
+int64_t asm_phase_bytes(int32_t T, size_t P) {
+  return align256(8 * (int64_t)T) + align256(24 * (int64_t)P) + align256(16 * (int64_t)P);
+}
+int64_t asm_blend_bytes(int32_t T, size_t nb, size_t L) {
+  return align256(8 * (int64_t)T) + align256(4 * (int64_t)(nb + 1)) + align256(4 * (int64_t)L) +
+         align256(8 * (int64_t)T);
+}
+
+// Leading eigenvector phases of each connected group of the overlap graph
+// (angular synchronisation), the group's lowest tile at 0.  Power iteration
+// on C + sigma I (sigma = the largest absolute row sum, so every eigenvalue is
+// >= 0 and the largest one leads) from the phases propagated along a
+// breadth-first tree of the group.
+void asm_synchronise(int32_t T, const std::vector<apic::AsmPair> &pairs,
+                     const std::vector<c64> &corr, float *theta) {
+  std::vector<std::vector<std::pair<int, std::complex<double>>>> adj(T);
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    const std::complex<double> c(corr[k].x, corr[k].y);
+    if (c == 0.0) continue;
+    adj[pairs[k].t].push_back({pairs[k].u, c});
+    adj[pairs[k].u].push_back({pairs[k].t, std::conj(c)});
+  }
+  std::vector<int> group_of(T, -1);
+  for (int s = 0; s < T; ++s) theta[s] = 0.f;
+  for (int s = 0; s < T; ++s) {
+    if (group_of[s] >= 0) continue;
+    std::vector<int> order{s};
+    std::vector<std::complex<double>> v0;
+    group_of[s] = s;
+    std::vector<double> phi(T, 0.0);
+    for (size_t h = 0; h < order.size(); ++h) {
+      const int t = order[h];
+      for (const auto &e : adj[t])
+        if (group_of[e.first] < 0) {
+          group_of[e.first] = s;
+          phi[e.first] = phi[t] - std::arg(e.second);  // C_tu ~ exp(j (theta_t - theta_u))
+          order.push_back(e.first);
+        }
+    }
+    if (order.size() == 1) continue;
+    std::sort(order.begin(), order.end());
+    std::vector<int> local(T, -1);
+    for (size_t i = 0; i < order.size(); ++i) local[order[i]] = (int)i;
+    double sigma = 0.0;
+    for (int t : order) {
+      double row = 0.0;
+      for (const auto &e : adj[t]) row += std::abs(e.second);
+      sigma = std::max(sigma, row);
+    }
+    const size_t m = order.size();
+    std::vector<std::complex<double>> v(m), w(m);
+    for (size_t i = 0; i < m; ++i) v[i] = std::polar(1.0, phi[order[i]]);
+    for (int it = 0; it < 200000; ++it) {
+      double nrm = 0.0;
+      for (size_t i = 0; i < m; ++i) {
+        std::complex<double> acc = sigma * v[i];
+        for (const auto &e : adj[order[i]]) acc += e.second * v[local[e.first]];
+        w[i] = acc;
+        nrm = std::max(nrm, std::abs(acc));
+      }
+      double change = 0.0;
+      for (size_t i = 0; i < m; ++i) {
+        w[i] /= nrm;
+        change = std::max(change, std::abs(w[i] - v[i]));
+      }
+      v.swap(w);
+      if (change < 1e-14) break;
+    }
+    const std::complex<double> ref = std::conj(v[0]) / std::abs(v[0]);
+    for (size_t i = 0; i < m; ++i) theta[order[i]] = (float)std::arg(v[i] * ref);
+  }
+}
+
+}  // namespace
+
+apic_status apic_assemble_workspace_bytes(int32_t n_tiles, int32_t n, const int32_t *pos,
+                                          int32_t min_overlap, int32_t canvas_h,
+                                          int32_t canvas_w, size_t *bytes) {
+  if (!bytes || !asm_args_ok(n_tiles, n, pos) || canvas_h < 0 || canvas_w < 0) return APIC_EINVAL;
+  const std::vector<AsmPair> pairs = asm_pairs(n_tiles, n, pos, std::max(1, min_overlap));
+  std::vector<int32_t> start, tiles;
+  asm_blocks(n_tiles, n, pos, canvas_h, canvas_w, start, tiles);
+  *bytes = (size_t)std::max<int64_t>(
+      256, std::max(asm_phase_bytes(n_tiles, pairs.size()),
+                    asm_blend_bytes(n_tiles, start.size() - 1, tiles.size())));
+  return APIC_OK;
+}
+
+apic_status apic_assemble_phases(int32_t n_tiles, int32_t n, const float *fields,
+                                 const int32_t *pos, int32_t min_overlap, float *theta_out,
+                                 void *workspace, size_t workspace_bytes, void *stream) {
+  if (!asm_args_ok(n_tiles, n, pos) || (n_tiles > 0 && (!fields || !theta_out)))
+    return APIC_EINVAL;
+  const std::vector<AsmPair> pairs = asm_pairs(n_tiles, n, pos, std::max(1, min_overlap));
+  for (int t = 0; t < n_tiles; ++t) theta_out[t] = 0.f;
+  if (pairs.empty()) return APIC_OK;
+  if (!workspace || (int64_t)workspace_bytes < asm_phase_bytes(n_tiles, pairs.size()) ||
+      (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return APIC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *ws = reinterpret_cast<char *>(workspace);
+  int32_t *d_pos = reinterpret_cast<int32_t *>(ws);
+  AsmPair *d_pairs = reinterpret_cast<AsmPair *>(ws + align256(8 * (int64_t)n_tiles));
+  c64 *d_corr = reinterpret_cast<c64 *>(ws + align256(8 * (int64_t)n_tiles) +
+                                        align256(24 * (int64_t)pairs.size()));
+  // the workspace may still be read by earlier work on the stream
+  APIC_HIP(hipStreamSynchronize(st));
+  APIC_HIP(hipMemcpy(d_pos, pos, 8 * (size_t)n_tiles, hipMemcpyHostToDevice));
+  APIC_HIP(hipMemcpy(d_pairs, pairs.data(), sizeof(AsmPair) * pairs.size(), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_overlap_corr, dim3((unsigned)pairs.size()), dim3(256), 0, st,
+                     reinterpret_cast<const c32 *>(fields), n, d_pos, d_pairs, d_corr);
+  APIC_LAUNCHED();
+  std::vector<c64> corr(pairs.size());
+  APIC_HIP(hipStreamSynchronize(st));
+  APIC_HIP(hipMemcpy(corr.data(), d_corr, sizeof(c64) * pairs.size(), hipMemcpyDeviceToHost));
+  asm_synchronise(n_tiles, pairs, corr, theta_out);
+  return APIC_OK;
+}
+
+apic_status apic_blend(int32_t n_tiles, int32_t n, const float *fields, const int32_t *pos,
+                       const float *theta, float ramp_width, float *canvas, int32_t canvas_h,
+                       int32_t canvas_w, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!asm_args_ok(n_tiles, n, pos) || canvas_h < 1 || canvas_w < 1 || !canvas ||
+      !(ramp_width >= 1.f) || (n_tiles > 0 && !fields))
+    return APIC_EINVAL;
+  std::vector<int32_t> start, tiles;
+  asm_blocks(n_tiles, n, pos, canvas_h, canvas_w, start, tiles);
+  const size_t nb = start.size() - 1;
+  if (!workspace || (int64_t)workspace_bytes < asm_blend_bytes(n_tiles, nb, tiles.size()) ||
+      (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return APIC_EINVAL;
+  std::vector<float> rot(2 * (size_t)n_tiles);
+  for (int t = 0; t < n_tiles; ++t) {
+    const double th = theta ? theta[t] : 0.0;
+    rot[2 * t] = (float)std::cos(th);
+    rot[2 * t + 1] = (float)-std::sin(th);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *ws = reinterpret_cast<char *>(workspace);
+  int64_t o = 0;
+  int32_t *d_pos = reinterpret_cast<int32_t *>(ws + o);
+  o += align256(8 * (int64_t)n_tiles);
+  int32_t *d_start = reinterpret_cast<int32_t *>(ws + o);
+  o += align256(4 * (int64_t)(nb + 1));
+  int32_t *d_tiles = reinterpret_cast<int32_t *>(ws + o);
+  o += align256(4 * (int64_t)tiles.size());
+  c32 *d_rot = reinterpret_cast<c32 *>(ws + o);
+  APIC_HIP(hipStreamSynchronize(st));
+  if (n_tiles > 0) {
+    APIC_HIP(hipMemcpy(d_pos, pos, 8 * (size_t)n_tiles, hipMemcpyHostToDevice));
+    APIC_HIP(hipMemcpy(d_rot, rot.data(), 4 * rot.size(), hipMemcpyHostToDevice));
+  }
+  APIC_HIP(hipMemcpy(d_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice));
+  if (!tiles.empty())
+    APIC_HIP(hipMemcpy(d_tiles, tiles.data(), 4 * tiles.size(), hipMemcpyHostToDevice));
+  const int bw = (canvas_w + kAsmBlock - 1) / kAsmBlock;
+  hipLaunchKernelGGL(k_blend, dim3((unsigned)nb), dim3(256), 0, st,
+                     reinterpret_cast<const c32 *>(fields), n, d_pos, d_start, d_tiles, d_rot,
+                     1.f / ramp_width, reinterpret_cast<c32 *>(canvas), canvas_h, canvas_w, bw);
+  APIC_LAUNCHED();
+  return APIC_OK;
 }
