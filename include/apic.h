@@ -314,33 +314,36 @@ apic_status apic_batch_fit(apic_batch *batch, size_t workspace_bytes);
  * adjacent scans keep overlapping regions, blended to hide the seams; a tile
  * with no neighbour is placed by its scan position).  Registration by image
  * features is not done here: positions are given.
+ * apic_assembly_create takes the layout: n_tiles tiles of side n, pos int32
+ * [T][2] (host; canvas row and column of each tile's [0][0]; tiles may reach
+ * outside the canvas), the pairs sharing at least min_overlap rows and
+ * columns, and a canvas of canvas_h x canvas_w; it builds the overlapping
+ * pairs and, per 32 x 32 canvas block, the covering tiles, and copies them to
+ * device memory it owns (needs the device; not capturable).
  *   fields  complex64 [T][n][n] (device), tile t at fields + 2 * t * n * n
  *           (e.g. the fN x fN fields of a single-geometry reconstruction)
- *   pos     int32 [T][2] (host): canvas row and column of each tile's [0][0]
  * Every reconstructed tile carries its own constant phase (KK fixes each
  * tile's DC phase), so tiles are brought to a common phase first.
  * apic_assemble_phases: C_tu = sum over the overlap of F_t conj(F_u) for every
- * pair sharing at least min_overlap rows and columns (FP64 sums on the
- * GPU); then, on the host, theta = the phases of the leading eigenvector of
- * C (angular synchronisation) per connected group of overlapping tiles, the
- * group's lowest-numbered tile at 0 (a tile with no neighbour gets 0).
- * theta_out float [T] (host).  Synchronises the host with `stream`.
+ * pair (FP64 sums on the GPU); then, on the host, theta = the phases of the
+ * leading eigenvector of C (angular synchronisation) per connected group of
+ * overlapping tiles, the group's lowest-numbered tile at 0 (a tile with no
+ * neighbour gets 0).  theta_out float [T] (host).  Synchronises the host with
+ * `stream`.
  * apic_blend: canvas(p) = sum_t w_t(p) F_t(p) exp(-j theta_t) / sum_t w_t(p)
  * (0 where no tile covers p), w = ramp(y) ramp(x) over each tile, ramp(v) =
- * min(1, (v + 1/2) / R, (n - v - 1/2) / R), R = ramp_width >= 1; theta host
- * [T] or NULL (all 0); canvas complex64 [canvas_h][canvas_w] (device); tiles
- * may reach outside the canvas.  Both calls upload small host-built lists to
- * the workspace (apic_assemble_workspace_bytes, 256-byte aligned) with
- * blocking copies after draining `stream`, so they are not capturable. */
-apic_status apic_assemble_workspace_bytes(int32_t n_tiles, int32_t n, const int32_t *pos,
-                                          int32_t min_overlap, int32_t canvas_h,
-                                          int32_t canvas_w, size_t *bytes);
-apic_status apic_assemble_phases(int32_t n_tiles, int32_t n, const float *fields,
-                                 const int32_t *pos, int32_t min_overlap, float *theta_out,
-                                 void *workspace, size_t workspace_bytes, void *stream);
-apic_status apic_blend(int32_t n_tiles, int32_t n, const float *fields, const int32_t *pos,
-                       const float *theta, float ramp_width, float *canvas, int32_t canvas_h,
-                       int32_t canvas_w, void *workspace, size_t workspace_bytes, void *stream);
+ * min(1, (v + 1/2) / R, (n - v - 1/2) / R), R = ramp_width >= 1; theta
+ * float [T] (DEVICE) or NULL (all 0); canvas complex64 [canvas_h][canvas_w]
+ * (device).  One kernel launch, no host work: capturable. */
+typedef struct apic_assembly apic_assembly;
+apic_status apic_assembly_create(int32_t n_tiles, int32_t n, const int32_t *pos,
+                                 int32_t min_overlap, int32_t canvas_h, int32_t canvas_w,
+                                 apic_assembly **out);
+apic_status apic_assembly_destroy(apic_assembly *assembly);
+apic_status apic_assemble_phases(apic_assembly *assembly, const float *fields, float *theta_out,
+                                 void *stream);
+apic_status apic_blend(const apic_assembly *assembly, const float *fields, const float *theta,
+                       float ramp_width, float *canvas, void *stream);
 
 /* ---------------------------------------------------------------- surrogate
  * Learned Zernike surrogate (not part of the paper's method): a perceptron

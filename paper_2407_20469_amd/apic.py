@@ -43,7 +43,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
            "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
-           "apic_estimate_pupil_pixel", "apic_assemble_workspace_bytes",
+           "apic_estimate_pupil_pixel", "apic_assembly_create", "apic_assembly_destroy",
            "apic_assemble_phases", "apic_blend",
            "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
            "apic_streamer_run", "apic_version"]
@@ -134,10 +134,10 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
-    lib.apic_assemble_workspace_bytes.argtypes = [i32, i32, P, i32, i32, i32,
-                                                  ctypes.POINTER(sz)]
-    lib.apic_assemble_phases.argtypes = [i32, i32, P, P, i32, P, P, sz, P]
-    lib.apic_blend.argtypes = [i32, i32, P, P, P, ctypes.c_float, P, i32, i32, P, sz, P]
+    lib.apic_assembly_create.argtypes = [i32, i32, P, i32, i32, i32, ctypes.POINTER(P)]
+    lib.apic_assembly_destroy.argtypes = [P]
+    lib.apic_assemble_phases.argtypes = [P, P, P, P]
+    lib.apic_blend.argtypes = [P, P, P, ctypes.c_float, P, P]
     lib.apic_estimate_pupil_pixel.argtypes = [P, i32, ctypes.POINTER(TileDesc), P,
                                               ctypes.c_double, i32, P, P, P, P, P, sz, P]
     lib.apic_streamer_create.argtypes = [P, i32, i32, i32, ctypes.POINTER(P)]
@@ -481,35 +481,70 @@ def estimate_pupil_pixel(plan, images, tol=1e-10, max_iter=1000, workspace=None,
     return phi, zern, iters, status
 
 
+class Assembly:
+    """Tiles of side n at integer canvas positions (T, 2) (row, column) on a
+    canvas of ``canvas_shape``: overlapping pairs and per-block tile lists
+    prepared once on the device (see apic_assembly_create)."""
+
+    def __init__(self, n, positions, canvas_shape, min_overlap=1):
+        self.lib = load_library()
+        self.pos = np.ascontiguousarray(np.asarray(positions, np.int32).reshape(-1, 2))
+        self.T, self.n = self.pos.shape[0], int(n)
+        self.shape = (int(canvas_shape[0]), int(canvas_shape[1]))
+        h = ctypes.c_void_p()
+        _check("apic_assembly_create", self.lib.apic_assembly_create(
+            self.T, self.n, self.pos.ctypes.data_as(ctypes.c_void_p), int(min_overlap),
+            self.shape[0], self.shape[1], ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.apic_assembly_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fields(self, fields):
+        import torch
+        f = fields.contiguous()
+        if (f.dtype != torch.complex64 or not f.is_cuda or f.numel() != self.T * self.n ** 2):
+            raise ValueError(f"fields must be complex64 CUDA ({self.T}, {self.n}, {self.n})")
+        return f
+
+    def phases(self, fields, stream=None):
+        """Constant phase of each tile (NumPy float32 (T,))."""
+        f = self._fields(fields)
+        theta = np.zeros(self.T, np.float32)
+        _check("apic_assemble_phases", self.lib.apic_assemble_phases(
+            self.handle, _ptr(f), theta.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return theta
+
+    def blend(self, fields, theta, ramp_width, out=None, stream=None):
+        """Blend onto a complex64 canvas; theta a float32 CUDA tensor (T,) or None."""
+        import torch
+        f = self._fields(fields)
+        canvas = out if out is not None else torch.empty(self.shape, dtype=torch.complex64,
+                                                         device=f.device)
+        th = None if theta is None else theta.contiguous().to(torch.float32)
+        _check("apic_blend", self.lib.apic_blend(
+            self.handle, _ptr(f), _ptr(th), float(ramp_width), _ptr(canvas), _stream(stream)))
+        return canvas
+
+
 def assemble(fields, positions, canvas_shape, ramp_width, min_overlap=1, align_phases=True,
-             workspace=None, stream=None):
-    """Blend tiles (complex64 CUDA tensor (T, n, n)) placed at integer canvas
-    positions (T, 2) (row, column) into a complex64 canvas; the tiles are first
-    brought to a common constant phase unless ``align_phases`` is False.
-    Returns (canvas, theta)."""
+             stream=None):
+    """Phase-align (unless ``align_phases`` is False) and blend tiles (complex64
+    CUDA (T, n, n)) at integer canvas positions.  Returns (canvas, theta)."""
     import torch
-    lib = load_library()
-    f = fields.contiguous()
-    if f.dtype != torch.complex64 or not f.is_cuda or f.dim() != 3 or f.shape[1] != f.shape[2]:
-        raise ValueError("fields must be a complex64 CUDA tensor (T, n, n)")
-    T, n = f.shape[0], f.shape[1]
-    pos = np.ascontiguousarray(np.asarray(positions, np.int32).reshape(T, 2))
-    H, W = int(canvas_shape[0]), int(canvas_shape[1])
-    pp = pos.ctypes.data_as(ctypes.c_void_p)
-    b = ctypes.c_size_t()
-    _check("apic_assemble_workspace_bytes", lib.apic_assemble_workspace_bytes(
-        T, n, pp, int(min_overlap), H, W, ctypes.byref(b)))
-    ws = workspace or Workspace()
-    wp, wb = ws.get(b.value, f.device)
-    theta = np.zeros(T, np.float32)
-    if align_phases:
-        _check("apic_assemble_phases", lib.apic_assemble_phases(
-            T, n, _ptr(f), pp, int(min_overlap), theta.ctypes.data_as(ctypes.c_void_p), wp, wb,
-            _stream(stream)))
-    canvas = torch.empty((H, W), dtype=torch.complex64, device=f.device)
-    _check("apic_blend", lib.apic_blend(
-        T, n, _ptr(f), pp, theta.ctypes.data_as(ctypes.c_void_p), float(ramp_width),
-        _ptr(canvas), H, W, wp, wb, _stream(stream)))
+    a = Assembly(fields.shape[-1], positions, canvas_shape, min_overlap)
+    theta = a.phases(fields, stream) if align_phases else np.zeros(a.T, np.float32)
+    canvas = a.blend(fields, torch.tensor(theta, device=fields.device), ramp_width,
+                     stream=stream)
+    a.close()
     return canvas, theta
 
 

@@ -1749,14 +1749,6 @@ void asm_blocks(int32_t T, int32_t n, const int32_t *pos, int32_t H, int32_t W,
   }
 }
 
-int64_t asm_phase_bytes(int32_t T, size_t P) {
-  return align256(8 * (int64_t)T) + align256(24 * (int64_t)P) + align256(16 * (int64_t)P);
-}
-int64_t asm_blend_bytes(int32_t T, size_t nb, size_t L) {
-  return align256(8 * (int64_t)T) + align256(4 * (int64_t)(nb + 1)) + align256(4 * (int64_t)L) +
-         align256(8 * (int64_t)T);
-}
-
 // Leading eigenvector phases of each connected group of the overlap graph
 // (angular synchronisation), the group's lowest tile at 0.  Power iteration
 // on C + sigma I (sigma = the largest absolute row sum, so every eigenvalue is
@@ -1824,90 +1816,104 @@ void asm_synchronise(int32_t T, const std::vector<apic::AsmPair> &pairs,
 
 }  // namespace
 
-apic_status apic_assemble_workspace_bytes(int32_t n_tiles, int32_t n, const int32_t *pos,
-                                          int32_t min_overlap, int32_t canvas_h,
-                                          int32_t canvas_w, size_t *bytes) {
-  if (!bytes || !asm_args_ok(n_tiles, n, pos) || canvas_h < 0 || canvas_w < 0) return APIC_EINVAL;
-  const std::vector<AsmPair> pairs = asm_pairs(n_tiles, n, pos, std::max(1, min_overlap));
+// A prepared assembly: overlapping pairs and per-block tile lists resident
+// on the device.
+struct apic_assembly {
+  uint32_t magic = 0x41534d42u;  // "ASMB"
+  int32_t T = 0, n = 0, H = 0, W = 0, bw = 0, nb = 0;
+  std::vector<int32_t> pos;
+  std::vector<apic::AsmPair> pairs;
+  void *dev = nullptr;  // pos, pairs, correlations, block starts, block tiles
+  int32_t *d_pos = nullptr, *d_start = nullptr, *d_tiles = nullptr;
+  apic::AsmPair *d_pairs = nullptr;
+  c64 *d_corr = nullptr;
+};
+
+static bool assembly_ok(const apic_assembly *a) { return a && a->magic == 0x41534d42u; }
+
+apic_status apic_assembly_create(int32_t n_tiles, int32_t n, const int32_t *pos,
+                                 int32_t min_overlap, int32_t canvas_h, int32_t canvas_w,
+                                 apic_assembly **out) {
+  if (!out) return APIC_EINVAL;
+  *out = nullptr;
+  if (!asm_args_ok(n_tiles, n, pos) || n_tiles < 1 || canvas_h < 1 || canvas_w < 1)
+    return APIC_EINVAL;
+  apic_assembly *a = new (std::nothrow) apic_assembly();
+  if (!a) return APIC_ENOMEM;
+  a->T = n_tiles;
+  a->n = n;
+  a->H = canvas_h;
+  a->W = canvas_w;
+  a->pos.assign(pos, pos + 2 * (size_t)n_tiles);
+  a->pairs = asm_pairs(n_tiles, n, pos, std::max(1, min_overlap));
   std::vector<int32_t> start, tiles;
   asm_blocks(n_tiles, n, pos, canvas_h, canvas_w, start, tiles);
-  *bytes = (size_t)std::max<int64_t>(
-      256, std::max(asm_phase_bytes(n_tiles, pairs.size()),
-                    asm_blend_bytes(n_tiles, start.size() - 1, tiles.size())));
+  a->nb = (int32_t)(start.size() - 1);
+  a->bw = (canvas_w + kAsmBlock - 1) / kAsmBlock;
+  const size_t P = a->pairs.size();
+  const int64_t o_pairs = align256(8 * (int64_t)n_tiles);
+  const int64_t o_corr = o_pairs + align256(24 * (int64_t)P);
+  const int64_t o_start = o_corr + align256(16 * (int64_t)P);
+  const int64_t o_tiles = o_start + align256(4 * (int64_t)start.size());
+  const int64_t total = o_tiles + align256(4 * (int64_t)std::max<size_t>(1, tiles.size()));
+  bool ok = hipMalloc(&a->dev, (size_t)total) == hipSuccess;
+  if (ok) {
+    char *d = reinterpret_cast<char *>(a->dev);
+    a->d_pos = reinterpret_cast<int32_t *>(d);
+    a->d_pairs = reinterpret_cast<AsmPair *>(d + o_pairs);
+    a->d_corr = reinterpret_cast<c64 *>(d + o_corr);
+    a->d_start = reinterpret_cast<int32_t *>(d + o_start);
+    a->d_tiles = reinterpret_cast<int32_t *>(d + o_tiles);
+    ok = hipMemcpy(a->d_pos, pos, 8 * (size_t)n_tiles, hipMemcpyHostToDevice) == hipSuccess &&
+         (P == 0 || hipMemcpy(a->d_pairs, a->pairs.data(), sizeof(AsmPair) * P,
+                              hipMemcpyHostToDevice) == hipSuccess) &&
+         hipMemcpy(a->d_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         (tiles.empty() || hipMemcpy(a->d_tiles, tiles.data(), 4 * tiles.size(),
+                                     hipMemcpyHostToDevice) == hipSuccess);
+  }
+  if (!ok) {
+    if (a->dev) (void)hipFree(a->dev);
+    delete a;
+    return APIC_EHIP;
+  }
+  *out = a;
   return APIC_OK;
 }
 
-apic_status apic_assemble_phases(int32_t n_tiles, int32_t n, const float *fields,
-                                 const int32_t *pos, int32_t min_overlap, float *theta_out,
-                                 void *workspace, size_t workspace_bytes, void *stream) {
-  if (!asm_args_ok(n_tiles, n, pos) || (n_tiles > 0 && (!fields || !theta_out)))
-    return APIC_EINVAL;
-  const std::vector<AsmPair> pairs = asm_pairs(n_tiles, n, pos, std::max(1, min_overlap));
-  for (int t = 0; t < n_tiles; ++t) theta_out[t] = 0.f;
-  if (pairs.empty()) return APIC_OK;
-  if (!workspace || (int64_t)workspace_bytes < asm_phase_bytes(n_tiles, pairs.size()) ||
-      (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-    return APIC_EINVAL;
+apic_status apic_assembly_destroy(apic_assembly *a) {
+  if (!a) return APIC_OK;
+  if (!assembly_ok(a)) return APIC_EINVAL;
+  if (a->dev) (void)hipFree(a->dev);
+  a->magic = 0;
+  delete a;
+  return APIC_OK;
+}
+
+apic_status apic_assemble_phases(apic_assembly *a, const float *fields, float *theta_out,
+                                 void *stream) {
+  if (!assembly_ok(a) || !fields || !theta_out) return APIC_EINVAL;
+  for (int t = 0; t < a->T; ++t) theta_out[t] = 0.f;
+  if (a->pairs.empty()) return APIC_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char *ws = reinterpret_cast<char *>(workspace);
-  int32_t *d_pos = reinterpret_cast<int32_t *>(ws);
-  AsmPair *d_pairs = reinterpret_cast<AsmPair *>(ws + align256(8 * (int64_t)n_tiles));
-  c64 *d_corr = reinterpret_cast<c64 *>(ws + align256(8 * (int64_t)n_tiles) +
-                                        align256(24 * (int64_t)pairs.size()));
-  // the workspace may still be read by earlier work on the stream
-  APIC_HIP(hipStreamSynchronize(st));
-  APIC_HIP(hipMemcpy(d_pos, pos, 8 * (size_t)n_tiles, hipMemcpyHostToDevice));
-  APIC_HIP(hipMemcpy(d_pairs, pairs.data(), sizeof(AsmPair) * pairs.size(), hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(k_overlap_corr, dim3((unsigned)pairs.size()), dim3(256), 0, st,
-                     reinterpret_cast<const c32 *>(fields), n, d_pos, d_pairs, d_corr);
+  hipLaunchKernelGGL(k_overlap_corr, dim3((unsigned)a->pairs.size()), dim3(256), 0, st,
+                     reinterpret_cast<const c32 *>(fields), a->n, a->d_pos, a->d_pairs,
+                     a->d_corr);
   APIC_LAUNCHED();
-  std::vector<c64> corr(pairs.size());
+  std::vector<c64> corr(a->pairs.size());
   APIC_HIP(hipStreamSynchronize(st));
-  APIC_HIP(hipMemcpy(corr.data(), d_corr, sizeof(c64) * pairs.size(), hipMemcpyDeviceToHost));
-  asm_synchronise(n_tiles, pairs, corr, theta_out);
+  APIC_HIP(hipMemcpy(corr.data(), a->d_corr, sizeof(c64) * corr.size(), hipMemcpyDeviceToHost));
+  asm_synchronise(a->T, a->pairs, corr, theta_out);
   return APIC_OK;
 }
 
-apic_status apic_blend(int32_t n_tiles, int32_t n, const float *fields, const int32_t *pos,
-                       const float *theta, float ramp_width, float *canvas, int32_t canvas_h,
-                       int32_t canvas_w, void *workspace, size_t workspace_bytes, void *stream) {
-  if (!asm_args_ok(n_tiles, n, pos) || canvas_h < 1 || canvas_w < 1 || !canvas ||
-      !(ramp_width >= 1.f) || (n_tiles > 0 && !fields))
-    return APIC_EINVAL;
-  std::vector<int32_t> start, tiles;
-  asm_blocks(n_tiles, n, pos, canvas_h, canvas_w, start, tiles);
-  const size_t nb = start.size() - 1;
-  if (!workspace || (int64_t)workspace_bytes < asm_blend_bytes(n_tiles, nb, tiles.size()) ||
-      (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-    return APIC_EINVAL;
-  std::vector<float> rot(2 * (size_t)n_tiles);
-  for (int t = 0; t < n_tiles; ++t) {
-    const double th = theta ? theta[t] : 0.0;
-    rot[2 * t] = (float)std::cos(th);
-    rot[2 * t + 1] = (float)-std::sin(th);
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char *ws = reinterpret_cast<char *>(workspace);
-  int64_t o = 0;
-  int32_t *d_pos = reinterpret_cast<int32_t *>(ws + o);
-  o += align256(8 * (int64_t)n_tiles);
-  int32_t *d_start = reinterpret_cast<int32_t *>(ws + o);
-  o += align256(4 * (int64_t)(nb + 1));
-  int32_t *d_tiles = reinterpret_cast<int32_t *>(ws + o);
-  o += align256(4 * (int64_t)tiles.size());
-  c32 *d_rot = reinterpret_cast<c32 *>(ws + o);
-  APIC_HIP(hipStreamSynchronize(st));
-  if (n_tiles > 0) {
-    APIC_HIP(hipMemcpy(d_pos, pos, 8 * (size_t)n_tiles, hipMemcpyHostToDevice));
-    APIC_HIP(hipMemcpy(d_rot, rot.data(), 4 * rot.size(), hipMemcpyHostToDevice));
-  }
-  APIC_HIP(hipMemcpy(d_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice));
-  if (!tiles.empty())
-    APIC_HIP(hipMemcpy(d_tiles, tiles.data(), 4 * tiles.size(), hipMemcpyHostToDevice));
-  const int bw = (canvas_w + kAsmBlock - 1) / kAsmBlock;
-  hipLaunchKernelGGL(k_blend, dim3((unsigned)nb), dim3(256), 0, st,
-                     reinterpret_cast<const c32 *>(fields), n, d_pos, d_start, d_tiles, d_rot,
-                     1.f / ramp_width, reinterpret_cast<c32 *>(canvas), canvas_h, canvas_w, bw);
+apic_status apic_blend(const apic_assembly *a, const float *fields, const float *theta,
+                       float ramp_width, float *canvas, void *stream) {
+  if (!assembly_ok(a) || !fields || !canvas || !(ramp_width >= 1.f)) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_blend, dim3((unsigned)a->nb), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const c32 *>(fields),
+                     a->n, a->d_pos, a->d_start, a->d_tiles, theta, 1.f / ramp_width,
+                     reinterpret_cast<c32 *>(canvas), a->H, a->W, a->bw);
   APIC_LAUNCHED();
   return APIC_OK;
 }

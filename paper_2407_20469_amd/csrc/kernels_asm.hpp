@@ -57,31 +57,57 @@ __device__ __forceinline__ float asm_ramp(int v, int n, float inv_w) {
 
 // canvas(p) = sum_t w_t(p) F_t(p) exp(-j theta_t) / sum_t w_t(p), 0 where no
 // tile covers p.  Block b of the canvas (row-major, kAsmBlock square) lists
-// its covering tiles in tiles[start[b] .. start[b + 1]); rot holds
-// (cos theta_t, -sin theta_t).
+// its covering tiles in tiles[start[b] .. start[b + 1]); theta [T] (device,
+// NULL = all 0).  The block's tile offsets and phase factors are staged in LDS
+// once; each pixel is written once.
+constexpr int kAsmMaxCover = 64;  // tiles staged per pass over a block's list
 __global__ __launch_bounds__(256) void k_blend(const c32 *fields, int n, const int32_t *pos,
                                                const int32_t *start, const int32_t *tiles,
-                                               const c32 *rot, float inv_w, c32 *canvas, int H,
+                                               const float *theta, float inv_w, c32 *canvas, int H,
                                                int W, int bw) {
+  __shared__ int s_t[kAsmMaxCover], s_y[kAsmMaxCover], s_x[kAsmMaxCover];
+  __shared__ c32 s_rot[kAsmMaxCover];
   const int b = blockIdx.x;
   const int by = (b / bw) * kAsmBlock, bx = (b % bw) * kAsmBlock;
   const int lx = threadIdx.x & 31, ly0 = threadIdx.x >> 5;  // 8 rows per pass
   const int x = bx + lx;
-  for (int ly = ly0; ly < kAsmBlock; ly += 8) {
-    const int y = by + ly;
-    if (y >= H || x >= W) continue;
-    float ar = 0.f, ai = 0.f, den = 0.f;
-    for (int k = start[b]; k < start[b + 1]; ++k) {
-      const int t = tiles[k];
-      const int ty = y - pos[2 * t], tx = x - pos[2 * t + 1];
-      if (ty < 0 || ty >= n || tx < 0 || tx >= n) continue;
-      const float w = asm_ramp(ty, n, inv_w) * asm_ramp(tx, n, inv_w);
-      const c32 f = cmul(fields[(int64_t)t * n * n + ty * n + tx], rot[t]);
-      ar = fmaf(w, f.x, ar);
-      ai = fmaf(w, f.y, ai);
-      den += w;
+  const int k0 = start[b], k1 = start[b + 1];
+  float ar[kAsmBlock / 8], ai[kAsmBlock / 8], den[kAsmBlock / 8];
+#pragma unroll
+  for (int i = 0; i < kAsmBlock / 8; ++i) ar[i] = ai[i] = den[i] = 0.f;
+  for (int c0 = k0; c0 < k1; c0 += kAsmMaxCover) {
+    const int cn = min(kAsmMaxCover, k1 - c0);
+    __syncthreads();
+    if (threadIdx.x < cn) {
+      const int t = tiles[c0 + threadIdx.x];
+      s_t[threadIdx.x] = t;
+      s_y[threadIdx.x] = pos[2 * t];
+      s_x[threadIdx.x] = pos[2 * t + 1];
+      float sn = 0.f, cs = 1.f;
+      if (theta) sincosf(theta[t], &sn, &cs);
+      s_rot[threadIdx.x] = make_float2(cs, -sn);
     }
-    canvas[(int64_t)y * W + x] = den > 0.f ? make_float2(ar / den, ai / den) : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kAsmBlock / 8; ++i) {
+      const int y = by + ly0 + 8 * i;
+      for (int k = 0; k < cn; ++k) {
+        const int ty = y - s_y[k], tx = x - s_x[k];
+        if (ty < 0 || ty >= n || tx < 0 || tx >= n) continue;
+        const float w = asm_ramp(ty, n, inv_w) * asm_ramp(tx, n, inv_w);
+        const c32 f = cmul(fields[(int64_t)s_t[k] * n * n + ty * n + tx], s_rot[k]);
+        ar[i] = fmaf(w, f.x, ar[i]);
+        ai[i] = fmaf(w, f.y, ai[i]);
+        den[i] += w;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kAsmBlock / 8; ++i) {
+    const int y = by + ly0 + 8 * i;
+    if (y < H && x < W)
+      canvas[(int64_t)y * W + x] =
+          den[i] > 0.f ? make_float2(ar[i] / den[i], ai[i] / den[i]) : make_float2(0.f, 0.f);
   }
 }
 

@@ -133,17 +133,14 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     rc = lib.apic_estimate_pupil_pixel(plan512.handle, 2, descs, fake, 1e-10, 100, fake, fake,
                                        None, fake, fake, need, None)
     assert rc == apic.APIC_EUNSUPPORTED
-    # assembly: ramp width >= 1, canvas size, workspace present
+    # assembly: layout arguments, bad handle, ramp width >= 1
     pos = (ctypes.c_int32 * 4)(0, 0, 0, 8)
-    rc = lib.apic_blend(2, 16, fake, pos, None, 0.5, fake, 32, 32, fake, 1 << 20, None)
+    h = ctypes.c_void_p()
+    assert lib.apic_assembly_create(2, 16, pos, 1, 0, 32, ctypes.byref(h)) == apic.APIC_EINVAL
+    assert lib.apic_assembly_create(0, 16, pos, 1, 32, 32, ctypes.byref(h)) == apic.APIC_EINVAL
+    assert lib.apic_assembly_create(2, 16, None, 1, 32, 32, ctypes.byref(h)) == apic.APIC_EINVAL
+    rc = lib.apic_blend(ctypes.cast(junk, ctypes.c_void_p), fake, None, 4.0, fake, None)
     assert rc == apic.APIC_EINVAL
-    rc = lib.apic_blend(2, 16, fake, pos, None, 4.0, fake, 0, 32, fake, 1 << 20, None)
-    assert rc == apic.APIC_EINVAL
-    rc = lib.apic_blend(2, 16, fake, pos, None, 4.0, fake, 32, 32, None, 0, None)
-    assert rc == apic.APIC_EINVAL
-    b = ctypes.c_size_t()
-    assert lib.apic_assemble_workspace_bytes(2, 16, pos, 1, 32, 32, ctypes.byref(b)) == 0
-    assert b.value >= 256
     # streamer: chunk >= 1, 2..4 buffers, geometry in range, null output handle
     h = ctypes.c_void_p()
     for geom, chunk, nbuf in ((0, 0, 3), (0, 4, 1), (0, 4, 5), (1, 4, 3), (-1, 4, 3)):
