@@ -15,6 +15,7 @@ closed-form solution", arXiv 2407.20469):
   upsampled output ..... Sec. 2.3, end of brightfield part (output.py)
   background test ...... Sec. 3.2, variance threshold (background.py)
   patch assembly ....... Sec. 2.5, overlap blending  (assemble.py)
+  colour combination ... Sec. 3.3, RGB channels      (rgb.py)
   surrogate MLP twin ... not in the paper             (mlp.py)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
