@@ -345,6 +345,21 @@ apic_status apic_assemble_phases(apic_assembly *assembly, const float *fields, f
 apic_status apic_blend(const apic_assembly *assembly, const float *fields, const float *theta,
                        float ramp_width, float *canvas, void *stream);
 
+/* ------------------------------------------------------------ colour image
+ * Sec. 3.3: for a stained slide the method runs once per colour channel (one
+ * geometry per wavelength); the amplitudes of the three reconstructed fields
+ * are combined and white balanced.  field_r/_g/_b complex64 [T][nf][nf]
+ * (device, same layout); rgb_out float [T][3][nf][nf] (device, planar per
+ * tile) = g_c |F_c|.  gains float [3] (host) or NULL for grey world: g_c =
+ * mean_c' m_c' / m_c with m_c the mean amplitude of channel c over all pixels
+ * (FP64 sums on the GPU; needs a workspace of 3 * 1024 doubles, 256-byte
+ * aligned, and synchronises the host with `stream`).  gains_out float [3]
+ * (host, nullable) receives the gains used. */
+apic_status apic_rgb_combine(int32_t n_tiles, int32_t nf, const float *field_r,
+                             const float *field_g, const float *field_b, const float *gains,
+                             float *rgb_out, float *gains_out, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------- surrogate
  * Learned Zernike surrogate (not part of the paper's method): a perceptron
  * 34 -> 128 -> 128 -> 12 (ReLU) from (tile x, tile y, the 32 features of

@@ -44,7 +44,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
            "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
            "apic_estimate_pupil_pixel", "apic_assembly_create", "apic_assembly_destroy",
-           "apic_assemble_phases", "apic_blend",
+           "apic_assemble_phases", "apic_blend", "apic_rgb_combine",
            "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
            "apic_streamer_run", "apic_version"]
 
@@ -134,6 +134,7 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
+    lib.apic_rgb_combine.argtypes = [i32, i32, P, P, P, P, P, P, P, sz, P]
     lib.apic_assembly_create.argtypes = [i32, i32, P, i32, i32, i32, ctypes.POINTER(P)]
     lib.apic_assembly_destroy.argtypes = [P]
     lib.apic_assemble_phases.argtypes = [P, P, P, P]
@@ -479,6 +480,28 @@ def estimate_pupil_pixel(plan, images, tol=1e-10, max_iter=1000, workspace=None,
         plan.handle, T, descs, _ptr(images), float(tol), int(max_iter), _ptr(phi), _ptr(zern),
         _ptr(iters), _ptr(status), wp, wb, _stream(stream)))
     return phi, zern, iters, status
+
+
+def rgb_combine(field_r, field_g, field_b, gains=None, stream=None):
+    """Colour image (T, 3, nf, nf) float32 of three channel fields (complex64
+    CUDA (T, nf, nf)): g_c |F_c|, grey-world gains unless given.  Returns
+    (image, gains)."""
+    import torch
+    fs = [f.contiguous() for f in (field_r, field_g, field_b)]
+    if any(f.dtype != torch.complex64 or not f.is_cuda or f.shape != fs[0].shape for f in fs):
+        raise ValueError("three complex64 CUDA fields of one shape (T, nf, nf)")
+    T, nf = fs[0].shape[0], fs[0].shape[-1]
+    out = torch.empty((T, 3, nf, nf), dtype=torch.float32, device=fs[0].device)
+    g_in = None if gains is None else np.ascontiguousarray(np.asarray(gains, np.float32))
+    g_out = np.zeros(3, np.float32)
+    ws = torch.empty(3 * 1024 * 8 + 256, dtype=torch.uint8, device=fs[0].device)
+    wp = (ws.data_ptr() + 255) & ~255
+    _check("apic_rgb_combine", load_library().apic_rgb_combine(
+        T, nf, _ptr(fs[0]), _ptr(fs[1]), _ptr(fs[2]),
+        None if g_in is None else g_in.ctypes.data_as(ctypes.c_void_p), _ptr(out),
+        g_out.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(wp), 3 * 1024 * 8,
+        _stream(stream)))
+    return out, g_out
 
 
 class Assembly:

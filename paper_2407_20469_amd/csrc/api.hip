@@ -16,6 +16,7 @@
 #include "kernels_df.hpp"
 #include "kernels_pix.hpp"
 #include "kernels_asm.hpp"
+#include "kernels_rgb.hpp"
 #include "chol.hpp"
 #include "calib.hpp"
 #include "mlp.hpp"
@@ -1914,6 +1915,48 @@ apic_status apic_blend(const apic_assembly *a, const float *fields, const float 
                      reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const c32 *>(fields),
                      a->n, a->d_pos, a->d_start, a->d_tiles, theta, 1.f / ramp_width,
                      reinterpret_cast<c32 *>(canvas), a->H, a->W, a->bw);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
+// ------------------------------------------------------------ colour image
+apic_status apic_rgb_combine(int32_t n_tiles, int32_t nf, const float *field_r,
+                             const float *field_g, const float *field_b, const float *gains,
+                             float *rgb_out, float *gains_out, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+  if (n_tiles < 0 || nf < 1) return APIC_EINVAL;
+  if (n_tiles == 0) return APIC_OK;
+  if (!field_r || !field_g || !field_b || !rgb_out) return APIC_EINVAL;
+  if (!gains && (!workspace || workspace_bytes < sizeof(double) * 3 * kRgbBlocks ||
+                 (reinterpret_cast<uintptr_t>(workspace) & 255) != 0))
+    return APIC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t plane = (int64_t)nf * nf, count = plane * n_tiles;
+  const c32 *fr = reinterpret_cast<const c32 *>(field_r);
+  const c32 *fg = reinterpret_cast<const c32 *>(field_g);
+  const c32 *fb = reinterpret_cast<const c32 *>(field_b);
+  float g[3] = {1.f, 1.f, 1.f};
+  if (gains) {
+    for (int c = 0; c < 3; ++c) g[c] = gains[c];
+  } else {
+    double *partial = reinterpret_cast<double *>(workspace);
+    hipLaunchKernelGGL(k_rgb_mean, dim3(kRgbBlocks), dim3(256), 0, st, fr, fg, fb, count,
+                       partial);
+    APIC_LAUNCHED();
+    std::vector<double> host(3 * kRgbBlocks);
+    APIC_HIP(hipStreamSynchronize(st));
+    APIC_HIP(hipMemcpy(host.data(), partial, sizeof(double) * host.size(), hipMemcpyDeviceToHost));
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < kRgbBlocks; ++b)
+      for (int c = 0; c < 3; ++c) m[c] += host[3 * b + c];
+    const double mean = (m[0] + m[1] + m[2]) / 3.0;
+    for (int c = 0; c < 3; ++c) g[c] = m[c] > 0.0 ? (float)(mean / m[c]) : 1.f;
+  }
+  if (gains_out)
+    for (int c = 0; c < 3; ++c) gains_out[c] = g[c];
+  const unsigned blocks = (unsigned)std::min<int64_t>(8192, (count + 255) / 256);
+  hipLaunchKernelGGL(k_rgb_combine, dim3(blocks), dim3(256), 0, st, fr, fg, fb, plane, count,
+                     g[0], g[1], g[2], rgb_out);
   APIC_LAUNCHED();
   return APIC_OK;
 }
