@@ -14,6 +14,10 @@ in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
 background tiles, nine geometry classes run concurrently in chunks that fit
 ``--ws-gb`` of workspace.
 
+``--workload rgb`` runs a stained slide in three colour channels (0.63, 0.52
+and 0.47 um; 256 px tiles, 8 NA-matched + 16 darkfield LEDs per channel) as
+one batch of three geometry classes, then the colour combination.
+
 ``--workload cfg4`` streams a slide: 512 px tiles (16 + 32 images) whose image
 stacks sit in pinned host memory, reconstructed in chunks through device
 staging buffers on several streams, background tiles skipped by their
@@ -22,7 +26,7 @@ fallback.  The rate is host wall-clock including the host-device copies; the
 sample is the first ``--tiles`` scanned tiles of the raster order (default
 256).
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg4] [--tiles T]
+    python bench.py [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg4|rgb] [--tiles T]
                     [--no-autotune] [--no-cpu-baseline]
 
 Prints one JSON line.  Only one GPU is supported.
@@ -287,7 +291,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg1", "cfg2", "cfg4"], default="cfg1")
+    ap.add_argument("--workload", choices=["cfg1", "cfg2", "cfg4", "rgb"], default="cfg1")
     ap.add_argument("--tiles", type=int, default=None)
     ap.add_argument("--ws-gb", type=float, default=128.0)
     ap.add_argument("--no-autotune", action="store_true")
@@ -302,7 +306,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.tiles is None:
-        args.tiles = {"cfg1": 1024, "cfg2": 4096, "cfg4": 256}[args.workload]
+        args.tiles = {"cfg1": 1024, "cfg2": 4096, "cfg4": 256, "rgb": 256}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the per-tile reconstruction has no "
               "cross-GPU step in this build (tiles shard across GPUs without communication)",
@@ -321,6 +325,10 @@ def main():
     if args.workload == "cfg1":
         ws_list = [S.config1(n_tiles=args.tiles)]
         order = [np.arange(ws_list[0].n_tiles)]
+    elif args.workload == "rgb":
+        from apic_synth.rgb import config_rgb
+        ws_list = config_rgb(n_tiles=args.tiles, n=256)
+        order = [np.arange(args.tiles) * 3 + c for c in range(3)]   # tile-major R, G, B
     else:
         ws_list = S.config2(n_tiles=args.tiles or 4096)
         order = [w.extra["tiles"] for w in ws_list]
@@ -478,7 +486,29 @@ def main():
     tt = sum(prof[k][0] for k in hbm) * 1e-3
     hbm["all"] = {"GB/s": tb / tt / 1e9, "frac": tb / tt / 1e9 / HBM_PEAK_GBS}
 
-    if args.workload == "cfg1":
+    rgb = None
+    if args.workload == "rgb":
+        nf = ws_list[0].n * ws_list[0].upsample
+        f3 = field.view(-1, nf, nf)
+        chans = [f3[c::3].contiguous() for c in range(3)]
+        apic.rgb_combine(*chans)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, gains = apic.rgb_combine(*chans, gains=(1.0, 1.0, 1.0))
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1)
+        nbytes = 3 * chans[0].numel() * 8 + 3 * chans[0].numel() * 4
+        rgb = {"combine_ms": cms, "combine_GBps": nbytes / (cms * 1e-3) / 1e9}
+        log(f"colour combination: {cms:.2f} ms ({rgb['combine_GBps']:.0f} GB/s)")
+    if args.workload == "rgb":
+        w = ws_list[0]
+        config = {"workload": f"{w.n_tiles} stained tiles {w.n}x{w.n} x 3 wavelengths "
+                              f"(0.63 / 0.52 / 0.47 um), 8 NA-matched + 16 darkfield per channel, "
+                              f"Poisson 1e4, 2x complex64 output per channel",
+                  "tiles": w.n_tiles, "channels": 3, "n": w.n, "n_bf": w.n_bf, "n_df": w.n_df}
+    elif args.workload == "cfg1":
         w = ws_list[0]
         config = {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
                               f"(NA 0.25 / 0.30 / 0.38), Poisson 1e4, 2x complex64 output",
@@ -508,6 +538,7 @@ def main():
         "kernel_groups": groups,
         "pixel_pupil": pixel,
         "assembly": assembly,
+        "rgb": rgb,
     }
     if not args.no_cpu_baseline:
         b0 = int(order[0][0])
