@@ -8,21 +8,21 @@ the microscope's side, implemented here a third time with torch so that large
 batches can be synthesised on the GPU; it is pinned against the oracle's own
 forward model by the tests).
 
-Every random draw uses ``numpy.random.default_rng([cfg, stream, tile])`` with
+Every random draw uses ``numpy.random.default_rng([seed_id, stream, tile])`` with
 streams 0 = object, 1 = noise, 2 = per-tile draws; the field-dependence model
 shared by the multi-tile workloads uses ``default_rng([2407, 20469])``.
 """
 
 from .leds import led_ring, led_rings
-from .objects import (gaussian_smooth_periodic, minmax, object_cfg0, object_background,
+from .objects import (gaussian_smooth_periodic, minmax, object_smooth, object_background,
                       object_blobs)
-from .configs import (OPTICS, Workload, config0, config1, config2, config2_classes, config2_tiles,
-                      field_model_cfg1, pupil_cfg0, small_workload)
+from .configs import (OPTICS, Workload, single_tile, grid_batch, uneven_batch, uneven_classes, uneven_tiles,
+                      field_model_quadratic, pupil_random, small_workload)
 from .imaging import form_images, add_poisson
 
 __all__ = [
-    "led_ring", "led_rings", "gaussian_smooth_periodic", "minmax", "object_cfg0",
-    "object_background", "object_blobs", "OPTICS", "Workload", "config0", "config1",
-    "config2", "config2_classes", "config2_tiles", "field_model_cfg1", "pupil_cfg0", "small_workload",
+    "led_ring", "led_rings", "gaussian_smooth_periodic", "minmax", "object_smooth",
+    "object_background", "object_blobs", "OPTICS", "Workload", "single_tile", "grid_batch",
+    "uneven_batch", "uneven_classes", "uneven_tiles", "field_model_quadratic", "pupil_random", "small_workload",
     "form_images", "add_poisson",
 ]

@@ -1,7 +1,7 @@
 """Large synthetic batches: objects drawn per tile with NumPy (seeded
-default_rng([cfg, 0, tile])), images formed with torch on the target device
+default_rng([seed_id, 0, tile])), images formed with torch on the target device
 in float64, Poisson noise drawn there per chunk of 32 tiles (torch generator
-seeded with cfg * 1000003 + first tile of the chunk), cast to float32."""
+seeded with seed_id * 1000003 + first tile of the chunk), cast to float32."""
 
 import numpy as np
 import torch
@@ -29,7 +29,7 @@ def synth_batch(w, device, tiles=None, chunk=CHUNK, log=None):
         objs = np.stack([w.object(t) for t in full])
         imgs = form_images(objs, w.coeffs[full], k_all, w.r, device=device, dtype=torch.float64)
         if w.photons:
-            imgs = add_poisson(imgs, w.photons, seed=w.cfg_id * 1000003 + first, device=device)
+            imgs = add_poisson(imgs, w.photons, seed=w.seed_id * 1000003 + first, device=device)
         for pos, t in members:
             out[pos] = imgs[t - first].to(torch.float32)
         if log and (done % 8 == 0):

@@ -9,7 +9,7 @@ from typing import Callable, List, Optional
 import numpy as np
 
 from .leds import led_rings
-from .objects import object_background, object_cfg0
+from .objects import object_background, object_smooth
 
 OPTICS = {"dx_um": 0.4, "wavelength_um": 0.52, "na_obj": 0.25}
 
@@ -24,8 +24,8 @@ class Workload:
     upsample: int = 2
     n_tiles: int = 1
     photons: Optional[float] = None      # Poisson scale per unit clear intensity
-    cfg_id: int = 0
-    obj_fn: Callable = object_cfg0       # (rng, n) -> complex object
+    seed_id: int = 0
+    obj_fn: Callable = object_smooth       # (rng, n) -> complex object
     coeffs: Optional[np.ndarray] = None  # (n_tiles, 15) true Noll coefficients
     positions: Optional[np.ndarray] = None  # (n_tiles, 2) normalised (u, v)
     dx_um: float = OPTICS["dx_um"]
@@ -50,7 +50,7 @@ class Workload:
         return len(self.k_bf) + len(self.k_df)
 
     def object(self, tile):
-        rng = np.random.default_rng([self.cfg_id, 0, tile])
+        rng = np.random.default_rng([self.seed_id, 0, tile])
         background = self.extra.get("background")
         if background is not None and background[tile]:
             return object_background(rng, self.n)
@@ -62,7 +62,7 @@ class Workload:
                 "k_df": np.asarray(self.k_df, np.int64), "upsample": self.upsample}
 
 
-def pupil_cfg0(seed=(0, 2, 0)):
+def pupil_random(seed=(0, 2, 0)):
     """c_j ~ N(0, 0.5^2) for Noll j in {4, 5, 6, 7, 8, 11}, others 0."""
     rng = np.random.default_rng(list(seed))
     c = np.zeros(15)
@@ -71,17 +71,17 @@ def pupil_cfg0(seed=(0, 2, 0)):
     return c
 
 
-def config0():
+def single_tile():
     """One 128 x 128 tile, 8 NA-matched LEDs at NA 0.25 and 8 darkfield at 0.32,
-    noise-free, smooth cfg-0 object, 2x output."""
+    noise-free, smooth object, 2x output."""
     n = 128
     leds_bf = led_rings(n, [(0.25, 8, 0.0, True)])
     leds_df = led_rings(n, [(0.32, 8, 0.0, False)])
-    return Workload("cfg0", n, leds_bf, leds_df, upsample=2, n_tiles=1, photons=None,
-                    cfg_id=0, coeffs=pupil_cfg0()[None, :], positions=np.zeros((1, 2)))
+    return Workload("single128", n, leds_bf, leds_df, upsample=2, n_tiles=1, photons=None,
+                    seed_id=0, coeffs=pupil_random()[None, :], positions=np.zeros((1, 2)))
 
 
-def field_model_cfg1(u, v, max_abs=1.5):
+def field_model_quadratic(u, v, max_abs=1.5):
     """Noll c_4..c_15 quadratic in the field position (u, v), rescaled so that the
     largest |c| over the given positions equals ``max_abs`` rad."""
     rng = np.random.default_rng([2407, 20469])
@@ -95,7 +95,7 @@ def field_model_cfg1(u, v, max_abs=1.5):
     return c * scale, a * scale
 
 
-def config1(n_tiles=1024, photons=1e4, n=256):
+def grid_batch(n_tiles=1024, photons=1e4, n=256):
     """1024 tiles of 256^2 on a 32 x 32 field grid; 16 NA-matched LEDs at 0.25,
     16 darkfield at 0.30 and 16 at 0.38 (half-step azimuth offset); Poisson noise."""
     leds_bf = led_rings(n, [(0.25, 16, 0.0, True)])
@@ -103,24 +103,24 @@ def config1(n_tiles=1024, photons=1e4, n=256):
     g = np.arange(1024)
     u = (g % 32 - 15.5) / 15.5
     v = (g // 32 - 15.5) / 15.5
-    c_all, _ = field_model_cfg1(u, v)
+    c_all, _ = field_model_quadratic(u, v)
     pos = np.stack([u, v], axis=1)
-    return Workload("cfg1", n, leds_bf, leds_df, upsample=2, n_tiles=n_tiles, photons=photons,
-                    cfg_id=1, coeffs=c_all[:n_tiles], positions=pos[:n_tiles])
+    return Workload("grid256", n, leds_bf, leds_df, upsample=2, n_tiles=n_tiles, photons=photons,
+                    seed_id=1, coeffs=c_all[:n_tiles], positions=pos[:n_tiles])
 
 
-def small_workload(n=64, n_bf=8, n_df=8, na_df=(0.32,), n_tiles=2, photons=None, cfg_id=7):
+def small_workload(n=64, n_bf=8, n_df=8, na_df=(0.32,), n_tiles=2, photons=None, seed_id=7):
     """A small geometry (default 64^2) for quick parity checks; same optics."""
     leds_bf = led_rings(n, [(0.25, n_bf, 0.0, True)])
     rings = [(na, n_df // len(na_df), 0.5 * (m % 2), False) for m, na in enumerate(na_df)]
     leds_df = led_rings(n, rings)
-    coeffs = np.stack([pupil_cfg0((cfg_id, 2, t)) * 0.5 for t in range(n_tiles)])
+    coeffs = np.stack([pupil_random((seed_id, 2, t)) * 0.5 for t in range(n_tiles)])
     return Workload(f"small{n}", n, leds_bf, leds_df, upsample=2, n_tiles=n_tiles,
-                    photons=photons, cfg_id=cfg_id, coeffs=coeffs,
+                    photons=photons, seed_id=seed_id, coeffs=coeffs,
                     positions=np.zeros((n_tiles, 2)))
 
 
-def config2_classes():
+def uneven_classes():
     """The nine geometry classes of the uneven batch: N in {128, 256, 512} x
     n_bf in {8, 12, 16}, n_df = 2 n_bf on rings at NA 0.30 and 0.38."""
     out = []
@@ -132,7 +132,7 @@ def config2_classes():
     return out
 
 
-def config2_tiles(n_tiles=4096, seed=2):
+def uneven_tiles(n_tiles=4096, seed=2):
     """Per-tile (size, n_bf, background, grid position) of the uneven batch:
     sizes 128/256/512 in the ratio 4:3:1, n_bf uniform in {8, 12, 16}, 40%
     background tiles, on a 64 x 64 field grid."""
@@ -150,21 +150,21 @@ def config2_tiles(n_tiles=4096, seed=2):
     return {"n": sizes, "n_bf": nbf, "background": bg, "u": u, "v": v}
 
 
-def config2(n_tiles=4096, photons=1e4, seed=2):
+def uneven_batch(n_tiles=4096, photons=1e4, seed=2):
     """The uneven batch as one Workload per geometry class (in the order of
-    ``config2_classes``), each with the batch-wide indices of its tiles in
+    ``uneven_classes``), each with the batch-wide indices of its tiles in
     ``extra["tiles"]`` and its background flags in ``extra["background"]``.
-    True pupils follow the cfg-1 field model at each tile's grid position."""
-    classes = config2_classes()
-    tiles = config2_tiles(n_tiles, seed)
-    c_all, _ = field_model_cfg1(tiles["u"], tiles["v"])
+    True pupils follow the quadratic field model at each tile's grid position."""
+    classes = uneven_classes()
+    tiles = uneven_tiles(n_tiles, seed)
+    c_all, _ = field_model_quadratic(tiles["u"], tiles["v"])
     out = []
     for ci, g in enumerate(classes):
         sel = np.nonzero((tiles["n"] == g["n"]) & (tiles["n_bf"] == g["n_bf"]))[0]
         if len(sel) == 0:
             continue
-        out.append(Workload(f"cfg2-{g['n']}-{g['n_bf']}", g["n"], g["k_bf"], g["k_df"],
-                            upsample=2, n_tiles=len(sel), photons=photons, cfg_id=20 + ci,
+        out.append(Workload(f"uneven-{g['n']}-{g['n_bf']}", g["n"], g["k_bf"], g["k_df"],
+                            upsample=2, n_tiles=len(sel), photons=photons, seed_id=20 + ci,
                             coeffs=c_all[sel],
                             positions=np.stack([tiles["u"][sel], tiles["v"][sel]], axis=1),
                             extra={"tiles": sel, "background": tiles["background"][sel],

@@ -22,7 +22,7 @@ def minmax(x):
     return (x - lo) / (hi - lo) if hi > lo else np.zeros_like(x)
 
 
-def object_cfg0(rng, n, sigma=2.0):
+def object_smooth(rng, n, sigma=2.0):
     """Amplitude 0.85-1.0 and phase 0..pi, both smoothed by a sigma-px Gaussian."""
     amp = 0.85 + 0.15 * minmax(gaussian_smooth_periodic(rng.random((n, n)), sigma))
     psi = np.pi * minmax(gaussian_smooth_periodic(rng.standard_normal((n, n)), sigma))
@@ -45,7 +45,7 @@ def object_background(rng, n, sigma=2.0):
 
 
 def object_blobs(rng, n, sigma_edge=1.5, px_per_blob=1500.0):
-    """Tissue-like object: soft elliptical cells with phase 0.5-2 rad on a cfg-0
+    """Tissue-like object: soft elliptical cells with phase 0.5-2 rad on a smooth
     amplitude."""
     amp = 0.85 + 0.15 * minmax(gaussian_smooth_periodic(rng.random((n, n)), 2.0))
     yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")

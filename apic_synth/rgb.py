@@ -6,7 +6,7 @@ illumination lattice and pupil.
   channel sees the same illumination NAs: 8 NA-matched LEDs at 0.25 and 8 + 8
   darkfield LEDs at 0.28 and 0.32 (half-step azimuth offset on the second
   ring).  The lattice point of each LED, and the pupil radius, scale as 1/lambda.
-* Stained tissue: the cfg-0 texture, whose optical path gives a phase scaled
+* Stained tissue: the smooth texture, whose optical path gives a phase scaled
   by 0.52 / lambda, under cell blobs carrying haematoxylin (nuclei) and eosin
   (cytoplasm) densities h(x), e(x); channel c transmits exp(-(h OD_H[c] +
   e OD_E[c])) with the published haematoxylin and eosin optical-density
@@ -20,7 +20,7 @@ illumination lattice and pupil.
 
 import numpy as np
 
-from .configs import OPTICS, Workload, field_model_cfg1
+from .configs import OPTICS, Workload, field_model_quadratic
 from .leds import led_rings
 from .objects import gaussian_smooth_periodic, minmax
 
@@ -33,7 +33,7 @@ DEFOCUS = {"R": 0.1, "G": 0.0, "B": -0.1}
 def stained_object(rng, n, channel, lam):
     """Complex transmission of one stained tile in one channel (the draws do
     not depend on the channel, so the three channels see the same tissue):
-    the cfg-0 texture (amplitude 0.85-1, optical path giving 0..pi rad at
+    the smooth texture (amplitude 0.85-1, optical path giving 0..pi rad at
     0.52 um, both smoothed by 2 px) with its phase scaled by 0.52 / lambda,
     times the stain transmission exp(-(h OD_H[c] + e OD_E[c])) of soft cells
     (eosin over the cell, haematoxylin over its nucleus)."""
@@ -66,7 +66,7 @@ def config_rgb(n_tiles=4, n=128, photons=1e4):
     g = np.arange(n_tiles)
     u = (g % side - (side - 1) / 2) / max(1.0, (side - 1) / 2)
     v = (g // side - (side - 1) / 2) / max(1.0, (side - 1) / 2)
-    c_green, _ = field_model_cfg1(u, v, max_abs=0.25)
+    c_green, _ = field_model_quadratic(u, v, max_abs=0.25)
     out = []
     for name, lam in CHANNELS:
         rings_bf = [(0.25, 8, 0.0, True)]
@@ -75,7 +75,7 @@ def config_rgb(n_tiles=4, n=128, photons=1e4):
         c = c_green * (0.52 / lam)
         c[:, 3] += DEFOCUS[name]
         w = Workload(f"rgb-{name}", n, led_rings(n, rings_bf, **kw), led_rings(n, rings_df, **kw),
-                     upsample=2, n_tiles=n_tiles, photons=photons, cfg_id=60,
+                     upsample=2, n_tiles=n_tiles, photons=photons, seed_id=60,
                      coeffs=c, positions=np.stack([u, v], axis=1), wavelength_um=lam,
                      extra={"channel": name})
         w.obj_fn = (lambda rng, nn, _c=name, _l=lam: stained_object(rng, nn, _c, _l))

@@ -55,7 +55,7 @@ def pool_workload(p_tissue=16, p_glass=4, photons=1e4, max_abs=1.5):
     glass = np.zeros(p, bool)
     glass[p_tissue:] = True
     return Workload("slide-pool", n, leds_bf, leds_df, upsample=2, n_tiles=p, photons=photons,
-                    cfg_id=4, obj_fn=object_blobs, coeffs=coeffs, positions=uv,
+                    seed_id=4, obj_fn=object_blobs, coeffs=coeffs, positions=uv,
                     extra={"background": glass})
 
 

@@ -3,10 +3,10 @@ images on the NA 0.25 ring, no darkfield), generated on the target device with
 torch.
 
 * Field model: c_4..c_15 quadratic in the normalised position (u, v) with the
-  coefficients of ``field_model_cfg1`` (default_rng([2407, 20469])), scaled so
+  coefficients of ``field_model_quadratic`` (default_rng([2407, 20469])), scaled so
   that max |c| over a 64 x 64 grid of [-1, 1]^2 equals ``max_abs``.
 * Content tiles: amplitude 0.85..1 and phase 0..pi, periodic Gaussian
-  smoothing sigma = 2 px (the cfg-0 recipe).  Background tiles: amplitude
+  smoothing sigma = 2 px (the smooth-object recipe).  Background tiles: amplitude
   1 - a_bg (1 - minmax(noise)) and smooth phase with standard deviation drawn
   from U(bg_lo, bg_hi) rad, the amplitude texture a_bg scaled with the same
   draw (0.01 at 0.02 rad), so the lowest draws approach blank glass.
@@ -19,7 +19,7 @@ import math
 import numpy as np
 import torch
 
-from .configs import field_model_cfg1
+from .configs import field_model_quadratic
 from .imaging import form_images
 from .leds import led_ring
 
@@ -37,7 +37,7 @@ def field_coeffs(max_abs=0.3):
     """Scaled quadratic field model: (12, 6) coefficients of (1, u, v, u^2, uv, v^2)."""
     g = (np.arange(64) - 31.5) / 31.5
     gu, gv = np.meshgrid(g, g)
-    _, a = field_model_cfg1(gu.ravel(), gv.ravel(), max_abs=max_abs)
+    _, a = field_model_quadratic(gu.ravel(), gv.ravel(), max_abs=max_abs)
     return a
 
 

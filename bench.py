@@ -9,7 +9,7 @@ tile batch, chunk sizes picked by the autotuner); the plain path (one tile
 per call, same kernels) and a graph replay of the batched step are reported
 beside it.
 
-``--workload cfg2`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
+``--workload uneven`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
 in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
 background tiles, nine geometry classes run concurrently in chunks that fit
 ``--ws-gb`` of workspace.
@@ -18,7 +18,7 @@ background tiles, nine geometry classes run concurrently in chunks that fit
 and 0.47 um; 256 px tiles, 8 NA-matched + 16 darkfield LEDs per channel) as
 one batch of three geometry classes, then the colour combination.
 
-``--workload cfg4`` streams a slide: 512 px tiles (16 + 32 images) whose image
+``--workload slide`` streams a slide: 512 px tiles (16 + 32 images) whose image
 stacks sit in pinned host memory, reconstructed in chunks through device
 staging buffers on several streams, background tiles skipped by their
 intensity variance, the pupil chosen by the surrogate with the closed-form
@@ -26,7 +26,7 @@ fallback.  The rate is host wall-clock including the host-device copies; the
 sample is the first ``--tiles`` scanned tiles of the raster order (default
 256).
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg4|rgb] [--tiles T]
+    python bench.py [--steps K] [--warmup W] [--workload grid|uneven|slide|rgb] [--tiles T]
                     [--no-autotune] [--no-cpu-baseline]
 
 Prints one JSON line.  Only one GPU is supported.
@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg1", "cfg2", "cfg4", "rgb"], default="cfg1")
+    ap.add_argument("--workload", choices=["grid", "uneven", "slide", "rgb"], default="grid")
     ap.add_argument("--tiles", type=int, default=None)
     ap.add_argument("--ws-gb", type=float, default=128.0)
     ap.add_argument("--no-autotune", action="store_true")
@@ -299,17 +299,17 @@ def main():
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--plain-tiles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--chunk", type=int, default=16, help="cfg4: tiles per staged chunk")
-    ap.add_argument("--buffers", type=int, default=3, help="cfg4: staging buffers / streams")
+    ap.add_argument("--chunk", type=int, default=16, help="slide: tiles per staged chunk")
+    ap.add_argument("--buffers", type=int, default=3, help="slide: staging buffers / streams")
     ap.add_argument("--bg-threshold", type=float, default=3e-3,
-                    help="cfg4: background statistic threshold")
+                    help="slide: background statistic threshold")
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.tiles is None:
-        args.tiles = {"cfg1": 1024, "cfg2": 4096, "cfg4": 256, "rgb": 256}[args.workload]
+        args.tiles = {"grid": 1024, "uneven": 4096, "slide": 256, "rgb": 256}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the per-tile reconstruction has no "
-              "cross-GPU step in this build (tiles shard across GPUs without communication)",
+              "cross-GPU step (tiles shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -320,17 +320,17 @@ def main():
     from paper_2407_20469_amd import apic
 
     dev = torch.device("cuda:0")
-    if args.workload == "cfg4":
+    if args.workload == "slide":
         return run_slide_stream(args, dev)
-    if args.workload == "cfg1":
-        ws_list = [S.config1(n_tiles=args.tiles)]
+    if args.workload == "grid":
+        ws_list = [S.grid_batch(n_tiles=args.tiles)]
         order = [np.arange(ws_list[0].n_tiles)]
     elif args.workload == "rgb":
         from apic_synth.rgb import config_rgb
         ws_list = config_rgb(n_tiles=args.tiles, n=256)
         order = [np.arange(args.tiles) * 3 + c for c in range(3)]   # tile-major R, G, B
     else:
-        ws_list = S.config2(n_tiles=args.tiles or 4096)
+        ws_list = S.uneven_batch(n_tiles=args.tiles or 4096)
         order = [w.extra["tiles"] for w in ws_list]
     n_total = sum(w.n_tiles for w in ws_list)
     # batch order: tile b of the batch is tile `pos` of class `cls`
@@ -405,7 +405,7 @@ def main():
     # the same step captured into a graph and replayed (the uneven batch's
     # chunked 512 px classes enqueue ~10^5 launches: no graph there by default)
     graph_ms = None
-    if args.graph if args.graph is not None else args.workload == "cfg1":
+    if args.graph if args.graph is not None else args.workload == "grid":
         gstream = torch.cuda.Stream()
         torch.cuda.synchronize()
         batch.capture(images, field, zern, status, ws, gstream)
@@ -441,7 +441,7 @@ def main():
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
 
     pixel = assembly = None
-    if args.workload == "cfg1":
+    if args.workload == "grid":
         assembly = assembly_timing(field, w0)
         log(f"assembly: blend {assembly['blend_ms']:.2f} ms ({assembly['blend_GBps']:.0f} GB/s), "
             f"prepare {assembly['prepare_ms_host']:.1f} ms, phases {assembly['phases_ms_host']:.1f} ms")
@@ -470,7 +470,7 @@ def main():
             # chunks whose products are exactly zero, so they issue fewer flops
             roof["executed_tflops"] = gram_exec / (tot_ms / args.steps * 1e-3) / 1e12
             roof["executed_frac"] = roof["executed_tflops"] / FP64_PEAK_TFLOPS
-            if args.workload == "cfg1" and n_total == 1024:
+            if args.workload == "grid" and n_total == 1024:
                 roof["traffic"] = measured_traffic()
     else:
         achieved = work / (tot_ms * 1e-3) / 1e9
@@ -508,7 +508,7 @@ def main():
                               f"(0.63 / 0.52 / 0.47 um), 8 NA-matched + 16 darkfield per channel, "
                               f"Poisson 1e4, 2x complex64 output per channel",
                   "tiles": w.n_tiles, "channels": 3, "n": w.n, "n_bf": w.n_bf, "n_df": w.n_df}
-    elif args.workload == "cfg1":
+    elif args.workload == "grid":
         w = ws_list[0]
         config = {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
                               f"(NA 0.25 / 0.30 / 0.38), Poisson 1e4, 2x complex64 output",

@@ -3,7 +3,8 @@
 // operands on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulate),
 // FP32 master weights and Adam.  Not part of the paper's method: it seeds or
 // replaces the pupil solve on tiles where the closed form is weak, and the
-// closed form stays its fallback and judge (residual rule below).
+// closed form stays its fallback and the arbiter of its error (residual
+// rule below).
 //
 // MFMA 16x16x16 operand layout (wave64): lane l holds A[l % 16][4 (l / 16) + q]
 // and B[4 (l / 16) + q][l % 16] for q = 0..3, and receives

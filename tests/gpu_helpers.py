@@ -21,7 +21,7 @@ def workload_images(w, tiles=None, photons=None, seed=11):
     for t in tiles:
         img = oracle.forward_images(w.object(t), k_all, w.coeffs[t], w.r)
         if photons:
-            rng = np.random.default_rng([w.cfg_id, 1, t, seed])
+            rng = np.random.default_rng([w.seed_id, 1, t, seed])
             img = rng.poisson(img * photons) / photons
         out.append(img.astype(np.float32))
     return np.stack(out)

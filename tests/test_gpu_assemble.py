@@ -34,7 +34,7 @@ def test_assembly_matches_oracle():
     rng = np.random.default_rng(3)
     n, stride = 64, 48
     H, W = 2 * stride + n + 80, 3 * stride + n
-    field = S.object_cfg0(rng, 256)[:H, :W]
+    field = S.object_smooth(rng, 256)[:H, :W]
     pos = [(i * stride, j * stride) for i in range(3) for j in range(4)]
     pos += [(H - n, 0), (H - n, 40)]   # a pair that overlaps only each other
     pos = np.array(pos)
@@ -63,8 +63,8 @@ def test_assembly_matches_oracle():
 
 def test_reconstructed_windows_assemble():
     n, stride = 64, 48
-    big = S.object_cfg0(np.random.default_rng([9, 0, 0]), 256)
-    w = S.small_workload(n=n, n_tiles=4, cfg_id=51)
+    big = S.object_smooth(np.random.default_rng([9, 0, 0]), 256)
+    w = S.small_workload(n=n, n_tiles=4, seed_id=51)
     pos_in = [(0, 0), (0, stride), (stride, 0), (stride, stride)]
     k_all = list(w.k_bf) + list(w.k_df)
     imgs = np.stack([oracle.forward_images(big[y:y + n, x:x + n], k_all, w.coeffs[t], w.r)

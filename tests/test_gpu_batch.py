@@ -30,9 +30,9 @@ def _log(msg):
 
 @pytest.fixture(scope="module")
 def uneven():
-    ws = [S.small_workload(n=64, n_bf=8, n_df=8, n_tiles=3, cfg_id=21),
-          S.small_workload(n=64, n_bf=12, n_df=12, na_df=(0.30, 0.32), n_tiles=2, cfg_id=22),
-          S.small_workload(n=128, n_bf=8, n_df=16, na_df=(0.30, 0.38), n_tiles=2, cfg_id=23)]
+    ws = [S.small_workload(n=64, n_bf=8, n_df=8, n_tiles=3, seed_id=21),
+          S.small_workload(n=64, n_bf=12, n_df=12, na_df=(0.30, 0.32), n_tiles=2, seed_id=22),
+          S.small_workload(n=128, n_bf=8, n_df=16, na_df=(0.30, 0.38), n_tiles=2, seed_id=23)]
     imgs = [workload_images(w) for w in ws]
     # interleaved tile order: (class, tile within class); the last tile skips darkfield
     order = [(0, 0), (2, 0), (1, 0), (0, 1), (2, 1), (1, 1), (0, 2)]
@@ -201,7 +201,7 @@ def test_uneven_nine_class_batch():
     8/12/16 NA-matched LEDs, twice as many darkfield), background and content
     tiles, Poisson noise: the autotuned concurrent batch equals the plain call;
     the 128 px tiles and one 256 px tile are checked against the oracle."""
-    ws = S.config2(n_tiles=4096)
+    ws = S.uneven_batch(n_tiles=4096)
     plan = apic.Plan([w.geometry_kwargs() for w in ws])
     geom_ids = list(range(len(ws)))
     tile_ids = [int(np.argmax(w.extra["background"])) if c % 2 else 0
@@ -246,10 +246,10 @@ def test_512_tile_with_one_darkfield_image():
     """A 512 px tile (16 NA-matched LEDs of the uneven batch's largest class and
     its first darkfield LED) against the oracle: the largest unknown count of
     the batch (N_u of the first darkfield image)."""
-    ws = S.config2(n_tiles=4096)
+    ws = S.uneven_batch(n_tiles=4096)
     big = ws[8]
     w = S.Workload("512-16+1", big.n, big.k_bf, big.k_df[:1], upsample=2, n_tiles=1,
-                   photons=1e4, cfg_id=big.cfg_id, coeffs=big.coeffs[:1],
+                   photons=1e4, seed_id=big.seed_id, coeffs=big.coeffs[:1],
                    positions=big.positions[:1])
     plan = apic.Plan(w.geometry_kwargs())
     _log(f"512 px tile: plan sizes {plan.sizes()}")

@@ -17,12 +17,12 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-def test_cfg1_full_batch_sampled_parity():
-    w = S.config1(n_tiles=1024)
-    print("[gpu-test] synth cfg1 1024 tiles", flush=True)
+def test_grid_batch_full_size_sampled_parity():
+    w = S.grid_batch(n_tiles=1024)
+    print("[gpu-test] synth 1024 grid tiles", flush=True)
     images = synth_batch(w, torch.device("cuda:0"))
     plan = apic.Plan(w.geometry_kwargs())
-    print("[gpu-test] reconstruct cfg1 1024 tiles", flush=True)
+    print("[gpu-test] reconstruct 1024 grid tiles", flush=True)
     field, zern, status = apic.reconstruct(plan, images)
     torch.cuda.synchronize()
     st = status.cpu().numpy()
@@ -32,7 +32,7 @@ def test_cfg1_full_batch_sampled_parity():
         ref = oracle.reconstruct(images[t].cpu().numpy().astype(np.float64), geom)
         err = rel_l2(field[t].cpu().numpy(), ref["field"])
         dz = float(np.abs(zern[t].cpu().numpy() - ref["c"]).max())
-        print(f"[gpu-test] cfg1 tile {t}: field rel-L2 {err:.3e} max|dc| {dz:.2e} "
+        print(f"[gpu-test] grid tile {t}: field rel-L2 {err:.3e} max|dc| {dz:.2e} "
               f"kappa {ref['pupil']['kappa']:.1f}", flush=True)
         assert dz < 1e-3
         assert err < 1e-4

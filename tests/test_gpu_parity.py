@@ -167,12 +167,12 @@ def test_upsample_parity(small):
         assert rel_l2(out[t], oracle.upsampled_field(spec[t].astype(np.complex128), 2)) < 2e-6
 
 
-@pytest.mark.parametrize("which", ["small64", "cfg0"])
+@pytest.mark.parametrize("which", ["small64", "single128"])
 def test_reconstruct_end_to_end(which, small):
     if which == "small64":
         w, imgs = small
     else:
-        w = S.config0()
+        w = S.single_tile()
         imgs = workload_images(w)
     _log(f"reconstruct {which}")
     plan = apic.Plan(w.geometry_kwargs())

@@ -44,9 +44,9 @@ def _oracle(img, w):
 
 
 CASES = [
-    ("64px-8", dict(n=64, n_bf=8, n_df=0, n_tiles=2, cfg_id=41), None),
-    ("128px-8", dict(n=128, n_bf=8, n_df=0, n_tiles=1, cfg_id=42), None),
-    ("128px-16-poisson", dict(n=128, n_bf=16, n_df=0, n_tiles=2, cfg_id=43), 1e4),
+    ("64px-8", dict(n=64, n_bf=8, n_df=0, n_tiles=2, seed_id=41), None),
+    ("128px-8", dict(n=128, n_bf=8, n_df=0, n_tiles=1, seed_id=42), None),
+    ("128px-16-poisson", dict(n=128, n_bf=16, n_df=0, n_tiles=2, seed_id=43), 1e4),
 ]
 
 
@@ -76,7 +76,7 @@ def test_pixel_pupil_matches_oracle(name, kw, photons):
 def test_pixel_pupil_benchmark_geometry():
     """One tile of the 256 px / 16 + 32 LED geometry (darkfield images present
     but unused by the pupil solve)."""
-    w = S.config1(n_tiles=1)
+    w = S.grid_batch(n_tiles=1)
     imgs = workload_images(w, photons=1e4)
     plan = apic.Plan(w.geometry_kwargs())
     _log("256 px benchmark geometry")
@@ -95,7 +95,7 @@ def test_pixel_pupil_benchmark_geometry():
 
 
 def test_pixel_pupil_iteration_cap_sets_status():
-    w = S.small_workload(n=64, n_bf=8, n_df=0, n_tiles=1, cfg_id=41)
+    w = S.small_workload(n=64, n_bf=8, n_df=0, n_tiles=1, seed_id=41)
     imgs = workload_images(w)
     plan = apic.Plan(w.geometry_kwargs())
     phi, z, iters, st = apic.estimate_pupil_pixel(plan, torch.tensor(imgs, device=DEV),

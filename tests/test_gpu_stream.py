@@ -35,7 +35,7 @@ def _log(msg):
 
 @pytest.fixture(scope="module")
 def slide():
-    w = S.small_workload(n=128, n_bf=8, n_df=8, n_tiles=10, cfg_id=31)
+    w = S.small_workload(n=128, n_bf=8, n_df=8, n_tiles=10, seed_id=31)
     bg = np.zeros(w.n_tiles, bool)
     bg[BG_TILES] = True
     w.extra["background"] = bg

@@ -65,12 +65,12 @@ def test_separates_glass_from_tissue():
     """On synthetic 128 px tiles at 1e4 photons, near-empty glass stays well
     under 1e-3 and blob tissue well over 1e-2 (the threshold range the
     stream uses)."""
-    from apic_synth.configs import Workload, config2_classes, field_model_cfg1
+    from apic_synth.configs import Workload, uneven_classes, field_model_quadratic
     from apic_synth.objects import object_background, object_blobs
     from apic_synth.imaging import form_images, add_poisson
-    cls = config2_classes()[0]
+    cls = uneven_classes()[0]
     w = Workload("t", cls["n"], cls["k_bf"], cls["k_df"])
-    c, _ = field_model_cfg1(np.zeros(1), np.zeros(1))
+    c, _ = field_model_quadratic(np.zeros(1), np.zeros(1))
     stats = {}
     for name, fn in (("glass", object_background), ("tissue", object_blobs)):
         o = fn(np.random.default_rng([5, 0, 1]), w.n)[None]

@@ -15,7 +15,7 @@ import oracle
 from oracle import darkfield as odf
 from oracle.grid import k_grid, circ, pupil_radius
 from oracle.zernike import zernike, noll_nm, pupil_phase
-from apic_synth.objects import object_weak, object_cfg0
+from apic_synth.objects import object_weak, object_smooth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -69,7 +69,7 @@ def test_p8_parseval_forward_and_output():
     times f^2 and its even samples are the band-limited object."""
     n, r = 64, 12.3
     rng = np.random.default_rng(1)
-    obj = object_cfg0(rng, n)
+    obj = object_smooth(rng, n)
     c = np.zeros(15)
     c[[3, 5, 7]] = [0.3, -0.2, 0.1]
     k = np.array([[12, 0], [0, -12]])
@@ -170,7 +170,7 @@ def test_p4_zernike_recovery_from_exact_spectra(lattice_geometry):
     g = lattice_geometry
     n = g["n"]
     r = pupil_radius(n, g["dx_um"], g["wavelength_um"], g["na_obj"])
-    obj_hat = np.fft.fft2(object_cfg0(np.random.default_rng(5), n))
+    obj_hat = np.fft.fft2(object_smooth(np.random.default_rng(5), n))
     c = np.zeros(15)
     c[3:15] = np.random.default_rng(6).normal(0, 0.04, 12)
     spectra = _analytic_spectra(obj_hat, g["k_bf"], c, r)
@@ -189,7 +189,7 @@ def test_p4_gauge_terms_do_not_matter(lattice_geometry):
     g = lattice_geometry
     n = g["n"]
     r = pupil_radius(n, g["dx_um"], g["wavelength_um"], g["na_obj"])
-    obj_hat = np.fft.fft2(object_cfg0(np.random.default_rng(7), n))
+    obj_hat = np.fft.fft2(object_smooth(np.random.default_rng(7), n))
     c = np.zeros(15)
     c[3:15] = np.random.default_rng(8).normal(0, 0.03, 12)
     c_gauge = c.copy()
@@ -206,7 +206,7 @@ def test_p5_seeded_solve_recovers_past_the_wrap(lattice_geometry):
     g = lattice_geometry
     n = g["n"]
     r = pupil_radius(n, g["dx_um"], g["wavelength_um"], g["na_obj"])
-    obj_hat = np.fft.fft2(object_cfg0(np.random.default_rng(9), n))
+    obj_hat = np.fft.fft2(object_smooth(np.random.default_rng(9), n))
     c = np.zeros(15)
     c[[3, 5, 7, 10]] = [1.2, -0.9, 0.8, 0.6]
     spectra = _analytic_spectra(obj_hat, g["k_bf"], c, r)
@@ -242,7 +242,7 @@ def test_p3_identity_pupil_on_weak_object(lattice_geometry):
 # ---------------------------------------------------------------- P7 brute force
 def _tiny_darkfield(n=24, r=5.0, seed=12):
     rng = np.random.default_rng(seed)
-    obj = object_cfg0(rng, n, sigma=1.0)
+    obj = object_smooth(rng, n, sigma=1.0)
     k_bf = np.array([(5, 0), (0, 5), (-5, 0), (0, -5)])
     k_j = np.array([6, 3])
     ky, kx = k_grid(n)
@@ -312,7 +312,7 @@ def test_p6_darkfield_exact_recovery():
     unknown spectrum (ridge -> 1e-12); C has full column rank and M/N_u >= 8."""
     n, r = 64, 12.0
     rng = np.random.default_rng(14)
-    obj = object_cfg0(rng, n, sigma=1.5)
+    obj = object_smooth(rng, n, sigma=1.5)
     c = np.zeros(15)
     c[[3, 4, 7]] = [0.4, -0.3, 0.2]
     k_bf = np.array([(12, 0), (8, 8), (0, 12), (-8, 8), (-12, 0), (-8, -8), (0, -12), (8, -8)])
@@ -340,7 +340,7 @@ def test_p12_mirrored_equations_give_same_solution():
     """Using Eq. 12's other cross term at -Q (F(I) is Hermitian) gives the same x."""
     n, r = 48, 9.0
     rng = np.random.default_rng(15)
-    obj = object_cfg0(rng, n, sigma=1.5)
+    obj = object_smooth(rng, n, sigma=1.5)
     c = np.zeros(15)
     c[[3, 6]] = [0.2, 0.15]
     k_bf = np.array([(9, 0), (0, 9), (-9, 0), (0, -9), (6, 6), (-6, 6), (-6, -6), (6, -6)])

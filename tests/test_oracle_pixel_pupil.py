@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from apic_synth.leds import led_rings
-from apic_synth.objects import object_cfg0
+from apic_synth.objects import object_smooth
 from oracle.aberration import estimate_pupil
 from oracle.grid import circ, fft_index, k_grid
 from oracle.pupil_pixel import pixel_system, pupil_pixels, solve_pixel_pupil
@@ -30,7 +30,7 @@ def _geometry(n=64, count=8):
 def _spectra(n, r, k_bf, phi_of, seed=0):
     """Eq. 9 structure: s_i(k) = O(k) exp(j [phi(k + k_i) - phi(k_i)]) on
     Circ(k + k_i), for a smooth random object spectrum O."""
-    obj = object_cfg0(np.random.default_rng([seed, 0, 0]), n)
+    obj = object_smooth(np.random.default_rng([seed, 0, 0]), n)
     O = np.fft.fft2(obj)
     ky, kx = k_grid(n)
     out = np.zeros((len(k_bf), n, n), complex)

@@ -11,9 +11,9 @@ from oracle import stitch as ost
 
 
 def _p6_error(n=48, r=9.0):
-    from apic_synth.objects import object_cfg0
+    from apic_synth.objects import object_smooth
     from oracle.grid import k_grid, circ
-    obj = object_cfg0(np.random.default_rng(21), n, sigma=1.5)
+    obj = object_smooth(np.random.default_rng(21), n, sigma=1.5)
     c = np.zeros(15)
     c[[3, 4]] = [0.3, -0.2]
     k_bf = np.array([(9, 0), (6, 6), (0, 9), (-6, 6), (-9, 0), (-6, -6), (0, -9), (6, -6)])

@@ -36,10 +36,10 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.apic_version()
 
 
-@pytest.mark.parametrize("wl", ["cfg0", "small64", "two_ring128"])
+@pytest.mark.parametrize("wl", ["single128", "small64", "two_ring128"])
 def test_plan_sets_equal_oracle_sets(wl):
-    if wl == "cfg0":
-        w = S.config0()
+    if wl == "single128":
+        w = S.single_tile()
     elif wl == "small64":
         w = S.small_workload(n=64)
     else:

@@ -22,11 +22,11 @@ def test_led_lattice_examples():
 
 
 def test_config_sizes():
-    w0 = S.config0()
+    w0 = S.single_tile()
     assert w0.n == 128 and len(w0.k_bf) == 8 and len(w0.k_df) == 8
-    w1 = S.config1(n_tiles=4)
+    w1 = S.grid_batch(n_tiles=4)
     assert w1.n == 256 and len(w1.k_bf) == 16 and len(w1.k_df) == 32
-    assert np.isclose(np.abs(S.field_model_cfg1(*np.meshgrid(
+    assert np.isclose(np.abs(S.field_model_quadratic(*np.meshgrid(
         (np.arange(32) - 15.5) / 15.5, (np.arange(32) - 15.5) / 15.5))[0]).max(), 1.5)
 
 
