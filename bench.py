@@ -204,7 +204,7 @@ def run_slide_stream(args, dev):
     pool.copy_(pool_dev)
     del pool_dev
     nf = w.n * w.upsample
-    ring = 2 * args.chunk * args.buffers
+    ring = args.chunk * (args.buffers + 1)   # more than the tiles in flight
     fields = [torch.empty((nf, nf), dtype=torch.complex64).pin_memory() for _ in range(ring)]
     log(f"pool synthesised and pinned in {time.time() - t0:.1f} s")
     sur = None
@@ -247,9 +247,11 @@ def run_slide_stream(args, dev):
     h2d = T * w.n_img * w.n * w.n * 4
     d2h = rec * nf * nf * 8
 
-    # the same kernels on device-resident tiles: one chunk of pool tiles per call
-    dev_imgs = pool[:args.chunk].to(dev)
-    posd = torch.tensor(w.positions[:args.chunk], dtype=torch.float32, device=dev)
+    # the same kernels on device-resident tiles: one chunk of tiles (the pool's
+    # tissue tiles, cycled) per call
+    res = np.arange(args.chunk) % p_tissue
+    dev_imgs = pool[torch.as_tensor(res)].to(dev)
+    posd = torch.tensor(w.positions[res], dtype=torch.float32, device=dev)
     ws = apic.Workspace()
     call = (lambda: apic.reconstruct_sur(plan, dev_imgs, posd, sur, workspace=ws)) if sur \
         else (lambda: apic.reconstruct(plan, dev_imgs, workspace=ws))
@@ -299,7 +301,7 @@ def main():
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--plain-tiles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--chunk", type=int, default=16, help="slide: tiles per staged chunk")
+    ap.add_argument("--chunk", type=int, default=64, help="slide: tiles per staged chunk")
     ap.add_argument("--buffers", type=int, default=3, help="slide: staging buffers / streams")
     ap.add_argument("--bg-threshold", type=float, default=3e-3,
                     help="slide: background statistic threshold")
