@@ -121,23 +121,23 @@ def test_stream_with_surrogate_and_no_threshold(slide):
 
 def test_stream_at_slide_size_matches_in_memory_call():
     """The slide stream's own launch configuration (512 px tiles, 16 + 32
-    images, chunks of 16 over 3 buffers, background threshold 3e-3): 20
-    scanned tiles cycling through a pool of 2 tissue tiles and 1 glass tile;
-    every reconstructed tile equals the in-memory call on its pool tile bit
-    for bit, the glass tiles are skipped."""
+    images, chunks of 64 over 3 buffers, background threshold 3e-3): 130
+    scanned tiles (two full chunks and a ragged one) cycling through a pool of
+    2 tissue tiles and 1 glass tile; every reconstructed tile equals the
+    in-memory call on its pool tile bit for bit, the glass tiles are skipped."""
     from apic_synth import slide
     from apic_synth.batch import synth_batch
     w = slide.pool_workload(2, 1)
     pool_dev = synth_batch(w, torch.device(DEV))
     pool = torch.empty(pool_dev.shape, dtype=torch.float32).pin_memory()
     pool.copy_(pool_dev)
-    src = [0, 1, 2, 0, 1, 0, 2, 1] * 2 + [0, 1, 2, 0]
+    src = ([0, 1, 2, 0, 1, 0, 2, 1] * 17)[:130]
     nf = w.n * w.upsample
     fields = [torch.full((nf, nf), complex(3.0, 3.0), dtype=torch.complex64).pin_memory()
               for _ in src]
     plan = apic.Plan(w.geometry_kwargs())
-    st = apic.Streamer(plan, 0, chunk=16, n_buffers=3)
-    _log(f"stream {len(src)} tiles of 512 px, chunk 16, 3 buffers")
+    st = apic.Streamer(plan, 0, chunk=64, n_buffers=3)
+    _log(f"stream {len(src)} tiles of 512 px, chunk 64, 3 buffers")
     z, status, stat = st.run([pool[k] for k in src], fields, bg_threshold=3e-3)
     st.close()
     _log("in-memory call on the two tissue tiles")
