@@ -32,15 +32,21 @@
  *
  * Memory and ownership
  *   - Every data pointer (images, outputs, workspace, seeds) is DEVICE memory
- *     owned by the caller.  apic_geometry and apic_tile_desc arrays are HOST
+ *     owned by the caller, except where an entry point says HOST (the slide
+ *     streamer's image and field buffers, assembly positions and phases,
+ *     colour gains).  apic_geometry and apic_tile_desc arrays are HOST
  *     memory, read during the call and not retained.
  *   - A plan owns its host tables; it uploads its device tables on first use
  *     (or on apic_plan_upload) to the current device and owns them until
  *     apic_plan_destroy.  Calls never allocate: scratch comes from the
- *     caller's workspace, sized by apic_workspace_bytes.
+ *     caller's workspace, sized by apic_workspace_bytes.  The prepared
+ *     objects are the exception, once, at creation: apic_batch_create
+ *     (descriptor tables, streams), apic_streamer_create (staging buffers,
+ *     pinned host staging, streams) and apic_assembly_create (pair and block
+ *     lists); their destroy calls free it.
  *   - Calls are asynchronous on `stream` (a hipStream_t, NULL = default
- *     stream).  A plan is immutable after upload; concurrent calls need
- *     separate workspaces.
+ *     stream) unless they say they synchronise.  A plan is immutable after
+ *     upload; concurrent calls need separate workspaces.
  *
  * Errors
  *   - Argument errors return a negative apic_status before anything is
