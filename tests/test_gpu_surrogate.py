@@ -113,11 +113,32 @@ def test_training_reduces_loss():
     assert loss[-1] < 0.1 * loss[0]
 
 
+def _fold_output_scale(theta, y_mean, y_std):
+    """Parameters whose outputs are y_std * net(x) + y_mean: an exact
+    reparametrisation of the last layer (rows 0..11 of W3 and b3)."""
+    th = theta.astype(np.float64).copy()
+    o3 = 128 * 64 + 128 + 128 * 128 + 128
+    w3 = th[o3:o3 + 16 * 128].reshape(16, 128)
+    b3 = th[o3 + 16 * 128:o3 + 16 * 128 + 16]
+    w3[:12] *= y_std[:, None]
+    b3[:12] = b3[:12] * y_std + y_mean
+    return th.astype(np.float32)
+
+
 @pytest.mark.timeout(600)
 def test_surrogate_gain_on_background_tiles():
     """Trained on the closed-form estimates of tiles at random field positions
     (40% background), evaluated on a 64 x 64 grid with 70% background tiles
-    whose content ranges down to blank glass."""
+    whose content ranges down to blank glass.
+
+    Training recipe: each tile's label is the median of the closed-form
+    estimates of its 32 nearest trusted tiles in (u, v) (trusted: weight sum
+    above the 40th percentile), so the labels of weak tiles come from their
+    neighbours' estimates instead of their own noisy ones; the network learns
+    standardised labels and the de-standardisation is folded exactly into its
+    last layer.  Fallback rule: the closed form is kept where its own
+    residual is small (R <= 0.1 rad^2) and the surrogate's excess residual
+    exceeds 0.05 rad."""
     dev = torch.device(DEV)
     geom = SS.geometry()
     plan = apic.Plan(geom)
@@ -130,17 +151,25 @@ def test_surrogate_gain_on_background_tiles():
     _log("closed-form labels")
     z, diag, feat, st = apic.estimate_pupil(plan, imgs_tr)
     x_tr = torch.cat([torch.tensor(uv_tr, dtype=torch.float32, device=dev), feat], dim=1)
-    y_tr = z[:, 3:15].contiguous()
+    y_cf = z[:, 3:15].contiguous()
     del imgs_tr
+    trusted = diag[:, 2] > torch.quantile(diag[:, 2], 0.4)
+    uvt = torch.tensor(uv_tr, dtype=torch.float32, device=dev)
+    near = torch.cdist(uvt, uvt[trusted]).topk(32, largest=False).indices
+    y_tr = y_cf[trusted][near].median(dim=1).values
+    y_mean, y_std = y_tr.mean(0), y_tr.std(0) + 1e-6
+    y_n = ((y_tr - y_mean) / y_std).contiguous()
     mean = x_tr.mean(0).cpu().numpy()
     std = x_tr.std(0).cpu().numpy() + 1e-6
     sur = apic.Surrogate(apic.init_mlp_params(7), mean, std, device=DEV)
-    order = np.concatenate([rng.permutation(n_train) for _ in range(40)]).astype(np.int32)
-    loss = sur.train(x_tr, y_tr, order, batch=256, lr=1e-3).cpu().numpy()
+    order = np.concatenate([rng.permutation(n_train) for _ in range(60)]).astype(np.int32)
+    loss = sur.train(x_tr, y_n, order, batch=256, lr=1e-3).cpu().numpy()
     order = np.concatenate([rng.permutation(n_train) for _ in range(20)]).astype(np.int32)
-    loss2 = sur.train(x_tr, y_tr, order, batch=256, lr=2e-4).cpu().numpy()
+    loss2 = sur.train(x_tr, y_n, order, batch=256, lr=2e-4).cpu().numpy()
     _log(f"training loss {loss[0]:.4f} -> {loss[-16:].mean():.5f} -> {loss2[-16:].mean():.5f} "
-         f"({len(loss) + len(loss2)} steps)")
+         f"({len(loss) + len(loss2)} steps, standardised labels)")
+    sur = apic.Surrogate(_fold_output_scale(sur.theta.cpu().numpy(), y_mean.cpu().numpy(),
+                                            y_std.cpu().numpy()), mean, std, device=DEV)
     g = (np.arange(64) - 31.5) / 31.5
     gu, gv = np.meshgrid(g, g)
     uv_ev = np.stack([gu.ravel(), gv.ravel()], axis=1)
@@ -149,7 +178,7 @@ def test_surrogate_gain_on_background_tiles():
     _log(f"synth {n_eval} evaluation tiles (70% background)")
     imgs_ev, c_ev = SS.make_tiles(uv_ev, bg, seed=2, device=dev, bg_lo=0.0, bg_hi=0.02)
     pos = torch.tensor(uv_ev, dtype=torch.float32, device=dev)
-    zc, zcf, zsur, dg, st = apic.estimate_pupil_sur(plan, imgs_ev, pos, sur)
+    zc, zcf, zsur, dg, st = apic.estimate_pupil_sur(plan, imgs_ev, pos, sur, resid_max=0.1)
     st = st.cpu().numpy()
 
     def rmse(zz, sel):
@@ -173,7 +202,23 @@ def test_surrogate_gain_on_background_tiles():
     used = (st & apic.TILE_SURROGATE_USED) != 0
     _log(f"surrogate used on {used.mean():.2f} of tiles "
          f"({used[bg].mean():.2f} of background, {used[~bg].mean():.2f} of content)")
-    # the gain: better overall and on background tiles, no loss on content tiles
-    assert res["surrogate+fallback"][0] < 0.7 * res["closed form"][0]
-    assert res["surrogate+fallback"][1] < 0.7 * res["closed form"][1]
-    assert res["surrogate+fallback"][2] < 1.2 * res["closed form"][2] + 0.01
+    # the gain: five times better overall and on background tiles, no loss on
+    # content tiles (observed: 15x, 19x, and 0.76x of the closed form's error)
+    assert res["surrogate+fallback"][0] < 0.2 * res["closed form"][0]
+    assert res["surrogate+fallback"][1] < 0.2 * res["closed form"][1]
+    assert res["surrogate+fallback"][2] < 1.2 * res["closed form"][2] + 0.002
+    # the fallback at work: an untrained network is rejected wherever the
+    # closed form is trustworthy (its residual under 0.1 rad^2), so those
+    # tiles keep exactly the closed form's estimate
+    bad = apic.Surrogate(apic.init_mlp_params(99), mean, std, device=DEV)
+    zb, zbcf, zbs, dgb, stb = apic.estimate_pupil_sur(plan, imgs_ev, pos, bad, resid_max=0.1)
+    stb = stb.cpu().numpy()
+    fell = (stb & apic.TILE_FALLBACK_USED) != 0
+    trust = dgb.cpu().numpy()[:, 0] <= 0.1
+    _log(f"untrained network: closed form trustworthy on {trust[~bg].mean():.2f} of content and "
+         f"{trust[bg].mean():.2f} of background tiles; fallback on {fell[trust].mean():.2f} of "
+         f"those; RMSE there {rmse(zb, trust):.4f} (network alone {rmse(zbs, trust):.4f}, "
+         f"closed form {rmse(zbcf, trust):.4f})")
+    assert fell[trust].mean() > 0.99
+    assert np.array_equal(zb.cpu().numpy()[trust & fell], zbcf.cpu().numpy()[trust & fell])
+    assert rmse(zb, trust) < 0.5 * rmse(zbs, trust)
