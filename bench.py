@@ -173,12 +173,23 @@ def train_slide_surrogate(dev, n_train=512, seed=41):
     z, diag, feat, st = apic.estimate_pupil(plan, imgs)
     del imgs
     x = torch.cat([torch.tensor(uv, dtype=torch.float32, device=dev), feat], dim=1)
-    y = z[:, 3:15].contiguous()
+    y = z[:, 3:15]
+    y_mean, y_std = y.mean(0), y.std(0) + 1e-6
     mean = x.mean(0).cpu().numpy()
     std = x.std(0).cpu().numpy() + 1e-6
     sur = apic.Surrogate(apic.init_mlp_params(seed), mean, std, device=dev)
     order = np.concatenate([rng.permutation(n_train) for _ in range(200)]).astype(np.int32)
-    loss = sur.train(x, y, order, batch=128, lr=1e-3).cpu().numpy()
+    loss = sur.train(x, ((y - y_mean) / y_std).contiguous(), order, batch=128,
+                     lr=1e-3).cpu().numpy()
+    # standardised labels: the de-standardisation folded exactly into the last layer
+    th = sur.theta.cpu().numpy().astype(np.float64)
+    o3 = 128 * 64 + 128 + 128 * 128 + 128
+    w3 = th[o3:o3 + 16 * 128].reshape(16, 128)
+    b3 = th[o3 + 16 * 128:o3 + 16 * 128 + 16]
+    ym, ys = y_mean.cpu().numpy(), y_std.cpu().numpy()
+    w3[:12] *= ys[:, None]
+    b3[:12] = b3[:12] * ys + ym
+    sur = apic.Surrogate(th.astype(np.float32), mean, std, device=dev)
     plan.close()
     return sur, float(loss[0]), float(loss[-8:].mean())
 
