@@ -222,3 +222,28 @@ def test_surrogate_gain_on_background_tiles():
     assert fell[trust].mean() > 0.99
     assert np.array_equal(zb.cpu().numpy()[trust & fell], zbcf.cpu().numpy()[trust & fell])
     assert rmse(zb, trust) < 0.5 * rmse(zbs, trust)
+
+
+def test_fallback_rule_at_its_extremes():
+    """Host-forced thresholds: with rho_max infinite the surrogate is kept on
+    every tile; with rho_max 0 and the trust limits infinite the closed form
+    (the least-squares minimiser of the residual, so any other estimate has
+    rho > 0) is kept on every tile.  The chosen coefficients are then exactly
+    the corresponding candidate."""
+    dev = torch.device(DEV)
+    plan = apic.Plan(SS.geometry())
+    rng = np.random.default_rng(21)
+    uv = rng.uniform(-1, 1, (24, 2))
+    imgs, _ = SS.make_tiles(uv, rng.uniform(size=24) < 0.5, seed=5, device=dev)
+    pos = torch.tensor(uv, dtype=torch.float32, device=dev)
+    sur = apic.Surrogate(apic.init_mlp_params(13), np.zeros(34), np.ones(34), device=DEV)
+    _log("fallback rule, forced extremes")
+    z, zcf, zs, _, st = apic.estimate_pupil_sur(plan, imgs, pos, sur, rho_max=1e30)
+    st = st.cpu().numpy()
+    assert np.all(st & apic.TILE_SURROGATE_USED) and not np.any(st & apic.TILE_FALLBACK_USED)
+    assert torch.equal(z[:, 3:], zs[:, 3:])
+    z, zcf, zs, _, st = apic.estimate_pupil_sur(plan, imgs, pos, sur, rho_max=0.0,
+                                                 kappa_max=1e30, resid_max=1e30)
+    st = st.cpu().numpy()
+    assert np.all(st & apic.TILE_FALLBACK_USED) and not np.any(st & apic.TILE_SURROGATE_USED)
+    assert torch.equal(z, zcf)
