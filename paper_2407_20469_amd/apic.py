@@ -765,6 +765,23 @@ class Surrogate:
     def model(self):
         return MlpModel(self.theta.data_ptr(), self.mean.data_ptr(), self.std.data_ptr())
 
+    def save(self, path):
+        """Checkpoint: parameters, input normalisation and Adam state (.npz)."""
+        np.savez(path, theta=self.theta.cpu().numpy(), in_mean=self.mean.cpu().numpy(),
+                 in_std=self.std.cpu().numpy(), adam_m=self.m.cpu().numpy(),
+                 adam_v=self.v.cpu().numpy(), adam_t=np.int64(self.t))
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        """Resume from a checkpoint written by save()."""
+        import torch
+        with np.load(path, allow_pickle=False) as f:
+            sur = cls(f["theta"], f["in_mean"], f["in_std"], device=device)
+            sur.m = torch.as_tensor(f["adam_m"], device=device).contiguous()
+            sur.v = torch.as_tensor(f["adam_v"], device=device).contiguous()
+            sur.t = int(f["adam_t"])
+        return sur
+
     def forward(self, inputs, stream=None):
         import torch
         x = inputs.contiguous().to(torch.float32)

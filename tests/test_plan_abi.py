@@ -162,3 +162,20 @@ def test_workspace_grows_with_tiles_and_mixed_classes():
     mixed = apic.tile_descs(2, 16, 64, 0)
     mixed[1].geom = 1
     assert plan.workspace_bytes(mixed) > plan.workspace_bytes(two)
+
+
+def test_surrogate_checkpoint_round_trip(tmp_path):
+    """Parameters, input normalisation and Adam state survive save / load
+    (host tensors; no GPU needed)."""
+    theta = apic.init_mlp_params(3)
+    sur = apic.Surrogate(theta, np.arange(34.0), np.ones(34) * 2.0, device="cpu")
+    sur.m += 0.25
+    sur.v += 0.5
+    sur.t = 123
+    path = tmp_path / "sur.npz"
+    sur.save(path)
+    back = apic.Surrogate.load(path, device="cpu")
+    assert np.array_equal(back.theta.numpy(), theta)
+    assert np.array_equal(back.mean.numpy(), np.arange(34.0, dtype=np.float32))
+    assert np.array_equal(back.m.numpy(), sur.m.numpy()) and np.array_equal(back.v.numpy(), sur.v.numpy())
+    assert back.t == 123
