@@ -80,6 +80,8 @@ __global__ __launch_bounds__(kPixThreads) void k_pix_cg(ClassArgs a, double tol,
   if (tid < a.n_bf) sled[tid] = (int)a.pix_tab[np + nr + tid];  // LED pixels
   const float *wrow = a.at<float>(t, a.lay.gram);
   const float *brow = wrow + pix_pad_f(nr);
+  // the iterate and the residual follow the two float arrays of pix_pad_f(nr)
+  // elements each, i.e. pix_pad_f(nr) doubles into the region
   double *x = reinterpret_cast<double *>(a.tile(t) + a.lay.gram) + pix_pad_f(nr);
   double *r = x + pix_pad_d(np);
 
