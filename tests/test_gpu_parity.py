@@ -199,3 +199,33 @@ def test_status_flags_on_bad_input(small):
     st = status.cpu().numpy()
     assert st[1] & apic.TILE_NONFINITE_INPUT
     assert st[0] & apic.TILE_LOG_FLOOR
+
+
+@pytest.mark.parametrize("rings,frac", [(((0.30, 4, 0.0), (0.385, 4, 0.5)), 0.39),
+                                        (((0.385, 4, 0.5),), 0.45)], ids=["unknown39", "unknown45"])
+def test_darkfield_at_large_unknown_fractions(rings, frac):
+    """Edge of the darkfield solve: 4 NA-matched LEDs and darkfield LEDs far
+    out, so that each darkfield image leaves 39% or 45% of its pupil
+    unknown (the paper reports the extension stays solvable up to about
+    42%) and Q holds only about twice as many equations as unknowns.  The
+    GPU must still match the oracle's regularised solve."""
+    import apic_synth as S
+    from apic_synth.leds import led_rings
+    n = 128
+    kbf = led_rings(n, [(0.25, 4, 0.0, True)])
+    kdf = led_rings(n, [(na, c, o, False) for na, c, o in rings])
+    w = S.Workload(f"edge{frac}", n, kbf, kdf, upsample=2, n_tiles=1, seed_id=71,
+                   coeffs=S.pupil_random((71, 2, 0))[None, :] * 0.5, positions=np.zeros((1, 2)))
+    plan = apic.Plan(w.geometry_kwargs())
+    tab = plan.query(6).reshape(-1, 5)
+    got_frac = (tab[:, 0] / plan.sizes()["n_pix"]).max()
+    assert abs(got_frac - frac) < 0.01
+    imgs = workload_images(w)
+    _log(f"darkfield edge: unknown fraction {got_frac:.2f}, min M/N_u "
+         f"{(tab[:, 1] / np.maximum(tab[:, 0], 1))[tab[:, 0] > 0].min():.1f}")
+    field, z, status = apic.reconstruct(plan, torch.tensor(imgs, device=DEV))
+    ref = oracle.reconstruct(imgs[0], oracle_geometry(w))
+    err = rel_l2(field[0].cpu().numpy(), ref["field"])
+    dz = np.abs(z[0].cpu().numpy() - ref["c"]).max()
+    _log(f"  field rel-L2 {err:.2e}, max|dc| {dz:.1e}, status {int(status[0])}")
+    assert err < 1e-4 and dz < 1e-3
