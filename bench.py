@@ -52,6 +52,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def run_env():
+    """Software and hardware the line was measured on."""
+    import torch
+    from paper_2407_20469_amd import apic
+    return {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+            "torch": torch.__version__, "library": apic.load_library().apic_version().decode(),
+            "host_cores": len(os.sched_getaffinity(0))}
+
+
 def measured_traffic():
     """HBM bytes per gram launch from the committed counter summary, or None when
     the gram's sources changed since the counters were taken."""
@@ -294,6 +303,7 @@ def run_slide_stream(args, dev):
         "slide_extrapolation": {"scanned_tiles_first_20000_raster": int(mask.ravel()[:20000].sum()),
                                 "est_s": float(mask.ravel()[:20000].sum()) * wall / T},
         "nonfinite_tiles": bad,
+        "env": run_env(),
     }
     st.close()
     print(json.dumps(out), flush=True)
@@ -552,6 +562,7 @@ def main():
         "pixel_pupil": pixel,
         "assembly": assembly,
         "rgb": rgb,
+        "env": run_env(),
     }
     if not args.no_cpu_baseline:
         b0 = int(order[0][0])
