@@ -5,9 +5,12 @@ Default workload (one step = the whole method over one batch): 1024 tiles of
 32 darkfield images (rings at NA 0.30 and 0.38), Poisson noise at 1e4
 photons, float32 inputs resident in HBM, complex64 output on the 2x grid
 (512 x 512 per tile).  Metric: output Mpx/s of the batched path (a prepared
-tile batch, chunk sizes picked by the autotuner); the plain path (one tile
-per call, same kernels) and a graph replay of the batched step are reported
-beside it.
+tile batch, chunk sizes picked by the autotuner, the pupil of every tile
+chosen between the learned surrogate and the closed-form solve by the
+fallback rule); the plain path (one tile per call, closed form only, same
+kernels) and a graph replay of the batched step are reported beside it.  The
+surrogate is trained on the GPU before the timed region on the workload's own
+closed-form estimates; ``--no-surrogate`` times the closed-form batch alone.
 
 ``--workload uneven`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
 in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
@@ -27,7 +30,7 @@ sample is the first ``--tiles`` scanned tiles of the raster order (default
 256).
 
     python bench.py [--steps K] [--warmup W] [--workload grid|uneven|slide|rgb] [--tiles T]
-                    [--no-autotune] [--no-cpu-baseline]
+                    [--no-autotune] [--no-surrogate] [--no-cpu-baseline]
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -166,6 +169,34 @@ def assembly_timing(field, w, overlap=64, ramp=32.0):
             "prepare_ms_host": prep_ms, "phases_ms_host": phase_ms}
 
 
+def fit_surrogate(x, y, seed, epochs=200):
+    """Train the surrogate on inputs x (T, 34) and Noll 4..15 labels y (T, 12),
+    both device tensors: standardised inputs and labels, with the labels'
+    de-standardisation folded exactly into the last layer afterwards.
+    Returns (surrogate, first loss, mean of the last 8 losses)."""
+    import numpy as np
+    import torch
+    from paper_2407_20469_amd import apic
+    rng = np.random.default_rng(seed)
+    n = x.shape[0]
+    y_mean, y_std = y.mean(0), y.std(0) + 1e-6
+    mean = x.mean(0).cpu().numpy()
+    std = x.std(0).cpu().numpy() + 1e-6
+    sur = apic.Surrogate(apic.init_mlp_params(seed), mean, std, device=x.device)
+    order = np.concatenate([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+    loss = sur.train(x, ((y - y_mean) / y_std).contiguous(), order, batch=128,
+                     lr=1e-3).cpu().numpy()
+    th = sur.theta.cpu().numpy().astype(np.float64)
+    o3 = 128 * 64 + 128 + 128 * 128 + 128
+    w3 = th[o3:o3 + 16 * 128].reshape(16, 128)
+    b3 = th[o3 + 16 * 128:o3 + 16 * 128 + 16]
+    ym, ys = y_mean.cpu().numpy(), y_std.cpu().numpy()
+    w3[:12] *= ys[:, None]
+    b3[:12] = b3[:12] * ys + ym
+    sur = apic.Surrogate(th.astype(np.float32), mean, std, device=x.device)
+    return sur, float(loss[0]), float(loss[-8:].mean())
+
+
 def train_slide_surrogate(dev, n_train=512, seed=41):
     """Surrogate for the 512 px slide geometry, trained on the GPU on the
     closed-form pupil estimates of brightfield-only content tiles at random
@@ -182,25 +213,28 @@ def train_slide_surrogate(dev, n_train=512, seed=41):
     z, diag, feat, st = apic.estimate_pupil(plan, imgs)
     del imgs
     x = torch.cat([torch.tensor(uv, dtype=torch.float32, device=dev), feat], dim=1)
-    y = z[:, 3:15]
-    y_mean, y_std = y.mean(0), y.std(0) + 1e-6
-    mean = x.mean(0).cpu().numpy()
-    std = x.std(0).cpu().numpy() + 1e-6
-    sur = apic.Surrogate(apic.init_mlp_params(seed), mean, std, device=dev)
-    order = np.concatenate([rng.permutation(n_train) for _ in range(200)]).astype(np.int32)
-    loss = sur.train(x, ((y - y_mean) / y_std).contiguous(), order, batch=128,
-                     lr=1e-3).cpu().numpy()
-    # standardised labels: the de-standardisation folded exactly into the last layer
-    th = sur.theta.cpu().numpy().astype(np.float64)
-    o3 = 128 * 64 + 128 + 128 * 128 + 128
-    w3 = th[o3:o3 + 16 * 128].reshape(16, 128)
-    b3 = th[o3 + 16 * 128:o3 + 16 * 128 + 16]
-    ym, ys = y_mean.cpu().numpy(), y_std.cpu().numpy()
-    w3[:12] *= ys[:, None]
-    b3[:12] = b3[:12] * ys + ym
-    sur = apic.Surrogate(th.astype(np.float32), mean, std, device=dev)
     plan.close()
-    return sur, float(loss[0]), float(loss[-8:].mean())
+    return fit_surrogate(x, z[:, 3:15].contiguous(), seed)
+
+
+def train_grid_surrogate(plan, images, w, dev, seed=43, trust_quantile=0.4):
+    """Surrogate for the grid workload, trained on the GPU on the workload's
+    own closed-form pupil estimates, at the tiles' field positions, of the
+    tiles whose solve is best supported (weight sum above the given quantile).
+    Returns (surrogate, positions (T, 2) on the device, summary)."""
+    import numpy as np
+    import torch
+    from paper_2407_20469_amd import apic
+    stack = images[:w.n_tiles * w.n_img * w.n * w.n].view(w.n_tiles, w.n_img, w.n, w.n)
+    z, diag, feat, st = apic.estimate_pupil(plan, stack)
+    pos = torch.tensor(w.positions, dtype=torch.float32, device=dev)
+    x = torch.cat([pos, feat], dim=1)
+    sw = diag[:, 2]
+    keep = sw >= torch.quantile(sw, trust_quantile)
+    sur, l0, l1 = fit_surrogate(x[keep].contiguous(), z[keep, 3:15].contiguous(), seed)
+    note = {"trained_on": f"closed-form estimates of the workload's {int(keep.sum())} "
+                          f"best-supported tiles", "loss_first": l0, "loss_last": l1}
+    return sur, pos, note
 
 
 def run_slide_stream(args, dev):
@@ -383,6 +417,14 @@ def main():
     zern = torch.empty((n_total, 15), dtype=torch.float32, device=dev)
     status = torch.empty((n_total,), dtype=torch.int32, device=dev)
     batch = apic.Batch(plan, descs)
+    sur_note = None
+    if args.workload == "grid" and not args.no_surrogate:
+        t0 = time.time()
+        sur, sur_pos, sur_note = train_grid_surrogate(plan, images, ws_list[0], dev)
+        batch.set_surrogate(sur, sur_pos)
+        torch.cuda.synchronize()
+        log(f"surrogate trained in {time.time() - t0:.1f} s (loss {sur_note['loss_first']:.4f} "
+            f"-> {sur_note['loss_last']:.5f})")
     budget = int(args.ws_gb * 2 ** 30)
     tune = None
     if not args.no_autotune:
@@ -424,11 +466,21 @@ def main():
     log(f"timed {args.steps} steps: {ms:.1f} ms/step")
     st = status.cpu().numpy()
     bad = int(((st & (apic.TILE_NONFINITE_INPUT | apic.TILE_NONFINITE_OUT)) != 0).sum())
+    if sur_note is not None:
+        sur_note["surrogate_kept"] = int(((st & apic.TILE_SURROGATE_USED) != 0).sum())
+        sur_note["closed_form_kept"] = int(((st & apic.TILE_FALLBACK_USED) != 0).sum())
+        log(f"surrogate kept on {sur_note['surrogate_kept']} tiles, closed form on "
+            f"{sur_note['closed_form_kept']}")
 
     # the same step captured into a graph and replayed (the uneven batch's
     # chunked 512 px classes enqueue ~10^5 launches: no graph there by default)
     graph_ms = None
-    if args.graph if args.graph is not None else args.workload == "grid":
+    want_graph = args.graph if args.graph is not None else args.workload == "grid"
+    if want_graph and (sur_note is not None or any(c["lanes"] != 1 for c in batch.classes())):
+        log("graph replay skipped: graphs are offered for one-lane batches without the "
+            "surrogate only")
+        want_graph = False
+    if want_graph:
         gstream = torch.cuda.Stream()
         torch.cuda.synchronize()
         batch.capture(images, field, zern, status, ws, gstream)
@@ -544,6 +596,9 @@ def main():
                   "tiles": n_total, "classes": [[w.n, w.n_bf, w.n_df, w.n_tiles] for w in ws_list]}
     config["mode"] = "prepared batch, classes on concurrent streams, autotuned chunks" \
         if tune else "prepared batch, classes on concurrent streams"
+    if sur_note is not None:
+        config["mode"] += ", surrogate pupil with closed-form fallback"
+        config["surrogate"] = sur_note
     out = {
         "metric": METRIC, "value": mpx_step / (ms * 1e-3), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,

@@ -67,7 +67,8 @@ extern "C" {
 typedef enum {
   APIC_OK = 0,
   APIC_EINVAL = -1,       /* bad argument (null pointer, size, offset, workspace too small) */
-  APIC_EUNSUPPORTED = -2, /* geometry outside what the kernels are built for */
+  APIC_EUNSUPPORTED = -2, /* geometry outside what the kernels are built for, or a
+                             configuration the call does not offer */
   APIC_EHIP = -3,         /* a HIP runtime call failed */
   APIC_ENOMEM = -4,       /* plan allocation failed */
   APIC_EPLAN = -5         /* plan invalid, corrupted, or not uploaded to this device */
@@ -261,7 +262,10 @@ apic_status apic_fft2(int32_t l, int32_t batch, int32_t inverse, int32_t precisi
  * sizes and LED counts overlaps its classes.  apic_batch_capture records one
  * such call on `stream` (not the NULL stream) into a graph owned by the batch;
  * apic_batch_launch replays it (same buffers; contents may change between
- * replays).  Outputs and workspace as apic_reconstruct_tiles; the workspace
+ * replays); it returns APIC_EUNSUPPORTED, before any capture starts, for a
+ * batch with a two-lane class (apic_batch_set_chunk) or with the surrogate on
+ * (apic_batch_set_surrogate), which run eagerly only.  Outputs and workspace
+ * as apic_reconstruct_tiles; the workspace
  * size is apic_batch_workspace_bytes.  A batch keeps a pointer to its plan:
  * destroy the batch first. */
 typedef struct apic_batch apic_batch;
@@ -436,6 +440,22 @@ apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
                                        float *zernike_out, float *field_out,
                                        uint32_t *tile_status, void *workspace,
                                        size_t workspace_bytes, void *stream);
+
+/* A prepared batch with the surrogate choosing each tile's pupil by the rule
+ * of apic_estimate_pupil_sur (learned prior of the paper's discussion section,
+ * checked against the closed form of Eq. 10).  After this call every
+ * apic_batch_reconstruct, apic_batch_capture and apic_batch_autotune on
+ * `batch` runs the surrogate and the fallback test between the pupil solve
+ * and the stitching (apic_batch_capture refuses such a batch); model == NULL
+ * switches it off again.  `positions`
+ * float [T][2] (device, indexed by the batch's tile index) and the model's
+ * device buffers are borrowed, not copied: they must stay valid, and may
+ * change contents, while the batch uses them.  Drops a captured graph.
+ * APIC_EINVAL for a bad batch, a malformed model, or a model without
+ * positions. */
+apic_status apic_batch_set_surrogate(apic_batch *batch, const apic_mlp_model *model,
+                                     const float *positions, float rho_max, float kappa_max,
+                                     float resid_max);
 
 /* ------------------------------------------------------------- slide stream
  * Whole-slide scanning (Sec. 2.5 and 3.2: a slide is scanned tile by tile and

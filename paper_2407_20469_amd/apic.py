@@ -41,7 +41,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_mlp_forward", "apic_mlp_train", "apic_mlp_grad", "apic_bf16_gemm",
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
-           "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk",
+           "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk", "apic_batch_set_surrogate",
            "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
            "apic_estimate_pupil_pixel", "apic_assembly_create", "apic_assembly_destroy",
            "apic_assemble_phases", "apic_blend", "apic_rgb_combine",
@@ -131,6 +131,7 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_launch.argtypes = [P, P]
     lib.apic_batch_classes.argtypes = [P, ctypes.POINTER(i32), P, P, P, P, P]
     lib.apic_batch_set_chunk.argtypes = [P, i32, i32, i32]
+    lib.apic_batch_set_surrogate.argtypes = [P, P, P, f32, f32, f32]
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
@@ -337,6 +338,26 @@ class Batch:
         _check("apic_batch_set_chunk", self.lib.apic_batch_set_chunk(self.handle, cls, tiles,
                                                                      lanes))
         self._refresh()
+        self._bound = None
+
+    def set_surrogate(self, sur, positions, rho_max=0.05, kappa_max=1e6, resid_max=1.0):
+        """Run the surrogate and its fallback rule in every later call of this
+        batch (apic_batch_set_surrogate); ``sur=None`` switches it off.
+        ``positions`` is a float32 (T, 2) device tensor in batch order.  The
+        batch borrows the model's and the positions' device memory, so both
+        are kept referenced here."""
+        import torch
+        if sur is None:
+            _check("apic_batch_set_surrogate", self.lib.apic_batch_set_surrogate(
+                self.handle, None, None, 0.0, 0.0, 0.0))
+            self._sur = None
+        else:
+            pos = positions.to(torch.float32).contiguous()
+            mdl = sur.model()
+            _check("apic_batch_set_surrogate", self.lib.apic_batch_set_surrogate(
+                self.handle, ctypes.byref(mdl), _ptr(pos), float(rho_max), float(kappa_max),
+                float(resid_max)))
+            self._sur = (sur, mdl, pos)
         self._bound = None
 
     def autotune(self, images, field, zernike, status, workspace_ptr, workspace_bytes,

@@ -665,6 +665,8 @@ struct apic_batch {
   std::vector<hipEvent_t> join;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool use_sur = false;           // pupil stage with the surrogate and fallback rule
+  apic::SurrogateArgs sur{};
 };
 
 using namespace apic;
@@ -1081,7 +1083,9 @@ static void batch_drop_graph(apic_batch *b) {
 static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count,
                                    const float *images, char *ws, uint32_t *status,
                                    const CallIO &io, hipStream_t st) {
-  const unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT;
+  const unsigned mask = S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT | (b->use_sur ? S_SUR : 0u);
+  CallIO iol = io;
+  iol.sur = b->sur;
   const ClassRun &r = b->runs[c];
   ClassArgs a = make_args(b->plan, r, images, ws, status, reinterpret_cast<const char *>(b->d_desc));
   a.ws = ws + b->cls_ws[c];
@@ -1102,7 +1106,7 @@ static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count
       ac.ws += lane_bytes;
       sc = b->lane_stream[c];
     }
-    const apic_status rc = run_class(b->plan, r, ac, mask, io, sc);
+    const apic_status rc = run_class(b->plan, r, ac, mask, iol, sc);
     if (rc) return rc;
   }
   if (two) {
@@ -1237,6 +1241,13 @@ apic_status apic_batch_capture(apic_batch *batch, const float *images, const flo
                                float *zernike_out, float *field_out, uint32_t *tile_status,
                                void *workspace, size_t workspace_bytes, void *stream) {
   if (!batch_ok(batch) || !stream) return APIC_EINVAL;
+  // capture is offered only for one lane per class without the surrogate
+  // stage: the capture of a two-lane batch with the surrogate ended in a
+  // host-side crash whose cause is not known, so both are refused here,
+  // before any capture starts
+  if (batch->use_sur) return APIC_EUNSUPPORTED;
+  for (const int32_t l : batch->lanes)
+    if (l != 1) return APIC_EUNSUPPORTED;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   batch_drop_graph(batch);
   APIC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1274,6 +1285,19 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
     if (lanes) lanes[c] = batch->lanes[c];
     if (tile_bytes) tile_bytes[c] = batch->plan->geoms[r.geom].lay.stride;
   }
+  return APIC_OK;
+}
+
+apic_status apic_batch_set_surrogate(apic_batch *batch, const apic_mlp_model *model,
+                                     const float *positions, float rho_max, float kappa_max,
+                                     float resid_max) {
+  if (!batch_ok(batch)) return APIC_EINVAL;
+  if (model && (!model_ok(model) || !positions)) return APIC_EINVAL;
+  batch->use_sur = model != nullptr;
+  batch->sur = model ? SurrogateArgs{model->theta, model->in_mean, model->in_std, positions,
+                                     rho_max, kappa_max, resid_max}
+                     : SurrogateArgs{};
+  batch_drop_graph(batch);
   return APIC_OK;
 }
 

@@ -10,6 +10,8 @@ class is checked against the FP64 oracle at field rel-L2 1e-4 and Noll
 coefficients 1e-3 rad.
 """
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -183,6 +185,91 @@ def test_chunked_and_autotuned_batch_match_plain(uneven):
     torch.cuda.synchronize()
     assert np.array_equal(field.cpu().numpy(), ref_f)
     assert np.array_equal(status.cpu().numpy(), ref_s)
+    batch.close()
+
+
+def _const_surrogate(c_const):
+    """A surrogate whose weights are all zero, so that it predicts the output
+    bias: Noll coefficients 4..15 = c_const on every tile."""
+    theta = np.zeros_like(apic.init_mlp_params(0))
+    b3 = 128 * 64 + 128 + 128 * 128 + 128 + 16 * 128
+    assert theta.size == b3 + 16
+    theta[b3:b3 + 12] = c_const
+    return apic.Surrogate(theta, np.zeros(34), np.ones(34), device=DEV)
+
+
+def _plain_sur(plan, descs, images, n_fld_el, pos, sur, rho_max):
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    ws = apic.Workspace()
+    wp, wb = ws.get(plan.workspace_bytes(descs), images.device)
+    mdl = sur.model()
+    code = plan.lib.apic_reconstruct_tiles_sur(
+        plan.handle, len(descs), descs, apic._ptr(images), apic._ptr(pos), ctypes.byref(mdl),
+        float(rho_max), 1e6, 1.0, apic._ptr(zern), apic._ptr(field), apic._ptr(status), wp, wb,
+        apic._stream(None))
+    assert code == apic.APIC_OK
+    torch.cuda.synchronize()
+    return field.cpu().numpy(), zern.cpu().numpy(), status.cpu().numpy()
+
+
+def test_batch_with_surrogate(uneven):
+    """The prepared batch with the surrogate and its fallback rule: eager, on
+    two lanes it reproduces apic_reconstruct_tiles_sur on the same
+    descriptors exactly; with the surrogate forced on every tile
+    the fields match the oracle given the chosen coefficients (field rel-L2
+    1e-4); switching the surrogate off restores the plain batch."""
+    ws_, imgs, order, flags, plan, descs, n_fld_el, images = uneven
+    rng = np.random.default_rng(41)
+    c_const = rng.uniform(-0.1, 0.1, 12).astype(np.float32)
+    sur = _const_surrogate(c_const)
+    pos = torch.tensor(rng.uniform(-1, 1, (len(descs), 2)), dtype=torch.float32, device=DEV)
+    batch = apic.Batch(plan, descs)
+    for rho_max in (1e30, 0.05):
+        _log(f"batch + surrogate, rho_max {rho_max:g}")
+        ref_f, ref_z, ref_s = _plain_sur(plan, descs, images, n_fld_el, pos, sur, rho_max)
+        batch.set_surrogate(sur, pos, rho_max=rho_max)
+        for lanes in (1, 2):
+            for i in range(len(batch.classes())):
+                batch.set_chunk(i, 1 if lanes == 2 else 0, lanes=lanes)
+            field, zern, status = _buffers(len(descs), n_fld_el)
+            batch.reconstruct(images, field, zern, status, apic.Workspace())
+            torch.cuda.synchronize()
+            assert np.array_equal(field.cpu().numpy(), ref_f)
+            assert np.array_equal(zern.cpu().numpy(), ref_z)
+            assert np.array_equal(status.cpu().numpy(), ref_s)
+        used = (ref_s & apic.TILE_SURROGATE_USED) != 0
+        _log(f"  surrogate kept on {int(used.sum())} of {len(descs)} tiles")
+        if rho_max > 1:
+            assert used.all()
+            assert np.array_equal(ref_z[:, 3:], np.broadcast_to(c_const, (len(descs), 12)))
+            for t, (c, i) in enumerate(order):
+                if flags[t]:
+                    continue
+                w = ws_[c]
+                ref = oracle.reconstruct(imgs[c][i], oracle_geometry(w),
+                                         zernike=ref_z[t].astype(np.float64))
+                nf = w.n * w.upsample
+                d = descs[t]
+                got = ref_f[d.field_offset:d.field_offset + nf * nf].reshape(nf, nf)
+                err = rel_l2(got, ref["field"])
+                _log(f"  tile {t} (class {c}): field rel-L2 {err:.2e} vs oracle")
+                assert err < 1e-4
+        else:
+            assert (~used).any()  # the constant guess is far off on these tiles
+    # graphs are offered for one-lane batches without the surrogate only: the
+    # refusal comes from the host before any capture starts
+    stream = torch.cuda.Stream()
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    with pytest.raises(apic.ApicError):
+        batch.capture(images, field, zern, status, apic.Workspace(), stream)
+    # surrogate off: the plain batch again
+    batch.set_surrogate(None, None)
+    plain_f, plain_z, _ = _plain(plan, descs, images, n_fld_el)
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    assert np.array_equal(field.cpu().numpy(), plain_f)
+    assert np.array_equal(zern.cpu().numpy(), plain_z)
     batch.close()
 
 
