@@ -36,3 +36,60 @@ def test_grid_batch_full_size_sampled_parity():
               f"kappa {ref['pupil']['kappa']:.1f}", flush=True)
         assert dz < 1e-3
         assert err < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_grid_batch_with_surrogate_full_size():
+    """The benchmark's timed configuration: the prepared batch of the 1024 grid
+    tiles with the surrogate trained on their own closed-form estimates (the
+    benchmark's recipe) and autotuned chunks.  Every tile equals the plain
+    surrogate call bit for bit; sampled tiles match the oracle given the
+    coefficients the fallback rule chose."""
+    import bench
+    dev = torch.device("cuda:0")
+    w = S.grid_batch(n_tiles=1024)
+    print("[gpu-test] synth 1024 grid tiles", flush=True)
+    images = synth_batch(w, dev)
+    flat = images.reshape(-1)
+    plan = apic.Plan(w.geometry_kwargs())
+    plan.upload()
+    print("[gpu-test] train the surrogate (benchmark recipe)", flush=True)
+    sur, pos, note = bench.train_grid_surrogate(plan, flat, w, dev)
+    descs, n_img_el, n_fld_el = apic.mixed_descs(plan, np.zeros(w.n_tiles, np.int64))
+    assert n_img_el == flat.numel()
+    batch = apic.Batch(plan, descs)
+    batch.set_surrogate(sur, pos)
+    field = torch.empty(n_fld_el, dtype=torch.complex64, device=dev)
+    zern = torch.empty((w.n_tiles, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((w.n_tiles,), dtype=torch.int32, device=dev)
+    buf = torch.empty(batch.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+    print("[gpu-test] autotune and run the batch", flush=True)
+    batch.autotune(flat, field, zern, status, (buf.data_ptr() + 255) & ~255,
+                   batch.workspace_bytes, slack=0.0)
+    del buf
+    batch.reconstruct(flat, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    print("[gpu-test] plain surrogate call on the same tiles", flush=True)
+    f_ref, z_ref, s_ref = apic.reconstruct_sur(plan, images, pos, sur)
+    torch.cuda.synchronize()
+    nf = w.n * w.upsample
+    assert torch.equal(field.view(w.n_tiles, nf, nf), f_ref)
+    assert torch.equal(zern, z_ref)
+    assert torch.equal(status, s_ref)
+    del f_ref
+    st = status.cpu().numpy()
+    used = int(((st & apic.TILE_SURROGATE_USED) != 0).sum())
+    print(f"[gpu-test] surrogate kept on {used} of {w.n_tiles} tiles", flush=True)
+    assert not (st & (apic.TILE_NONFINITE_INPUT | apic.TILE_NONFINITE_OUT)).any()
+    assert np.all((st & (apic.TILE_SURROGATE_USED | apic.TILE_FALLBACK_USED)) != 0)
+    geom = oracle.Geometry(**w.geometry_kwargs())
+    fv = field.view(w.n_tiles, nf, nf)
+    for t in (0, 613):
+        zc = zern[t].cpu().numpy()
+        ref = oracle.reconstruct(images[t].cpu().numpy().astype(np.float64), geom,
+                                 zernike=zc.astype(np.float64))
+        err = rel_l2(fv[t].cpu().numpy(), ref["field"])
+        print(f"[gpu-test] grid tile {t} (status {int(st[t])}): field rel-L2 {err:.3e} "
+              f"given the chosen coefficients", flush=True)
+        assert err < 1e-4
+    batch.close()
