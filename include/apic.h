@@ -35,7 +35,9 @@
  *     owned by the caller, except where an entry point says HOST (the slide
  *     streamer's image and field buffers, assembly positions and phases,
  *     colour gains).  apic_geometry and apic_tile_desc arrays are HOST
- *     memory, read during the call and not retained.
+ *     memory, read during the call and not retained.  Exception:
+ *     apic_batch_set_surrogate keeps the model's and the positions' device
+ *     pointers until the surrogate is switched off or the batch destroyed.
  *   - A plan owns its host tables; it uploads its device tables on first use
  *     (or on apic_plan_upload) to the current device and owns them until
  *     apic_plan_destroy.  Calls never allocate: scratch comes from the
