@@ -352,7 +352,7 @@ class Batch:
                 self.handle, None, None, 0.0, 0.0, 0.0))
             self._sur = None
         else:
-            pos = positions.to(torch.float32).contiguous()
+            pos = _positions(positions, self.n_tiles, images_device=None)
             mdl = sur.model()
             _check("apic_batch_set_surrogate", self.lib.apic_batch_set_surrogate(
                 self.handle, ctypes.byref(mdl), _ptr(pos), float(rho_max), float(kappa_max),
@@ -431,6 +431,18 @@ class Batch:
         if self._bound is None:
             raise RuntimeError("launch before capture")
         _check("apic_batch_launch", self.lib.apic_batch_launch(self.handle, _stream(stream)))
+
+
+def _positions(positions, n_tiles, images_device):
+    """Surrogate positions as a contiguous float32 (T, 2) device tensor; the
+    kernels read row t for every tile t, so the shape is checked here."""
+    import torch
+    if not isinstance(positions, torch.Tensor) or positions.shape != (n_tiles, 2):
+        raise ValueError(f"positions must be a ({n_tiles}, 2) tensor")
+    if positions.device.type != "cuda" or (images_device is not None and
+                                           positions.device != images_device):
+        raise ValueError("positions must live on the images' GPU")
+    return positions.to(torch.float32).contiguous()
 
 
 def _batch_args(plan, images, geom=0):
@@ -878,7 +890,7 @@ def estimate_pupil_sur(plan, images, positions, sur, rho_max=0.05, kappa_max=1e6
     descs = tile_descs(T, n_img, n, 0)
     ws = workspace or Workspace()
     wp, wb = ws.get(plan.workspace_bytes(descs), dev)
-    pos = positions.contiguous().to(torch.float32)
+    pos = _positions(positions, T, images.device)
     mdl = sur.model()
     _check("apic_estimate_pupil_sur", plan.lib.apic_estimate_pupil_sur(
         plan.handle, T, descs, _ptr(images), _ptr(pos), ctypes.byref(mdl), float(rho_max),
@@ -901,7 +913,7 @@ def reconstruct_sur(plan, images, positions, sur, rho_max=0.05, kappa_max=1e6, r
     descs = tile_descs(T, n_img, n, nf * nf)
     ws = workspace or Workspace()
     wp, wb = ws.get(plan.workspace_bytes(descs), dev)
-    pos = positions.contiguous().to(torch.float32)
+    pos = _positions(positions, T, images.device)
     mdl = sur.model()
     _check("apic_reconstruct_tiles_sur", plan.lib.apic_reconstruct_tiles_sur(
         plan.handle, T, descs, _ptr(images), _ptr(pos), ctypes.byref(mdl), float(rho_max),

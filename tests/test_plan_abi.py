@@ -179,3 +179,18 @@ def test_surrogate_checkpoint_round_trip(tmp_path):
     assert np.array_equal(back.mean.numpy(), np.arange(34.0, dtype=np.float32))
     assert np.array_equal(back.m.numpy(), sur.m.numpy()) and np.array_equal(back.v.numpy(), sur.v.numpy())
     assert back.t == 123
+
+
+def test_surrogate_positions_are_checked_on_the_host():
+    """The surrogate kernels read positions row t for every tile t: a buffer of
+    the wrong shape or off the GPU is refused before any call."""
+    import torch
+    from paper_2407_20469_amd import apic
+    with pytest.raises(ValueError):
+        apic._positions(torch.zeros((3, 2)), 4, None)
+    with pytest.raises(ValueError):
+        apic._positions(torch.zeros((4, 3)), 4, None)
+    with pytest.raises(ValueError):
+        apic._positions(np.zeros((4, 2), np.float32), 4, None)
+    with pytest.raises(ValueError):  # right shape, host memory
+        apic._positions(torch.zeros((4, 2)), 4, None)
