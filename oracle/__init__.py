@@ -17,6 +17,7 @@ closed-form solution", arXiv 2407.20469):
   patch assembly ....... Sec. 2.5, overlap blending  (assemble.py)
   colour combination ... Sec. 3.3, RGB channels      (rgb.py)
   surrogate MLP twin ... not in the paper             (mlp.py)
+  surrogate fallback ... not in the paper; Eq. 10 judges (fallback.py)
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import or execute anything in this package.  The product path

@@ -247,3 +247,53 @@ def test_fallback_rule_at_its_extremes():
     st = st.cpu().numpy()
     assert np.all(st & apic.TILE_FALLBACK_USED) and not np.any(st & apic.TILE_SURROGATE_USED)
     assert torch.equal(z, zcf)
+
+
+def test_fallback_decision_matches_oracle():
+    """Every tile's choice against the oracle's rule (oracle/fallback.py),
+    evaluated on the oracle's FP64 normal-equation sums of the same images with
+    the GPU's two candidates (the decision is taken on the same float32
+    coefficients on both sides).  rho_max is set at the median of the oracle's
+    rho so that both outcomes occur; a tile within 1e-3 relative of a
+    threshold is not compared, since a different rounding order of the sums
+    may decide it."""
+    import oracle
+    from oracle import fallback as FB
+    dev = torch.device(DEV)
+    geom = SS.geometry()
+    plan = apic.Plan(geom)
+    rng = np.random.default_rng(31)
+    T = 24
+    uv = rng.uniform(-1, 1, (T, 2))
+    imgs, _ = SS.make_tiles(uv, rng.uniform(size=T) < 0.3, seed=9, device=dev)
+    pos = torch.tensor(uv, dtype=torch.float32, device=dev)
+    sur = apic.Surrogate(apic.init_mlp_params(17), np.zeros(34), np.ones(34), device=DEV)
+    _log("fallback decision vs oracle: candidates")
+    _, zcf, zs, _, _ = apic.estimate_pupil_sur(plan, imgs, pos, sur, rho_max=1e30)
+    zcf, zs = zcf.cpu().numpy(), zs.cpu().numpy()
+    g = oracle.Geometry(**geom)
+    host = imgs.cpu().numpy().astype(np.float64)
+    ref = []
+    for t in range(T):
+        spectra, _ = oracle.pipeline.kk_stack(host[t], g)
+        sums = oracle.aberration_sums(spectra, g.k_bf, g.r)
+        ref.append((sums, float(np.linalg.cond(sums["A"]))))
+    rhos = [FB.choose(s, zcf[t, 3:], zs[t, 3:], k, 0.0, 1e30, 1e30)[1]
+            for t, (s, k) in enumerate(ref)]
+    rho_max = float(np.median(rhos))
+    _log(f"  oracle rho {min(rhos):.3g} .. {max(rhos):.3g}, rho_max {rho_max:.3g}")
+    _, _, _, _, st = apic.estimate_pupil_sur(plan, imgs, pos, sur, rho_max=rho_max,
+                                             kappa_max=1e6, resid_max=1.0)
+    st = st.cpu().numpy()
+    compared, outcomes = 0, set()
+    for t, (sums, kappa) in enumerate(ref):
+        use_sur, rho, r_cf = FB.choose(sums, zcf[t, 3:], zs[t, 3:], kappa, rho_max, 1e6, 1.0)
+        if (abs(rho - rho_max) < 1e-3 * rho_max or abs(r_cf - 1.0) < 1e-3
+                or abs(kappa - 1e6) < 1e3):
+            continue
+        compared += 1
+        outcomes.add(use_sur)
+        assert bool(st[t] & apic.TILE_SURROGATE_USED) == use_sur, t
+        assert bool(st[t] & apic.TILE_FALLBACK_USED) == (not use_sur), t
+    _log(f"  {compared} of {T} tiles compared")
+    assert compared >= T - 2 and outcomes == {True, False}
