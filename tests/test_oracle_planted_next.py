@@ -1,16 +1,18 @@
 """Plant plausible mistakes in the oracle's pixel-domain pupil solve, patch
-assembly, background statistic and colour combination (on the CPU), and check
-that one of their pins catches each."""
+assembly, background statistic, colour combination and surrogate fallback
+rule (on the CPU), and check that one of their pins catches each."""
 
 import numpy as np
 import pytest
 
 import test_oracle_assemble as PA
 import test_oracle_background as PB
+import test_oracle_fallback as PF
 import test_oracle_pixel_pupil as PP
 import test_oracle_rgb as PR
 from oracle import assemble as oa
 from oracle import background as obg
+from oracle import fallback as ofb
 from oracle import pupil_pixel as opp
 from oracle import rgb as orgb
 
@@ -83,3 +85,25 @@ def test_inverted_grey_world_gains_are_caught(monkeypatch):
     monkeypatch.setattr(orgb, "grey_world_gains", inverted)
     with pytest.raises(AssertionError):
         PR.test_constant_channels_come_out_grey()
+
+
+def test_sign_slip_in_the_expanded_residual_is_caught(monkeypatch):
+    """S_bb + 2 c.b + c.A c instead of S_bb - 2 c.b + c.A c."""
+    def slipped(sums, c12):
+        c = np.asarray(c12, np.float64)
+        return float((sums["sbb"] + 2.0 * (c @ sums["b"]) + c @ sums["A"] @ c) / sums["sw"])
+    monkeypatch.setattr(ofb, "residual", slipped)
+    with pytest.raises(AssertionError):
+        PF.test_residual_matches_brute_force_over_rows()
+
+
+def test_inverted_rho_threshold_is_caught(monkeypatch):
+    """Closed form kept when the surrogate is within rho_max instead of beyond."""
+    def inverted(sums, c_cf, c_sur, kappa, rho_max, kappa_max, resid_max):
+        r_cf = ofb.residual(sums, c_cf)
+        rho = float(np.sqrt(max(0.0, ofb.residual(sums, c_sur) - r_cf)))
+        keep_cf = rho <= rho_max and kappa <= kappa_max and r_cf <= resid_max
+        return (not keep_cf), rho, r_cf
+    monkeypatch.setattr(ofb, "choose", inverted)
+    with pytest.raises(AssertionError):
+        PF.test_decision_at_the_thresholds()
