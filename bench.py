@@ -7,10 +7,12 @@ photons, float32 inputs resident in HBM, complex64 output on the 2x grid
 (512 x 512 per tile).  Metric: output Mpx/s of the batched path (a prepared
 tile batch, chunk sizes picked by the autotuner, the pupil of every tile
 chosen between the learned surrogate and the closed-form solve by the
-fallback rule); the plain path (one tile per call, closed form only, same
-kernels) and a graph replay of the batched step are reported beside it.  The
-surrogate is trained on the GPU before the timed region on the workload's own
-closed-form estimates; ``--no-surrogate`` times the closed-form batch alone.
+fallback rule).  Reported beside it: the same batch with the surrogate off
+(the closed-form batched method, ``closed_form_batch``), a graph replay of
+that closed-form step, and the plain path (one tile per call, closed form,
+same kernels).  The surrogate is trained on the GPU before the timed region on
+the workload's own closed-form estimates; ``--no-surrogate`` times the
+closed-form batch as the main value.
 
 ``--workload uneven`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
 in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
@@ -472,13 +474,32 @@ def main():
         log(f"surrogate kept on {sur_note['surrogate_kept']} tiles, closed form on "
             f"{sur_note['closed_form_kept']}")
 
-    # the same step captured into a graph and replayed (the uneven batch's
-    # chunked 512 px classes enqueue ~10^5 launches: no graph there by default)
+    # the closed-form batch (surrogate off) on the same tiles, timed the same
+    # way after the surrogate step: the plain batched method beside it
+    closed_form = None
+    if sur_note is not None:
+        batch.set_surrogate(None, None)
+        batch.reconstruct(images, field, zern, status, ws)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for i in range(args.steps):
+            batch.reconstruct(images, field, zern, status, ws)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        cf_ms = c0.elapsed_time(c1) / args.steps
+        closed_form = {"value": mpx_step / (cf_ms * 1e-3), "unit": "Mpx/s", "ms_per_step": cf_ms}
+        log(f"closed-form batch (surrogate off): {cf_ms:.1f} ms/step")
+
+    # a step captured into a graph and replayed: the closed-form batch, since
+    # graphs are offered for one-lane batches without the surrogate (the
+    # uneven batch's chunked 512 px classes enqueue ~10^5 launches: no graph
+    # there by default)
     graph_ms = None
     want_graph = args.graph if args.graph is not None else args.workload == "grid"
-    if want_graph and (sur_note is not None or any(c["lanes"] != 1 for c in batch.classes())):
-        log("graph replay skipped: graphs are offered for one-lane batches without the "
-            "surrogate only")
+    if want_graph and any(c["lanes"] != 1 for c in batch.classes()):
+        log("graph replay skipped: graphs are offered for one-lane batches only")
         want_graph = False
     if want_graph:
         gstream = torch.cuda.Stream()
@@ -604,8 +625,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": config,
+        "closed_form_batch": closed_form,
         "graph": None if graph_ms is None else {"value": mpx_step / (graph_ms * 1e-3),
-                                                "ms_per_step": graph_ms},
+                                                "ms_per_step": graph_ms,
+                                                "of": "closed-form batch"},
         "plain": {"value": (nf0 * nf0 / 1e6) / plain_s, "unit": "Mpx/s", "tiles_timed": P,
                   "ms_per_tile": plain_s * 1e3, "class": 0},
         "autotune": tune,
