@@ -300,14 +300,15 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
  * a captured graph. */
 apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, int32_t lanes);
 /* Autotuner.  For class `cls` (all classes when cls < 0), times the method
- * on its first k tiles for k = 1, 2, 4, ... up to the class size, as long as
- * k tiles' workspace fits
- * `workspace_bytes` (and stops once doubling k gains under 3% past k = 4, or
- * after a run longer than 10 s), then sets the
+ * (with the surrogate stage when apic_batch_set_surrogate switched it on) on
+ * its first k tiles for k = 1, 2, 4, ... up to the class size, as long as k
+ * tiles' workspace fits `workspace_bytes` (and stops once doubling k gains
+ * under 3% past k = 4, or after a run longer than 10 s).  It then sets the
  * class's chunk to the smallest k whose time per tile is within (1 + slack)
- * of the best, then tries two lanes of half that chunk over the same tiles
- * (same workspace) and keeps them if 2% faster; if the classes' chunk blocks together exceed `workspace_bytes`
- * (they run concurrently), the largest blocks are halved until they fit.
+ * of the best, tries two lanes of half that chunk over the same tiles (same
+ * workspace) and keeps them if 2% faster.  If the classes' chunk blocks
+ * together exceed `workspace_bytes` (they run concurrently), the largest
+ * blocks are halved until they fit.
  * Synchronises the host with `stream` after every run (not
  * capturable); writes outputs and status of the timed tiles.  `ms_per_tile`
  * (nullable, one per class, indexed by class) receives the best time.  Changes
