@@ -32,7 +32,7 @@ import scipy.linalg
 from .grid import k_grid, circ, fft_index, in_range
 from .zernike import pupil_phase
 
-ROW_CHUNK = 4096
+ROW_CHUNK = 2048
 
 
 def coords_of(mask):
@@ -119,17 +119,53 @@ def autocorrelation(p_hat, p, d):
     return out
 
 
+def autocorrelation_grid(p_hat):
+    """R(d) = sum_p P_hat(p) conj(P_hat(p + d)) for every d in [-N, N)^2.
+
+    The spectrum is placed at its signed positions on a 2N x 2N grid, where
+    no product of the linear sum wraps, and the correlation is taken by FFT:
+    with a = conj(P_hat) on that grid, ifft2(|fft2(a)|^2)(d) = sum_p conj(a(p))
+    a(p + d) = R(d).  Returned as a (2N, 2N) array indexed by d mod 2N."""
+    n = p_hat.shape[0]
+    ky, kx = k_grid(n)
+    a = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    a[np.mod(ky, 2 * n), np.mod(kx, 2 * n)] = np.conj(p_hat)
+    fa = np.fft.fft2(a)
+    return np.fft.ifft2(np.abs(fa) ** 2)
+
+
+def rhs_by_correlation(p_hat, q, u, b):
+    """C^H b = N^-2 sum_{k in Q} P_hat(u + k) b(k) for every u in U, as a
+    linear cross-correlation on a 2N x 2N grid (every u + k lies in
+    [-N, N - 2], so nothing wraps): with x = conj(b) placed at Q,
+    ifft2(conj(fft2(x)) fft2(P_hat))(u) = sum_k b(k) P_hat(k + u)."""
+    n = p_hat.shape[0]
+    ky, kx = k_grid(n)
+    grid_p = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    grid_p[np.mod(ky, 2 * n), np.mod(kx, 2 * n)] = p_hat
+    grid_b = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    grid_b[np.mod(q[:, 0], 2 * n), np.mod(q[:, 1], 2 * n)] = np.conj(b)
+    corr = np.fft.ifft2(np.conj(np.fft.fft2(grid_b)) * np.fft.fft2(grid_p))
+    return corr[np.mod(u[:, 0], 2 * n), np.mod(u[:, 1], 2 * n)] / float(n) ** 2
+
+
 def gram_t_minus_e(p_hat, sets):
     """The same gram as ``normal_equations_fullq`` through the identity
     G[u, u'] = R(u' - u)/N^4 - sum_{k in E} P_hat(u+k) conj(P_hat(u'+k))/N^4,
-    where the first term sums over every k (all of P - U) and E = (P - U) - Q."""
+    where the first term sums over every k (all of P - U) and E = (P - U) - Q.
+    R comes from ``autocorrelation_grid``; the E-sum is C restricted to the
+    rows of E, built chunk by chunk."""
     n = p_hat.shape[0]
-    u, p, e = sets["U"], sets["P"], sets["E"]
-    diff = (u[None, :, :] - u[:, None, :]).reshape(-1, 2)  # (u' - u) for [u, u']
-    uniq, inv = np.unique(diff, axis=0, return_inverse=True)
-    t = autocorrelation(p_hat, p, uniq)[inv.reshape(-1)].reshape(len(u), len(u))
-    ce = conv_matrix(p_hat, e, u)
-    return t / float(n) ** 4 - ce.conj().T @ ce
+    u, e = sets["U"], sets["E"]
+    rgrid = autocorrelation_grid(p_hat)
+    dy = np.mod(u[None, :, 0] - u[:, None, 0], 2 * n)   # (u' - u) for [u, u']
+    dx = np.mod(u[None, :, 1] - u[:, None, 1], 2 * n)
+    g = rgrid[dy, dx] / float(n) ** 4
+    del dy, dx
+    for s in range(0, len(e), ROW_CHUNK):
+        ce = conv_matrix(p_hat, e[s:s + ROW_CHUNK], u)
+        g -= ce.conj().T @ ce
+    return g
 
 
 def extend_darkfield(obj_hat, known, intensity, k_j, c, r, ridge=1e-4, gram="fullq"):
@@ -148,9 +184,11 @@ def extend_darkfield(obj_hat, known, intensity, k_j, c, r, ridge=1e-4, gram="ful
     qq = sets["Q"]
     yy, xx = fft_index(qq[:, 0], qq[:, 1], n)
     b = np.conj(f_img[yy, xx] - f_pp[yy, xx])
-    g, v = normal_equations_fullq(p_hat, qq, sets["U"], b)
     if gram == "t-e":
         g = gram_t_minus_e(p_hat, sets)
+        v = rhs_by_correlation(p_hat, qq, sets["U"], b)
+    else:
+        g, v = normal_equations_fullq(p_hat, qq, sets["U"], b)
     lam = ridge * np.trace(g).real / len(sets["U"])
     cf = scipy.linalg.cho_factor(g + lam * np.eye(len(sets["U"])), lower=True)
     x = scipy.linalg.cho_solve(cf, v)
