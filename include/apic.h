@@ -111,6 +111,15 @@ typedef struct {
   double ridge_pupil;      /* mu: ridge mu * tr(A)/12 in Eq. 10 (default 1e-9)      */
   double ridge_darkfield;  /* lambda: ridge lambda * tr(G)/N_u in Eq. 13 (1e-4)     */
   double log_floor_rel;    /* eps = log_floor_rel * mean(I) before the log (1e-6)   */
+  int32_t pupil_bands;     /* 1 (default): solve Eq. 10 coarse to fine, first on the
+                              rows with |K| <= f r for f = 0.05, 0.1, 0.2, 0.4, 0.8,
+                              1.6 (bands of fewer than 256 rows skipped), each band
+                              re-wrapping beta about the previous band's solution
+                              (the seeded variant) and solved with a ridge of
+                              0.1 tr(A)/12, then on every row; phase
+                              differences near K = 0 stay unwrapped however large
+                              the aberration.  0: the single pass of Eq. 10.
+                              Without effect when a seed is given.               */
 } apic_geometry;
 
 /* One tile of a batch (host memory). */
@@ -145,7 +154,11 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *          1: darkfield step j's known set P        (ky, kx pairs)
  *          2: darkfield step j's linear region Q    (ky, kx pairs)
  *          3: darkfield step j's excluded set E     (ky, kx pairs)
- *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs
+ *          4: pupil rows (i, l, ky, kx, cell) quintuples over all pairs, in
+ *             the plan's order: sorted (stably) by the first band of the
+ *             pupil continuation that holds them
+ *          7: row counts of the continuation's band passes (empty when
+ *             pupil_bands is 0)
  *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps,
  *             unknowns per gram block, E rows per gram chunk, pupil pixels
  *          6: per darkfield step (N_u, |Q|, |E|, live gram chunks of all lower
@@ -388,6 +401,18 @@ typedef struct {
   const float *theta;    /* [APIC_MLP_PARAMS] device */
   const float *in_mean;  /* [34] device */
   const float *in_std;   /* [34] device */
+  int32_t seeds_solve;   /* pupil stages only.  0: the closed form (the
+                            continuation of apic_geometry.pupil_bands, or one
+                            pass seeded by the caller's zernike_seed) runs as
+                            usual and the surrogate's prediction competes with
+                            it.  1: the prediction seeds the solve instead (a
+                            plain pass over the rows gives the features, then
+                            one pass re-wrapped about the prediction, Eq. 10's
+                            seeded variant); the closed form that results
+                            judges the prediction.  A caller's zernike_seed is
+                            not accepted with 1 (APIC_EINVAL).  In either case
+                            both candidates are judged on the final pass's
+                            sums, R(c - c0) with c0 that pass's seed.         */
 } apic_mlp_model;
 
 /* outputs[n][12] = network(inputs[n][34]). */

@@ -18,7 +18,20 @@ Readings taken:
   weight w = |z|;
 * least squares by normal equations with a ridge mu * tr(A) / 12, FP64
   Cholesky;
-* optional seeded variant: beta is re-wrapped around a seed c0, one pass.
+* optional seeded variant: beta is re-wrapped around a seed c0, one pass;
+* coarse-to-fine continuation (the default; the paper does not discuss the
+  wrap of beta): the relation is first solved on the rows with |K| <= f r for
+  growing f (0.05, 0.1, 0.2, 0.4, 0.8, 1.6), each band's solution being the
+  seed about which the next band re-wraps beta, and last on every row seeded
+  by the last band.  Near K = 0 the row operator is about K times a gradient
+  difference of the pupil phase, so the low-|K| rows stay unwrapped however
+  large the aberration, and every later band only has to add a correction
+  smaller than pi.  A band holding fewer than MIN_BAND_ROWS rows is skipped.
+  The band solves carry a strong ridge (PUPIL_BAND_RIDGE tr(A) / 12): the
+  low-|K| rows leave some directions of c nearly unconstrained, and the ridge
+  keeps the band's increment there near zero instead of fitting noise, which
+  the next band's re-wrap would then amplify; the final pass keeps the
+  ordinary ridge.  With a caller's seed the one seeded pass is used instead.
 """
 
 import numpy as np
@@ -30,6 +43,9 @@ from .zernike import zernike, SOLVED
 N_FEATURE_ANGLE = 8
 N_FEATURE_BAND = 4
 N_FEATURES = N_FEATURE_ANGLE * N_FEATURE_BAND
+PUPIL_BANDS = (0.05, 0.1, 0.2, 0.4, 0.8, 1.6)
+MIN_BAND_ROWS = 256
+PUPIL_BAND_RIDGE = 0.1
 
 
 def pupil_pairs(n, k_bf, r):
@@ -76,11 +92,12 @@ def wrap(x):
     return x - 2.0 * np.pi * np.round(x / (2.0 * np.pi))
 
 
-def aberration_sums(spectra, k_bf, r, seed=None):
+def aberration_sums(spectra, k_bf, r, seed=None, k_max=None):
     """Normal-equation sums of Eq. 10 over all overlapping pairs.
 
     spectra  complex (n_bf, N, N) KK spectra in FFT order
     seed     optional Noll coefficients c0 (15,) for the re-wrapped variant
+    k_max    optional: only the rows with |K| <= k_max
     Returns dict with A (12x12), b (12), sbb, sw, rows, and the 32 per-cell
     weight sums used as surrogate features.
     """
@@ -94,6 +111,11 @@ def aberration_sums(spectra, k_bf, r, seed=None):
     cells = np.zeros(N_FEATURES)
     c0 = None if seed is None else np.asarray(seed, dtype=np.float64)[3:15]
     for i, l, K_y, K_x in pupil_pairs(n, k_bf, r):
+        if k_max is not None:
+            sel = K_x.astype(np.float64) ** 2 + K_y.astype(np.float64) ** 2 <= k_max * k_max
+            K_y, K_x = K_y[sel], K_x[sel]
+            if len(K_y) == 0:
+                continue
         yy, xx = fft_index(K_y, K_x, n)
         z = spectra[i][yy, xx] * np.conj(spectra[l][yy, xx])
         beta = np.arctan2(z.imag, z.real)
@@ -131,9 +153,22 @@ def solve_aberration(sums, ridge=1e-9, seed=None):
             "sw": sums["sw"], "min_pivot": float(np.min(np.diag(cf[0]).real))}
 
 
-def estimate_pupil(spectra, k_bf, r, ridge=1e-9, seed=None):
-    """Eq. 8-10 end to end: sums, then the regularised solve."""
+def estimate_pupil(spectra, k_bf, r, ridge=1e-9, seed=None, bands=PUPIL_BANDS):
+    """Eq. 8-10 end to end: sums, then the regularised solve.
+
+    Without a seed the solve runs the coarse-to-fine continuation over
+    ``bands`` (fractions of r; an empty tuple gives the paper's single pass).
+    The returned diagnostics and sums are those of the last pass over all
+    rows; with a seed (given or from the bands) its sums hold the re-wrapped
+    phases, so R(c) is the residual of the returned coefficients."""
+    if seed is None and bands:
+        for f in bands:
+            band = aberration_sums(spectra, k_bf, r, seed=seed, k_max=f * r)
+            if band["rows"] < MIN_BAND_ROWS:
+                continue
+            seed = solve_aberration(band, ridge=PUPIL_BAND_RIDGE, seed=seed)["c"]
     sums = aberration_sums(spectra, k_bf, r, seed=seed)
     out = solve_aberration(sums, ridge=ridge, seed=seed)
     out["sums"] = sums
+    out["seed"] = None if seed is None else np.asarray(seed, dtype=np.float64).copy()
     return out

@@ -9,7 +9,7 @@ import numpy as np
 
 from .grid import pupil_radius
 from .kk import kk_field, kk_spectrum
-from .aberration import estimate_pupil
+from .aberration import estimate_pupil, PUPIL_BANDS
 from .stitch import stitch_brightfield
 from .darkfield import extend_darkfield
 from .output import upsampled_field
@@ -28,6 +28,7 @@ class Geometry:
     ridge_pupil: float = 1e-9
     ridge_darkfield: float = 1e-4
     log_floor_rel: float = 1e-6
+    pupil_bands: int = 1
     extra: dict = dc_field(default_factory=dict)
 
     @property
@@ -66,7 +67,8 @@ def reconstruct(images, geom, seed=None, zernike=None, gram="fullq", keep=False)
     images = np.asarray(images, dtype=np.float64)
     r = geom.r
     spectra, floor_hit = kk_stack(images, geom)
-    pupil = estimate_pupil(spectra, geom.k_bf, r, ridge=geom.ridge_pupil, seed=seed)
+    pupil = estimate_pupil(spectra, geom.k_bf, r, ridge=geom.ridge_pupil, seed=seed,
+                           bands=PUPIL_BANDS if geom.pupil_bands else ())
     c = pupil["c"] if zernike is None else np.asarray(zernike, dtype=np.float64)
     obj_hat, known = stitch_brightfield(spectra, geom.k_bf, c, r)
     bf_hat = obj_hat.copy()

@@ -63,12 +63,12 @@ class Geometry(ctypes.Structure):
                 ("na_obj", ctypes.c_double), ("n_bf", ctypes.c_int32), ("n_df", ctypes.c_int32),
                 ("k_bf", ctypes.POINTER(ctypes.c_int32)), ("k_df", ctypes.POINTER(ctypes.c_int32)),
                 ("ridge_pupil", ctypes.c_double), ("ridge_darkfield", ctypes.c_double),
-                ("log_floor_rel", ctypes.c_double)]
+                ("log_floor_rel", ctypes.c_double), ("pupil_bands", ctypes.c_int32)]
 
 
 class MlpModel(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_void_p), ("in_mean", ctypes.c_void_p),
-                ("in_std", ctypes.c_void_p)]
+                ("in_std", ctypes.c_void_p), ("seeds_solve", ctypes.c_int32)]
 
 
 class TileDesc(ctypes.Structure):
@@ -201,6 +201,7 @@ class Plan:
             c.ridge_pupil = float(g.get("ridge_pupil", 1e-9))
             c.ridge_darkfield = float(g.get("ridge_darkfield", 1e-4))
             c.log_floor_rel = float(g.get("log_floor_rel", 1e-6))
+            c.pupil_bands = int(g.get("pupil_bands", 1))
             g["n_bf"], g["n_df"] = int(c.n_bf), int(c.n_df)
         self.handle = ctypes.c_void_p()
         _check("apic_plan_create", self.lib.apic_plan_create(arr, len(self.geoms),
@@ -794,9 +795,11 @@ class Surrogate:
         self.v = torch.zeros_like(self.theta)
         self.grad = torch.zeros_like(self.theta)
         self.t = 0
+        self.seeds_solve = False    # True: the prediction seeds the re-wrapped pupil solve
 
     def model(self):
-        return MlpModel(self.theta.data_ptr(), self.mean.data_ptr(), self.std.data_ptr())
+        return MlpModel(self.theta.data_ptr(), self.mean.data_ptr(), self.std.data_ptr(),
+                        int(bool(self.seeds_solve)))
 
     def save(self, path):
         """Checkpoint: parameters, input normalisation and Adam state (.npz)."""

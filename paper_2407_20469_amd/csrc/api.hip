@@ -199,6 +199,8 @@ ClassArgs make_args(const apic_plan *p, const ClassRun &r, const float *images, 
   a.log_floor_rel = (float)g.log_floor_rel;
   a.n_rows = g.n_rows;
   a.n_chunks = g.n_chunks;
+  a.n_band = (int)g.band_rows.size();
+  for (int b = 0; b < a.n_band; ++b) a.band_rows[b] = g.band_rows[b];
   a.nu_pad = g.nu_pad;
   a.ridge_pupil = g.ridge_pupil;
   a.ridge_df = g.ridge_df;
@@ -303,17 +305,56 @@ template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t
   return APIC_OK;
 }
 
-apic_status run_pupil(const ClassArgs &a, const float *seed, float *zout, float *diag,
-                      float *feat, hipStream_t st) {
-  ProfScope ps(APIC_PROF_PUPIL, (double)a.T * a.n_rows * 16.0, st);  // two complex64 reads per row
-  hipLaunchKernelGGL(k_pupil_partial, dim3(a.T * a.n_chunks), dim3(256), 0, st, a, seed);
+// One pass of Eq. 8-10 over the first ab.n_rows rows: partial sums, their
+// fixed-order reduction, and (unless sums_only) the 12x12 solve.
+apic_status pupil_pass(const ClassArgs &ab, const float *caller_seed, int seed_src, int final_pass,
+                       bool sums_only, float *zout, float *diag, float *feat, hipStream_t st) {
+  hipLaunchKernelGGL(k_pupil_partial, dim3(ab.T * ab.n_chunks), dim3(256), 0, st, ab, caller_seed,
+                     seed_src);
   APIC_LAUNCHED();
-  hipLaunchKernelGGL(k_pupil_reduce, dim3(a.T), dim3(128), 0, st, a);
+  hipLaunchKernelGGL(k_pupil_reduce, dim3(ab.T), dim3(128), 0, st, ab);
   APIC_LAUNCHED();
-  hipLaunchKernelGGL(k_pupil_solve, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, seed, zout,
-                     diag, feat);
+  if (sums_only) return APIC_OK;
+  hipLaunchKernelGGL(k_pupil_solve, dim3(blocks_for(ab.T, 64)), dim3(64), 0, st, ab, caller_seed,
+                     seed_src, final_pass, zout, diag, feat);
   APIC_LAUNCHED();
   return APIC_OK;
+}
+
+// A band pass of the continuation: the first `rows` of the class's sorted
+// pupil rows, solved with the band ridge.
+ClassArgs band_args(const ClassArgs &a, int rows) {
+  ClassArgs ab = a;
+  ab.n_rows = rows;
+  ab.n_chunks = std::max(1, (rows + kAbChunk - 1) / kAbChunk);
+  ab.ridge_pupil = kPupilBandRidge;
+  return ab;
+}
+
+// Eq. 8-10 for every tile of the class.  With a caller's seed: one seeded
+// pass.  Otherwise the coarse-to-fine continuation: each band pass solves on
+// the rows with |K| <= f r, re-wrapped about the previous band's solution
+// (kept in the tile's seed block), and the final pass over every row is
+// seeded by the last band.  *final_src receives the seed source of the final
+// pass (its sums are re-wrapped about that seed).
+apic_status run_pupil(const ClassArgs &a, const float *caller_seed, float *zout, float *diag,
+                      float *feat, int *final_src, hipStream_t st) {
+  int64_t rows = a.n_rows;
+  if (!caller_seed)
+    for (int b = 0; b < a.n_band; ++b) rows += a.band_rows[b];
+  ProfScope ps(APIC_PROF_PUPIL, (double)a.T * rows * 16.0, st);  // two complex64 reads per row
+  int src = caller_seed ? kSeedCaller : kSeedNone;
+  if (!caller_seed) {
+    for (int b = 0; b < a.n_band; ++b) {
+      apic_status rc = pupil_pass(band_args(a, a.band_rows[b]), nullptr,
+                                  b == 0 ? kSeedNone : kSeedBand, 0, false, nullptr, nullptr,
+                                  nullptr, st);
+      if (rc) return rc;
+    }
+    if (a.n_band > 0) src = kSeedBand;
+  }
+  if (final_src) *final_src = src;
+  return pupil_pass(a, caller_seed, src, 1, false, zout, diag, feat, st);
 }
 
 apic_status run_stitch(const ClassArgs &a, int64_t n_disk, float *spec_out, hipStream_t st) {
@@ -499,9 +540,25 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
     rc = run_kk<N>(a, reinterpret_cast<c32 *>(io.kk_out), st);
     if (rc) return rc;
   }
-  if (st_mask & S_PUPIL) {
-    rc = run_pupil(a, io.seed, io.zout, io.diag, io.feat, st);
+  int pupil_src = io.seed ? kSeedCaller : kSeedNone;
+  const bool sur_seeds = (st_mask & S_SUR) && io.sur.seed_mode;
+  if ((st_mask & S_PUPIL) && !sur_seeds) {
+    rc = run_pupil(a, io.seed, io.zout, io.diag, io.feat, &pupil_src, st);
     if (rc) return rc;
+  }
+  if ((st_mask & S_PUPIL) && sur_seeds) {
+    // the surrogate seeds the solve: a plain pass gives the features, the
+    // surrogate predicts, and one pass re-wrapped about its prediction gives
+    // the closed form that judges it
+    ProfScope ps(APIC_PROF_PUPIL, (double)a.T * a.n_rows * 32.0, st);
+    rc = pupil_pass(a, nullptr, kSeedNone, 1, true, nullptr, nullptr, nullptr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_surrogate_predict, dim3(blocks_for(a.T, kMlpTile)), dim3(256), 0, st, a,
+                       io.sur);
+    APIC_LAUNCHED();
+    rc = pupil_pass(a, nullptr, kSeedSur, 1, false, io.zout, io.diag, io.feat, st);
+    if (rc) return rc;
+    pupil_src = kSeedSur;
   }
   if (st_mask & S_PIX) {
     if (a.n_pix == 0) return APIC_EUNSUPPORTED;
@@ -512,11 +569,13 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
     APIC_LAUNCHED();
   }
   if (st_mask & S_SUR) {
-    hipLaunchKernelGGL(k_surrogate_predict, dim3(blocks_for(a.T, kMlpTile)), dim3(256), 0, st, a,
-                       io.sur);
-    APIC_LAUNCHED();
+    if (!sur_seeds) {
+      hipLaunchKernelGGL(k_surrogate_predict, dim3(blocks_for(a.T, kMlpTile)), dim3(256), 0, st,
+                         a, io.sur);
+      APIC_LAUNCHED();
+    }
     hipLaunchKernelGGL(k_surrogate_decide, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a, io.sur,
-                       io.zout, io.zcf, io.zsur);
+                       io.seed, pupil_src, io.zout, io.zcf, io.zsur);
     APIC_LAUNCHED();
   }
   if (st_mask & S_COEF_IN) {
@@ -787,6 +846,8 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
   } else if (what == 5) {
     v = {g.n_pairs, g.n_rows, g.nu_max, g.m_max, g.ne_max, g.n_active, kGramUB, kEChunk,
          g.n_pix};
+  } else if (what == 7) {
+    v.assign(g.band_rows.begin(), g.band_rows.end());
   } else if (what == 6) {
     for (const DfStep &d : g.steps) {
       v.push_back(d.nu);
@@ -1011,7 +1072,7 @@ apic_status apic_bf16_gemm(int32_t m, int32_t n, int32_t k, const uint16_t *a, c
 }
 
 static bool model_ok(const apic_mlp_model *m) {
-  return m && m->theta && m->in_mean && m->in_std;
+  return m && m->theta && m->in_mean && m->in_std && (m->seeds_solve == 0 || m->seeds_solve == 1);
 }
 
 apic_status apic_estimate_pupil_sur(const apic_plan *plan, int32_t n_tiles,
@@ -1029,7 +1090,7 @@ apic_status apic_estimate_pupil_sur(const apic_plan *plan, int32_t n_tiles,
   io.zout = zernike_out;  // closed form first, then the surrogate stage's choice
   io.sur = SurrogateArgs{model ? model->theta : nullptr, model ? model->in_mean : nullptr,
                          model ? model->in_std : nullptr, positions, rho_max, kappa_max,
-                         resid_max};
+                         resid_max, model ? model->seeds_solve : 0};
   io.zcf = zernike_cf_out;
   io.zsur = zernike_sur_out;
   return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
@@ -1051,7 +1112,7 @@ apic_status apic_reconstruct_tiles_sur(const apic_plan *plan, int32_t n_tiles,
   io.field = field_out;
   io.sur = SurrogateArgs{model ? model->theta : nullptr, model ? model->in_mean : nullptr,
                          model ? model->in_std : nullptr, positions, rho_max, kappa_max,
-                         resid_max};
+                         resid_max, model ? model->seeds_solve : 0};
   return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
                   S_KK | S_PUPIL | S_SUR | S_STITCH | S_DF | S_OUT, io);
 }
@@ -1213,6 +1274,7 @@ apic_status apic_batch_reconstruct(apic_batch *batch, const float *images,
   if (!images || !zernike_out || !field_out || !tile_status) return APIC_EINVAL;
   if (!workspace || (int64_t)workspace_bytes < batch->ws_bytes) return APIC_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return APIC_EINVAL;
+  if (zernike_seed && batch->use_sur && batch->sur.seed_mode) return APIC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char *ws = reinterpret_cast<char *>(workspace);
   CallIO io;
@@ -1295,7 +1357,7 @@ apic_status apic_batch_set_surrogate(apic_batch *batch, const apic_mlp_model *mo
   if (model && (!model_ok(model) || !positions)) return APIC_EINVAL;
   batch->use_sur = model != nullptr;
   batch->sur = model ? SurrogateArgs{model->theta, model->in_mean, model->in_std, positions,
-                                     rho_max, kappa_max, resid_max}
+                                     rho_max, kappa_max, resid_max, model->seeds_solve}
                      : SurrogateArgs{};
   batch_drop_graph(batch);
   return APIC_OK;
@@ -1632,7 +1694,7 @@ apic_status apic_streamer_run(apic_streamer *s, int32_t n_tiles, const float *co
   if (model) {
     mask |= S_SUR;
     io.sur = SurrogateArgs{model->theta, model->in_mean, model->in_std, nullptr, rho_max,
-                           kappa_max, resid_max};
+                           kappa_max, resid_max, model->seeds_solve};
   }
   const int nch = (n_tiles + s->chunk - 1) / s->chunk;
 

@@ -75,6 +75,8 @@ struct ClassArgs {
   double r_d;             // pupil radius in double precision
   float log_floor_rel;
   int n_rows, n_chunks, nu_pad;
+  int n_band;                     // band passes of the pupil continuation (0: single pass)
+  int band_rows[kPupilBands];     // rows of each band pass (a prefix of the sorted rows)
   double ridge_pupil, ridge_df;
   int kx[kMaxImg], ky[kMaxImg];  // NA-matched first, then darkfield
   const float *images;

@@ -182,12 +182,29 @@ template <int N> struct OpKK4 {
 };
 
 // ---------------------------------------------------------------- pupil solve
+// Where a re-wrapped pupil pass takes its seed c0 (Noll 4..15) from: nowhere
+// (plain pass), the caller's [T][15] array, the tile's seed block (the
+// previous band of the coarse-to-fine continuation) or the tile's surrogate
+// prediction.
+enum SeedSrc : int { kSeedNone = 0, kSeedCaller = 1, kSeedBand = 2, kSeedSur = 3 };
+
+__device__ __forceinline__ const float *seed_of(const ClassArgs &a, int t, const float *caller,
+                                                int src) {
+  if (src == kSeedCaller) return caller + (int64_t)a.gidx(t) * 15 + 3;
+  if (src == kSeedBand) return a.at<float>(t, a.lay.seed);
+  if (src == kSeedSur) return a.at<float>(t, a.lay.sur);
+  return nullptr;
+}
+
 // One row of Eq. 10 per (pair, K): beta = arg(s_i conj(s_l)), w = |s_i s_l|,
 // a_j = Z_j(K+k_i) - Z_j(K+k_l) - Z_j(k_i) + Z_j(k_l).  A workgroup takes a
 // chunk of rows of one tile, stages (w a, a, beta, w, cell) of 256 rows in
 // LDS, and 124 threads accumulate one normal-equation entry each in FP64:
 // 78 entries of A's upper triangle, 12 of b, sum w beta^2, sum w, 32 cells.
-__global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float *seed) {
+// The rows are sorted by |K| band, so a pass over the first a.n_rows rows is
+// a pass over the rows with |K| <= f r of one band of the continuation.
+__global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float *caller_seed,
+                                                       int seed_src) {
   const int t = blockIdx.x / a.n_chunks, chunk = blockIdx.x % a.n_chunks;
   __shared__ float s_wa[256][13];
   __shared__ float s_a[256][13];
@@ -208,10 +225,11 @@ __global__ __launch_bounds__(256) void k_pupil_partial(ClassArgs a, const float 
     q = p + rem;
   }
   float c0[12];
+  const float *seed = seed_of(a, t, caller_seed, seed_src);
   const bool seeded = seed != nullptr;
   if (seeded) {
 #pragma unroll
-    for (int j = 0; j < 12; ++j) c0[j] = seed[(int64_t)a.gidx(t) * 15 + 3 + j];
+    for (int j = 0; j < 12; ++j) c0[j] = seed[j];
   }
   const c32 *stack = a.at<c32>(t, a.lay.stack);
   const int nn = a.n * a.n;
@@ -339,11 +357,16 @@ __device__ inline void jacobi_eig12(double m[12][12], double ev[12]) {
 
 // One thread per tile: c_J = (A + mu tr(A)/12 I)^-1 b by FP64 Cholesky;
 // diagnostics R(c) = (sum w beta^2 - 2 c.b + c.A.c)/sum w, kappa(A), sum w,
-// smallest pivot; surrogate features log1p(cell / N^4).
-__global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *seed,
-                                                    float *zout, float *diag, float *feat) {
+// smallest pivot; surrogate features log1p(cell / N^4).  With a seed the
+// solution is the increment and c = c0 + x.  A band pass of the continuation
+// (final = 0) writes c to the tile's seed block and nothing else; the final
+// pass writes the coefficient block, outputs, diagnostics and status.
+__global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *caller_seed,
+                                                    int seed_src, int final_pass, float *zout,
+                                                    float *diag, float *feat) {
   const int t = blockIdx.x * 64 + threadIdx.x;
   if (t >= a.T) return;
+  const float *seed = seed_of(a, t, caller_seed, seed_src);
   const double *s = a.at<double>(t, a.lay.sums);
   double A[12][12], L[12][12], b[12], x[12];
   int e = 0;
@@ -355,7 +378,7 @@ __global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *se
   for (int p = 0; p < 12; ++p) tr += A[p][p];
   const double mu = a.ridge_pupil * tr / 12.0;
   double minpiv = 1e300;
-  uint32_t bits = seed ? APIC_TILE_SEEDED : 0u;
+  uint32_t bits = seed_src == kSeedCaller ? APIC_TILE_SEEDED : 0u;
   for (int j = 0; j < 12; ++j) {
     double d = A[j][j] + mu;
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
@@ -381,6 +404,15 @@ __global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *se
     for (int k = i + 1; k < 12; ++k) v -= L[k][i] * x[k];
     x[i] = v / L[i][i];
   }
+  if (!final_pass) {
+    // the band's solution seeds the next band (read in full before writing:
+    // the seed may be this same block)
+    float nxt[12];
+    for (int j = 0; j < 12; ++j) nxt[j] = (float)(x[j] + (seed ? (double)seed[j] : 0.0));
+    float *sb = a.at<float>(t, a.lay.seed);
+    for (int j = 0; j < 12; ++j) sb[j] = nxt[j];
+    return;
+  }
   double cb = 0.0, cac = 0.0;
   for (int p = 0; p < 12; ++p) {
     cb += x[p] * b[p];
@@ -402,7 +434,7 @@ __global__ __launch_bounds__(64) void k_pupil_solve(ClassArgs a, const float *se
   float *co = a.at<float>(t, a.lay.coef);
   for (int j = 0; j < 12; ++j) {
     double cj = x[j];
-    if (seed) cj += (double)seed[(int64_t)g * 15 + 3 + j];
+    if (seed) cj += (double)seed[j];
     if (!isfinite(cj)) bits |= APIC_TILE_NONFINITE_OUT;
     co[j] = (float)cj;
     if (zout) zout[(int64_t)g * 15 + 3 + j] = (float)cj;

@@ -275,6 +275,8 @@ struct SurrogateArgs {
   float rho_max;                     // residual excess allowed before falling back (rad)
   float kappa_max;                   // tiles with kappa(A) above this keep the surrogate
   float resid_max;                   // tiles whose closed form fits worse keep the surrogate
+  int seed_mode;                     // 0: the surrogate replaces the closed form when the
+                                     // rule allows; 1: it also seeds the re-wrapped solve
 };
 
 // c_sur of every tile of the class: inputs are the tile position and the 32
@@ -310,26 +312,33 @@ __global__ __launch_bounds__(256) void k_surrogate_predict(ClassArgs a, Surrogat
 // rho = sqrt(max(0, R(c_sur) - R(c_cf))) the closed form is kept when
 // rho > rho_max on a tile where the closed form is trustworthy (kappa(A) <=
 // kappa_max and R(c_cf) <= resid_max: noise-only tiles have random wrapped
-// phase differences, R near pi^2 / 3), the surrogate otherwise.
-__global__ __launch_bounds__(64) void k_surrogate_decide(ClassArgs a, SurrogateArgs s, float *zout,
-                                                         float *zcf, float *zsur) {
+// phase differences, R near pi^2 / 3), the surrogate otherwise.  When the
+// final pupil pass was re-wrapped about a seed c0 (the caller's, the last
+// continuation band's or the surrogate's own prediction) its sums describe
+// the increment, so both candidates are judged as R(c - c0).
+__global__ __launch_bounds__(64) void k_surrogate_decide(ClassArgs a, SurrogateArgs s,
+                                                         const float *caller_seed, int seed_src,
+                                                         float *zout, float *zcf, float *zsur) {
   const int t = blockIdx.x * 64 + threadIdx.x;
   if (t >= a.T) return;
   const double *sm = a.at<double>(t, a.lay.sums);
   float *co = a.at<float>(t, a.lay.coef);
   const float *cs = a.at<float>(t, a.lay.sur);
+  const float *c0 = seed_of(a, t, caller_seed, seed_src);
   double A[12][12], b[12];
   int e = 0;
   for (int p = 0; p < 12; ++p)
     for (int q = p; q < 12; ++q, ++e) A[p][q] = A[q][p] = sm[e];
   for (int p = 0; p < 12; ++p) b[p] = sm[78 + p];
   auto resid = [&](const float *c) {
+    double d[12];
+    for (int p = 0; p < 12; ++p) d[p] = (double)c[p] - (c0 ? (double)c0[p] : 0.0);
     double cb = 0.0, cac = 0.0;
     for (int p = 0; p < 12; ++p) {
-      cb += (double)c[p] * b[p];
+      cb += d[p] * b[p];
       double r = 0.0;
-      for (int q = 0; q < 12; ++q) r += A[p][q] * (double)c[q];
-      cac += (double)c[p] * r;
+      for (int q = 0; q < 12; ++q) r += A[p][q] * d[q];
+      cac += d[p] * r;
     }
     return (sm[90] - 2.0 * cb + cac) / sm[91];
   };

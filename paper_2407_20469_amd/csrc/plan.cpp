@@ -139,6 +139,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   if (!(g.dx_um > 0) || !(g.wavelength_um > 0) || !(g.na_obj > 0)) return APIC_EINVAL;
   if (!(g.ridge_pupil >= 0) || !(g.ridge_darkfield >= 0) || !(g.log_floor_rel > 0))
     return APIC_EINVAL;
+  if (g.pupil_bands != 0 && g.pupil_bands != 1) return APIC_EINVAL;
 
   const int n = g.n;
   p.n = n;
@@ -201,6 +202,43 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   }
   p.n_rows = int(p.row_k.size());
   p.n_chunks = std::max(1, (p.n_rows + kAbChunk - 1) / kAbChunk);
+  // band of each row: the first f with Kx^2 + Ky^2 <= (f r)^2, kPupilBands
+  // if none; rows sorted by band (stable), band passes = prefixes
+  {
+    std::vector<int> band(p.n_rows);
+    std::vector<int64_t> count(kPupilBands + 1, 0);
+    for (int rI = 0; rI < p.n_rows; ++rI) {
+      const double ky = unpack_ky(p.row_k[rI]), kx = unpack_kx(p.row_k[rI]);
+      const double k2 = kx * kx + ky * ky;
+      int b = kPupilBands;
+      for (int f = 0; f < kPupilBands; ++f) {
+        const double km = kPupilBandFrac[f] * p.r;
+        if (k2 <= km * km) {
+          b = f;
+          break;
+        }
+      }
+      band[rI] = b;
+      ++count[b];
+    }
+    std::vector<int> order(p.n_rows);
+    for (int rI = 0; rI < p.n_rows; ++rI) order[rI] = rI;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return band[x] < band[y]; });
+    std::vector<uint32_t> il(p.n_rows), kk(p.n_rows);
+    for (int rI = 0; rI < p.n_rows; ++rI) {
+      il[rI] = p.row_il[order[rI]];
+      kk[rI] = p.row_k[order[rI]];
+    }
+    p.row_il.swap(il);
+    p.row_k.swap(kk);
+    p.pupil_bands = g.pupil_bands != 0;
+    p.band_rows.clear();
+    int64_t cum = 0;
+    for (int f = 0; f < kPupilBands; ++f) {
+      cum += count[f];
+      if (p.pupil_bands && cum >= kMinBandRows) p.band_rows.push_back(int(cum));
+    }
+  }
   build_pixel_tables(p, g.n_bf);
 
   // ---- darkfield sets (Eq. 11-13)
@@ -418,6 +456,7 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.sums = take(128 * 8);
   L.coef = take((16 + kMaxImg) * 4);
   L.sur = take(16 * 4);
+  L.seed = take(16 * 4);
   L.eps = take(kMaxImg * 4);
   L.stride = o;
   return APIC_OK;

@@ -22,6 +22,14 @@ constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granulari
 constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
 constexpr int kEChunk = 2;          // E rows per gram k-chunk
 constexpr int kPixMax = 7936;       // pupil pixels of the pixel-domain solve (LDS bound)
+// Coarse-to-fine continuation of the pupil solve: bands |K| <= f r for these
+// f, each band used when it holds at least kMinBandRows rows.
+constexpr int kPupilBands = 6;
+constexpr double kPupilBandFrac[kPupilBands] = {0.05, 0.1, 0.2, 0.4, 0.8, 1.6};
+constexpr int kMinBandRows = 256;
+// Ridge of the band solves (relative, mu tr(A) / 12): keeps each band's
+// increment near zero in the directions its low-|K| rows hardly constrain.
+constexpr double kPupilBandRidge = 0.1;
 constexpr uint32_t kPlanMagic = 0x41504943u;  // "APIC"
 
 // Signed (ky, kx) packed in one word: low half ky, high half kx (int16 each).
@@ -49,7 +57,7 @@ struct DfStep {
 // Per-tile workspace layout (byte offsets from the tile's base).
 struct TileLayout {
   int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, fimg = 0, ptil = 0, vec = 0,
-          gram = 0, linv = 0, part = 0, sums = 0, coef = 0, sur = 0, eps = 0, stride = 0;
+          gram = 0, linv = 0, part = 0, sums = 0, coef = 0, sur = 0, seed = 0, eps = 0, stride = 0;
 };
 
 struct GeomPlan {
@@ -59,10 +67,16 @@ struct GeomPlan {
   int64_t n_disk = 0;                // grid points inside Circ
   double ridge_pupil = 1e-9, ridge_df = 1e-4, log_floor_rel = 1e-6;
   std::vector<int32_t> kbf, kdf;     // (kx, ky) pairs
-  // pupil rows (Eq. 8-10): one row per (pair, K) with K in S_il, K != 0
+  // pupil rows (Eq. 8-10): one row per (pair, K) with K in S_il, K != 0,
+  // sorted by the first continuation band that holds them (stable, so pairs
+  // stay in order inside a band)
   int n_pairs = 0, n_rows = 0, n_chunks = 0;
   std::vector<uint32_t> row_il;      // i | l << 8 | feature cell << 16
   std::vector<uint32_t> row_k;       // packed K
+  // row counts of the continuation's band passes (rows with |K| <= f r, for
+  // the bands holding at least kMinBandRows); empty for the single pass
+  bool pupil_bands = true;
+  std::vector<int> band_rows;
   // pupil pixels (Eq. 10 with one unknown per pixel), raster order over the
   // disk (ky ascending, then kx): built when n_pix <= kPixMax.  pix_tab holds
   // the pixels' packed k, then per pupil row the pixel indices of K + K_i

@@ -70,12 +70,13 @@ int main() {
         g.ridge_pupil = 1e-9;
         g.ridge_darkfield = 1e-4;
         g.log_floor_rel = 1e-6;
+        g.pupil_bands = 1;
         apic::GeomPlan p;
         const apic_status rc = apic::build_geom_plan(g, p);
         if (rc == APIC_OK) {
           ++built;
-          std::printf("n %d n_bf %d n_df %d rows %d pix %d steps %zu walk %ld\n", n, nbf, g.n_df,
-                      p.n_rows, p.n_pix, p.steps.size(), walk(p));
+          std::printf("n %d n_bf %d n_df %d rows %d bands %zu pix %d steps %zu walk %ld\n", n, nbf,
+                      g.n_df, p.n_rows, p.band_rows.size(), p.n_pix, p.steps.size(), walk(p));
         } else {
           ++rejected;
         }

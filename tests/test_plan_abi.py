@@ -7,6 +7,8 @@ import os
 import re
 
 import numpy as np
+
+from oracle import aberration as oab
 import pytest
 
 import oracle
@@ -67,7 +69,21 @@ def test_plan_sets_equal_oracle_sets(wl):
         cells = feature_cell(w.k_bf[i], w.k_bf[l], K_y, K_x, r)
         for a, b, c in zip(K_y, K_x, cells):
             want.append((i, l, a, b, c))
-    assert np.array_equal(rows, np.array(want))
+    want = np.array(want)
+    # the same rows (the plan sorts them by continuation band)
+    assert len(rows) == len(want)
+    assert np.array_equal(rows[np.lexsort(rows.T[::-1])], want[np.lexsort(want.T[::-1])])
+    # each band pass is a prefix of the plan's rows: the oracle's rows with
+    # |K| <= f r, counted by the oracle's own band selection
+    ones = np.ones((len(w.k_bf), n, n), complex)
+    counts = [oab.aberration_sums(ones, w.k_bf, r, k_max=f * r)["rows"] for f in oab.PUPIL_BANDS]
+    want_bands = [c for c in counts if c >= oab.MIN_BAND_ROWS]
+    got_bands = list(plan.query(7))
+    assert got_bands == want_bands
+    k2 = rows[:, 2].astype(np.float64) ** 2 + rows[:, 3].astype(np.float64) ** 2
+    for f, cnt in zip(oab.PUPIL_BANDS, counts):
+        inside = k2 <= (f * r) ** 2
+        assert inside.sum() == cnt and np.all(inside[:cnt])
 
 
 def test_plan_rejects_bad_geometry():
