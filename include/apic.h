@@ -180,6 +180,30 @@ apic_status apic_reconstruct_tiles(const apic_plan *plan, int32_t n_tiles,
                                    float *field_out, uint32_t *tile_status, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* apic_reconstruct_tiles without a caller workspace, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The scratch is one static device array of
+ * APIC_STATIC_SCRATCH_BYTES (256 MiB) per GPU, held from the first call on
+ * that GPU until the process ends; the call itself allocates nothing and
+ * copies nothing from the host.  Arguments as apic_reconstruct_tiles.
+ * Preconditions, checked before anything is enqueued:
+ *   - the plan was uploaded to the current device (apic_plan_upload, which
+ *     allocates the plan's tables): else APIC_EPLAN;
+ *   - the workspace the tiles need (apic_workspace_bytes) fits the array:
+ *     else APIC_ENOMEM (e.g. 8 tiles of 256^2 with 16 + 32 images fit);
+ *   - the descriptors of each geometry class are regular (tile t of the
+ *     class at base + t * step in images, outputs and batch index; any list
+ *     of one or two tiles is): irregular lists would need a host copy, so
+ *     they return APIC_EUNSUPPORTED.
+ * Every call on a GPU uses that GPU's one array, which keeps the last call's
+ * contents (nothing in it needs clearing: every kernel writes what it later
+ * reads); calls that overlap on one GPU (several streams or threads) race. */
+#define APIC_STATIC_SCRATCH_BYTES (256ll << 20)
+apic_status apic_reconstruct_tiles_static(const apic_plan *plan, int32_t n_tiles,
+                                          const apic_tile_desc *tiles, const float *images,
+                                          const float *zernike_seed, float *zernike_out,
+                                          float *field_out, uint32_t *tile_status, void *stream);
+
 /* Fig. 2 upper half, Eq. 4-10 only.
  *   diag_out      float [T][4]: linearised residual R(c) (rad^2), kappa(A),
  *                 total weight sum w, smallest Cholesky pivot

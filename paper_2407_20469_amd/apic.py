@@ -35,7 +35,8 @@ MLP_PARAMS, MLP_INPUTS, MLP_OUTPUTS = 26896, 34, 12
 TILE_SKIP_DARKFIELD = 0x1
 
 EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_workspace_bytes",
-           "apic_plan_query", "apic_reconstruct_tiles", "apic_estimate_pupil", "apic_kk_spectra",
+           "apic_plan_query", "apic_reconstruct_tiles", "apic_reconstruct_tiles_static",
+           "apic_estimate_pupil", "apic_kk_spectra",
            "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
            "apic_profile", "apic_profile_read", "apic_calib_fma64", "apic_calib_copy",
            "apic_mlp_forward", "apic_mlp_train", "apic_mlp_grad", "apic_bf16_gemm",
@@ -104,6 +105,8 @@ def load_library(path=LIB_PATH):
                                     ctypes.POINTER(i64)]
     lib.apic_reconstruct_tiles.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, P, sz,
                                            P]
+    lib.apic_reconstruct_tiles_static.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P,
+                                                  P]
     lib.apic_estimate_pupil.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, P, P, P, sz,
                                         P]
     lib.apic_kk_spectra.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, P, sz, P]

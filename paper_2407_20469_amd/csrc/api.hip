@@ -701,6 +701,30 @@ apic_status fft2_c(int l, int batch, bool inv, const void *in, void *out, hipStr
   }
 }
 
+// ------------------------------------------------------------ static scratch
+// Scratch of apic_reconstruct_tiles_static: one array per device.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in): it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) char scratch[APIC_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_at[64] = {};
+
+apic_status static_scratch(void **out) {
+  int dev = 0;
+  APIC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return APIC_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void *p = nullptr;
+    APIC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0) return APIC_EHIP;
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return APIC_OK;
+}
+
 }  // namespace
 }  // namespace apic
 
@@ -879,6 +903,36 @@ apic_status apic_reconstruct_tiles(const apic_plan *plan, int32_t n_tiles,
   io.field = field_out;
   return run_call(plan, n_tiles, tiles, images, tile_status, workspace, workspace_bytes, stream,
                   S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT, io);
+}
+
+apic_status apic_reconstruct_tiles_static(const apic_plan *plan, int32_t n_tiles,
+                                          const apic_tile_desc *tiles, const float *images,
+                                          const float *zernike_seed, float *zernike_out,
+                                          float *field_out, uint32_t *tile_status, void *stream) {
+  if (!plan_ok(plan)) return APIC_EPLAN;
+  if (n_tiles > 0 && (!images || !zernike_out || !field_out || !tile_status)) return APIC_EINVAL;
+  std::vector<ClassRun> runs;
+  int64_t need = 0;
+  apic_status rc = layout_call(plan, n_tiles, tiles, runs, need);
+  if (rc) return rc;
+  if (n_tiles == 0) return APIC_OK;
+  if (need > (int64_t)APIC_STATIC_SCRATCH_BYTES) return APIC_ENOMEM;
+  for (const ClassRun &r : runs)
+    if (!r.affine) return APIC_EUNSUPPORTED;
+  int dev = 0;
+  APIC_HIP(hipGetDevice(&dev));
+  if (!plan->uploaded || plan->device != dev) return APIC_EPLAN;
+  void *ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc) return rc;
+  // with the plan uploaded and regular descriptors, run_call neither
+  // allocates nor copies from the host
+  CallIO io;
+  io.seed = zernike_seed;
+  io.zout = zernike_out;
+  io.field = field_out;
+  return run_call(plan, n_tiles, tiles, images, tile_status, ws, (size_t)APIC_STATIC_SCRATCH_BYTES,
+                  stream, S_KK | S_PUPIL | S_STITCH | S_DF | S_OUT, io);
 }
 
 apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
