@@ -11,8 +11,21 @@ fallback rule).  Reported beside it: the same batch with the surrogate off
 (the closed-form batched method, ``closed_form_batch``), a graph replay of
 that closed-form step, and the plain path (one tile per call, closed form,
 same kernels).  The surrogate is trained on the GPU before the timed region on
-the workload's own closed-form estimates; ``--no-surrogate`` times the
-closed-form batch as the main value.
+the closed-form estimates of 4096 training tiles disjoint from the timed ones,
+and in the timed step it seeds the re-wrapped pupil solve whose closed form
+judges it; the line reports the pupil RMSE against the truth of the chosen
+coefficients, the closed form (coarse-to-fine continuation), the single pass
+of Eq. 10, the surrogate alone and the closed form it seeds.
+``--no-surrogate`` times the closed-form batch as the main value.
+
+The gram's roofline figure counts the nonzero products of its E-sum (the
+algorithmic work, from the plan's sets), with the dense E-sum and the
+products the kernels issue beside it.  The default line also carries, each
+with its own warmup and step count, the uneven batch (one full pass of the
+4096 tiles) and the slide stream over its first 128 scanned tiles, while the
+whole run stays within its time budget (``--no-extra`` skips them), and the
+FP64 oracle timed over 16 tiles in a pool of one process per host core
+(run before the GPU is touched; ``--no-cpu-baseline`` skips it).
 
 ``--workload uneven`` runs the uneven batch instead: 4096 tiles, 128/256/512 px
 in the ratio 4:3:1, 8/12/16 NA-matched LEDs with twice as many darkfield, 40%
@@ -32,7 +45,7 @@ sample is the first ``--tiles`` scanned tiles of the raster order (default
 256).
 
     python bench.py [--steps K] [--warmup W] [--workload grid|uneven|slide|rgb] [--tiles T]
-                    [--no-autotune] [--no-surrogate] [--no-cpu-baseline]
+                    [--no-autotune] [--no-surrogate] [--no-cpu-baseline] [--no-extra]
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -81,22 +94,72 @@ def measured_traffic():
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(images_host, w):
-    """The FP64 oracle on one tile of the same workload, on the host cores."""
+def _oracle_tile(job):
+    """One tile of the FP64 oracle in a worker process (BLAS threads = 1):
+    its own forward model and Poisson draw, then the whole reconstruction."""
     import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    geom = oracle.Geometry(**w.geometry_kwargs())
+    w, t, photons = job
+    k_all = list(w.k_bf) + list(w.k_df)
+    img = oracle.forward_images(w.object(t), k_all, w.coeffs[t], w.r)
+    img = np.random.default_rng([w.seed_id, 1, t]).poisson(img * photons) / photons
+    img = img.astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
-    oracle.reconstruct(images_host.astype(np.float64), geom)
-    dt = time.perf_counter() - t0
-    mpx = (w.n * w.upsample) ** 2 / 1e6
-    return {"value": mpx / dt, "unit": "Mpx/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 tile of the workload (tile 0), full-Q FP64 oracle, {dt:.1f} s"}
+    oracle.reconstruct(img, oracle.Geometry(**w.geometry_kwargs()))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_pool(w, n_sample=None):
+    """The FP64 oracle (full-Q gram, as it stands) over a seeded subset of the
+    workload's tiles (tiles 0 .. n_sample-1, images from the oracle's own
+    forward model with Poisson noise at the workload's photon level), one tile
+    per worker process with one BLAS thread each, a pool over every host core.
+    Runs before the GPU is touched: the workers are spawned processes."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    n_sample = n_sample or max(8, min(16, cores))
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(min(cores, n_sample)) as pool:
+        per = pool.map(_oracle_tile, [(w, t, w.photons) for t in range(n_sample)])
+    wall = time.perf_counter() - t0
+    mpx = n_sample * (w.n * w.upsample) ** 2 / 1e6
+    return {"value": mpx / wall, "unit": "Mpx/s", "cores": min(cores, n_sample), "kind": "oracle",
+            "sample": f"tiles 0..{n_sample - 1} of the workload (oracle forward model, Poisson "
+                      f"1e4), full-Q FP64 oracle, one tile per process with BLAS threads = 1, "
+                      f"pool of {min(cores, n_sample)} processes on {cores} host cores: "
+                      f"{wall:.1f} s wall",
+            "per_tile_s_in_pool": {"mean": sum(per) / len(per), "max": max(per)},
+            "extrapolated_s_for_workload": wall * w.n_tiles / n_sample,
+            "extrapolation": f"linear in tiles: {w.n_tiles} / {n_sample} x the pool's wall time"}
+
+
+def gram_nonzero_flops(plan, geom):
+    """FP64 flops per tile of the nonzero products of the T-E gram's E-sum:
+    for each darkfield step and each excluded k, the n_k unknowns u with u + k
+    in P give n_k (n_k + 1) / 2 complex MACs of the Hermitian lower triangle,
+    8 flops each (counted from the plan's U, P and E tables)."""
+    import numpy as np
+    n = plan.geoms[geom]["n"]
+    h = n // 2
+    total = 0.0
+    for j in range(plan.geoms[geom]["n_df"]):
+        u = plan.query(0, geom, j).reshape(-1, 2).astype(np.int64)
+        if len(u) == 0:
+            continue
+        p = plan.query(1, geom, j).reshape(-1, 2).astype(np.int64)
+        e = plan.query(3, geom, j).reshape(-1, 2).astype(np.int64)
+        pm = np.zeros((n, n), bool)
+        pm[p[:, 0] % n, p[:, 1] % n] = True
+        for s in range(0, len(e), 256):
+            ky = u[None, :, 0] + e[s:s + 256, None, 0]
+            kx = u[None, :, 1] + e[s:s + 256, None, 1]
+            ok = (ky >= -h) & (ky < h) & (kx >= -h) & (kx < h)
+            nk = (ok & pm[ky % n, kx % n]).sum(axis=1).astype(np.float64)
+            total += float((nk * (nk + 1) / 2).sum()) * 8.0
+    return total
 
 
 def pixel_pupil_timing(plan, images, w, chunk=512):
@@ -219,28 +282,87 @@ def train_slide_surrogate(dev, n_train=512, seed=41):
     return fit_surrogate(x, z[:, 3:15].contiguous(), seed)
 
 
-def train_grid_surrogate(plan, images, w, dev, seed=43, trust_quantile=0.4):
-    """Surrogate for the grid workload, trained on the GPU on the workload's
-    own closed-form pupil estimates, at the tiles' field positions, of the
-    tiles whose solve is best supported (weight sum above the given quantile).
-    Returns (surrogate, positions (T, 2) on the device, summary)."""
+def grid_training_workload(w, n_train=4096, seed=43):
+    """Training tiles for the grid workload's surrogate, disjoint from the
+    timed ones: the same geometry without darkfield images (the surrogate's
+    inputs and the closed-form labels come from the NA-matched images only),
+    objects drawn with their own seed, positions uniform over the field, true
+    pupils from the same field model (its quadratic coefficients fitted on the
+    workload's 32 x 32 grid)."""
     import numpy as np
+    import apic_synth as S
+    g = np.arange(1024)
+    _, a = S.field_model_quadratic((g % 32 - 15.5) / 15.5, (g // 32 - 15.5) / 15.5)
+    uv = np.random.default_rng([seed, 2, 0]).uniform(-1.0, 1.0, (n_train, 2))
+    u, v = uv[:, 0], uv[:, 1]
+    c = np.zeros((n_train, 15))
+    c[:, 3:] = np.stack([np.ones_like(u), u, v, u * u, u * v, v * v], axis=1) @ a.T
+    return S.Workload("grid256-train", w.n, w.k_bf, [], upsample=w.upsample, n_tiles=n_train,
+                      photons=w.photons, seed_id=seed, coeffs=c, positions=uv)
+
+
+def train_grid_surrogate(w, dev, seed=43, trust_quantile=0.4):
+    """Surrogate for the grid workload, trained on the GPU on the closed-form
+    pupil estimates (coarse-to-fine continuation) of 4096 training tiles
+    disjoint from the timed ones, at their field positions, keeping the tiles
+    whose solve is best supported (weight sum above the given quantile).  It
+    seeds the re-wrapped pupil solve of the timed step.  Returns (surrogate,
+    summary)."""
     import torch
+    from apic_synth.batch import synth_batch
     from paper_2407_20469_amd import apic
-    stack = images[:w.n_tiles * w.n_img * w.n * w.n].view(w.n_tiles, w.n_img, w.n, w.n)
-    z, diag, feat, st = apic.estimate_pupil(plan, stack)
-    pos = torch.tensor(w.positions, dtype=torch.float32, device=dev)
-    x = torch.cat([pos, feat], dim=1)
+    wt = grid_training_workload(w, seed=seed)
+    imgs = synth_batch(wt, dev)
+    plan = apic.Plan(wt.geometry_kwargs())
+    z, diag, feat, st = apic.estimate_pupil(plan, imgs)
+    del imgs
+    x = torch.cat([torch.tensor(wt.positions, dtype=torch.float32, device=dev), feat], dim=1)
     sw = diag[:, 2]
     keep = sw >= torch.quantile(sw, trust_quantile)
-    sur, l0, l1 = fit_surrogate(x[keep].contiguous(), z[keep, 3:15].contiguous(), seed)
-    note = {"trained_on": f"closed-form estimates of the workload's {int(keep.sum())} "
-                          f"best-supported tiles", "loss_first": l0, "loss_last": l1}
-    return sur, pos, note
+    sur, l0, l1 = fit_surrogate(x[keep].contiguous(), z[keep, 3:15].contiguous(), seed,
+                                epochs=100)
+    sur.seeds_solve = True
+    import numpy as np
+    err = z.cpu().numpy()[:, 3:] - wt.coeffs[:, 3:]
+    note = {"trained_on": f"closed-form estimates of {int(keep.sum())} best-supported of "
+                          f"{wt.n_tiles} training tiles disjoint from the timed ones "
+                          f"(own objects and noise, uniform random field positions)",
+            "label_rmse_vs_truth": float(np.sqrt(np.mean(np.sum(err * err, axis=1)))),
+            "loss_first": l0, "loss_last": l1, "seeds_solve": True}
+    plan.close()
+    return sur, note
 
 
-def run_slide_stream(args, dev):
-    """Slide stream (see the module docstring)."""
+def pupil_accuracy(plan_geom, images, w, z_chosen, sur, pos, dev):
+    """Pupil RMSE against the truth (sqrt of the mean over tiles of
+    sum_j (c_j - c_true_j)^2, Noll 4..15) on the timed tiles: the step's chosen
+    coefficients, the closed form (continuation), the single pass of Eq. 10,
+    the surrogate alone and the closed form seeded by the surrogate."""
+    import numpy as np
+    from paper_2407_20469_amd import apic
+    stack = images[:w.n_tiles * w.n_img * w.n * w.n].view(w.n_tiles, w.n_img, w.n, w.n)
+    truth = w.coeffs[:, 3:]
+
+    def rmse(z):
+        d = z.cpu().numpy()[:, 3:15] - truth
+        return float(np.sqrt(np.mean(np.sum(d * d, axis=1))))
+
+    out = {"chosen_in_timed_step": rmse(z_chosen)}
+    cf, _, _, _ = apic.estimate_pupil(apic.Plan(plan_geom), stack)
+    out["closed_form_continuation"] = rmse(cf)
+    one, _, _, _ = apic.estimate_pupil(apic.Plan({**plan_geom, "pupil_bands": 0}), stack)
+    out["closed_form_single_pass"] = rmse(one)
+    if sur is not None:
+        _, zcf, zs, _, _ = apic.estimate_pupil_sur(apic.Plan(plan_geom), stack, pos, sur)
+        out["surrogate_alone"] = rmse(zs)
+        out["closed_form_seeded_by_surrogate"] = rmse(zcf)
+    out["unit"] = "rad"
+    return out
+
+
+def slide_stream(args, dev, tiles, steps, warmup):
+    """Slide stream (see the module docstring) over the first ``tiles``
+    scanned tiles; returns the record."""
     import numpy as np
     import torch
     from apic_synth import slide
@@ -250,7 +372,7 @@ def run_slide_stream(args, dev):
     p_tissue, p_glass = 16, 4
     w = slide.pool_workload(p_tissue, p_glass)
     mask = slide.slide_mask()
-    idx, src = slide.scan_order(mask, args.tiles, p_tissue, p_glass)
+    idx, src = slide.scan_order(mask, tiles, p_tissue, p_glass)
     T = len(idx)
     log(f"slide {mask.shape[0]} x {mask.shape[1]} tiles, {mask.mean():.2f} tissue; "
         f"streaming the first {T} scanned tiles from a pool of {w.n_tiles}")
@@ -284,16 +406,16 @@ def run_slide_stream(args, dev):
         return st.run(host_imgs[:n], host_flds[:n], positions=pos[:n], sur=sur,
                       bg_threshold=args.bg_threshold)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         run(min(T, 2 * args.chunk))
-        log(f"warmup {i + 1}/{args.warmup} done")
+        log(f"warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     times = []
-    for i in range(args.steps):
+    for i in range(steps):
         t0 = time.perf_counter()
         z, status, stat = run(T)
         times.append(time.perf_counter() - t0)
-        log(f"stream pass {i + 1}/{args.steps}: {times[-1]:.2f} s")
+        log(f"stream pass {i + 1}/{steps}: {times[-1]:.2f} s")
     wall = float(np.median(times))
     skipped = (status & apic.TILE_BACKGROUND) != 0
     rec = int((~skipped).sum())
@@ -320,7 +442,7 @@ def run_slide_stream(args, dev):
 
     out = {
         "metric": METRIC, "value": mpx / wall, "unit": "Mpx/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"slide stream: first {T} scanned 512x512 tiles (16 NA-matched + "
@@ -342,10 +464,107 @@ def run_slide_stream(args, dev):
         "env": run_env(),
     }
     st.close()
-    print(json.dumps(out), flush=True)
+    plan.close()
+    return out
+
+
+def run_slide_stream(args, dev):
+    print(json.dumps(slide_stream(args, dev, args.tiles, args.steps, args.warmup)), flush=True)
+
+
+def synth_into(ws_list, order, plan, dev):
+    """Synthesise every class of a batch into one flat image buffer laid out by
+    the plan's mixed descriptors.  Returns (descs, images, field elements)."""
+    import numpy as np
+    import torch
+    from apic_synth.batch import synth_batch
+    from paper_2407_20469_amd import apic
+    n_total = sum(w.n_tiles for w in ws_list)
+    cls_of = np.zeros(n_total, np.int64)
+    for ci, idx in enumerate(order):
+        cls_of[idx] = ci
+    descs, n_img_el, n_fld_el = apic.mixed_descs(plan, cls_of)
+    images = torch.empty(n_img_el, dtype=torch.float32, device=dev)
+    for ci, w in enumerate(ws_list):
+        log(f"synthesising class {ci}: {w.n_tiles} tiles of {w.n}^2 x {w.n_img} images")
+        imgs = synth_batch(w, dev, log=log)
+        per = w.n_img * w.n * w.n
+        for p_, b in enumerate(order[ci]):
+            o = descs[int(b)].image_offset
+            images[o:o + per] = imgs[p_].reshape(-1)
+        del imgs
+    torch.cuda.synchronize()
+    return descs, images, n_fld_el
+
+
+def timed_steps(fn, steps, stream):
+    """HIP events on ``stream`` around ``steps`` calls of fn; ms per call."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def uneven_block(dev, ws_gb, warmup=1, steps=1):
+    """The uneven batch (4096 tiles, nine geometry classes, closed form) with
+    its own warmup and timed passes; chunks fitted to a workspace budget
+    without the autotuner's timing runs."""
+    import numpy as np
+    import torch
+    import apic_synth as S
+    from paper_2407_20469_amd import apic
+    t_start = time.time()
+    ws_list = S.uneven_batch(n_tiles=4096)
+    order = [w.extra["tiles"] for w in ws_list]
+    plan = apic.Plan([w.geometry_kwargs() for w in ws_list])
+    plan.upload()
+    descs, images, n_fld = synth_into(ws_list, order, plan, dev)
+    n_total = sum(w.n_tiles for w in ws_list)
+    mpx = sum(w.n_tiles * (w.n * w.upsample) ** 2 for w in ws_list) / 1e6
+    field = torch.empty(n_fld, dtype=torch.complex64, device=dev)
+    zern = torch.empty((n_total, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((n_total,), dtype=torch.int32, device=dev)
+    batch = apic.Batch(plan, descs)
+    batch.fit(int(ws_gb * 2 ** 30))
+    ws = apic.Workspace()
+    log(f"uneven: {len(ws_list)} classes, workspace {batch.workspace_bytes / 2 ** 30:.1f} GiB, "
+        f"synth + setup {time.time() - t_start:.1f} s")
+    for i in range(warmup):
+        batch.reconstruct(images, field, zern, status, ws)
+        torch.cuda.synchronize()
+        log(f"uneven warmup {i + 1}/{warmup} done")
+    ms = timed_steps(lambda: batch.reconstruct(images, field, zern, status, ws), steps,
+                     torch.cuda.current_stream())
+    st = status.cpu().numpy()
+    rec = {"value": mpx / (ms * 1e-3), "unit": "Mpx/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": ms,
+           "workload": f"uneven batch of {n_total} tiles: 128/256/512 px (4:3:1), 8/12/16 "
+                       f"NA-matched + 2x darkfield, 40% background, Poisson 1e4, 2x complex64 "
+                       f"output",
+           "mode": "prepared batch, nine classes on concurrent streams, closed form, chunks "
+                   "fitted to the workspace budget",
+           "classes": [[w.n, w.n_bf, w.n_df, w.n_tiles, c["chunk"], c["lanes"]]
+                       for w, c in zip(ws_list, batch.classes())],
+           "workspace_gib": batch.workspace_bytes / 2 ** 30,
+           "nonfinite_tiles": int(((st & (apic.TILE_NONFINITE_INPUT
+                                         | apic.TILE_NONFINITE_OUT)) != 0).sum()),
+           "block_wall_s": None}
+    batch.close()
+    del images, field, ws
+    torch.cuda.empty_cache()
+    rec["block_wall_s"] = time.time() - t_start
+    log(f"uneven: {ms / 1e3:.1f} s per pass, {rec['value']:.1f} Mpx/s")
+    return rec
 
 
 def main():
+    t_start = time.time()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -358,6 +577,10 @@ def main():
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--plain-tiles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="grid: skip the uneven-batch and slide-stream blocks")
+    ap.add_argument("--side-steps", type=int, default=5,
+                    help="grid: timed steps of the side measurements (closed form, graph)")
     ap.add_argument("--chunk", type=int, default=64, help="slide: tiles per staged chunk")
     ap.add_argument("--buffers", type=int, default=3, help="slide: staging buffers / streams")
     ap.add_argument("--bg-threshold", type=float, default=3e-3,
@@ -373,9 +596,17 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import apic_synth as S
-    from apic_synth.batch import synth_batch
+
+    # the oracle's pool runs first, in spawned processes, before anything
+    # touches the GPU
+    cpu_base = None
+    if args.workload == "grid" and not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle over a tile subset, one process per core")
+        cpu_base = cpu_baseline_pool(S.grid_batch(n_tiles=args.tiles))
+        log(f"cpu baseline: {cpu_base['sample']}")
+
+    import torch
     from paper_2407_20469_amd import apic
 
     dev = torch.device("cuda:0")
@@ -392,26 +623,10 @@ def main():
         ws_list = S.uneven_batch(n_tiles=args.tiles or 4096)
         order = [w.extra["tiles"] for w in ws_list]
     n_total = sum(w.n_tiles for w in ws_list)
-    # batch order: tile b of the batch is tile `pos` of class `cls`
-    cls_of = np.zeros(n_total, np.int64)
-    pos_of = np.zeros(n_total, np.int64)
-    for ci, idx in enumerate(order):
-        cls_of[idx] = ci
-        pos_of[idx] = np.arange(len(idx))
     plan = apic.Plan([w.geometry_kwargs() for w in ws_list])
     plan.upload()
-    descs, n_img_el, n_fld_el = apic.mixed_descs(plan, cls_of)
-    images = torch.empty(n_img_el, dtype=torch.float32, device=dev)
     t0 = time.time()
-    for ci, w in enumerate(ws_list):
-        log(f"synthesising class {ci}: {w.n_tiles} tiles of {w.n}^2 x {w.n_img} images")
-        imgs = synth_batch(w, dev, log=log)
-        per = w.n_img * w.n * w.n
-        for p_, b in enumerate(order[ci]):
-            o = descs[int(b)].image_offset
-            images[o:o + per] = imgs[p_].reshape(-1)
-        del imgs
-    torch.cuda.synchronize()
+    descs, images, n_fld_el = synth_into(ws_list, order, plan, dev)
     log(f"synth done in {time.time() - t0:.1f} s")
     mpx_step = sum(w.n_tiles * (w.n * w.upsample) ** 2 for w in ws_list) / 1e6
 
@@ -419,14 +634,16 @@ def main():
     zern = torch.empty((n_total, 15), dtype=torch.float32, device=dev)
     status = torch.empty((n_total,), dtype=torch.int32, device=dev)
     batch = apic.Batch(plan, descs)
-    sur_note = None
+    sur = sur_note = sur_pos = None
     if args.workload == "grid" and not args.no_surrogate:
         t0 = time.time()
-        sur, sur_pos, sur_note = train_grid_surrogate(plan, images, ws_list[0], dev)
+        sur, sur_note = train_grid_surrogate(ws_list[0], dev)
+        sur_pos = torch.tensor(ws_list[0].positions, dtype=torch.float32, device=dev)
         batch.set_surrogate(sur, sur_pos)
         torch.cuda.synchronize()
         log(f"surrogate trained in {time.time() - t0:.1f} s (loss {sur_note['loss_first']:.4f} "
-            f"-> {sur_note['loss_last']:.5f})")
+            f"-> {sur_note['loss_last']:.5f}; label RMSE vs truth "
+            f"{sur_note['label_rmse_vs_truth']:.4f} rad)")
     budget = int(args.ws_gb * 2 ** 30)
     tune = None
     if not args.no_autotune:
@@ -443,8 +660,7 @@ def main():
         log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk, lanes) "
             f"{[(c['geom'], c['tiles'], c['chunk'], c['lanes']) for c in tune]}")
     elif batch.workspace_bytes > budget:
-        for i, c in enumerate(batch.classes()):
-            batch.set_chunk(i, max(1, budget // (len(ws_list) * c["tile_bytes"])))
+        batch.fit(budget)
     ws = apic.Workspace()
     log(f"workspace {batch.workspace_bytes / 2 ** 30:.1f} GiB")
 
@@ -454,15 +670,8 @@ def main():
         log(f"warmup {i + 1}/{args.warmup} done")
     stream = torch.cuda.current_stream()
     apic.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for i in range(args.steps):
-        batch.reconstruct(images, field, zern, status, ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = timed_steps(lambda: batch.reconstruct(images, field, zern, status, ws), args.steps,
+                     stream)
     prof = apic.profile_read()
     apic.profile(False)
     log(f"timed {args.steps} steps: {ms:.1f} ms/step")
@@ -473,29 +682,27 @@ def main():
         sur_note["closed_form_kept"] = int(((st & apic.TILE_FALLBACK_USED) != 0).sum())
         log(f"surrogate kept on {sur_note['surrogate_kept']} tiles, closed form on "
             f"{sur_note['closed_form_kept']}")
+    accuracy = None
+    if args.workload == "grid":
+        accuracy = pupil_accuracy(ws_list[0].geometry_kwargs(), images, ws_list[0], zern, sur,
+                                  sur_pos, dev)
+        log(f"pupil RMSE vs truth: {accuracy}")
 
     # the closed-form batch (surrogate off) on the same tiles, timed the same
     # way after the surrogate step: the plain batched method beside it
     closed_form = None
+    side = max(1, min(args.side_steps, args.steps))
     if sur_note is not None:
         batch.set_surrogate(None, None)
         batch.reconstruct(images, field, zern, status, ws)
-        torch.cuda.synchronize()
-        c0 = torch.cuda.Event(enable_timing=True)
-        c1 = torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
-        for i in range(args.steps):
-            batch.reconstruct(images, field, zern, status, ws)
-        c1.record(stream)
-        torch.cuda.synchronize()
-        cf_ms = c0.elapsed_time(c1) / args.steps
-        closed_form = {"value": mpx_step / (cf_ms * 1e-3), "unit": "Mpx/s", "ms_per_step": cf_ms}
+        cf_ms = timed_steps(lambda: batch.reconstruct(images, field, zern, status, ws), side,
+                            stream)
+        closed_form = {"value": mpx_step / (cf_ms * 1e-3), "unit": "Mpx/s", "ms_per_step": cf_ms,
+                       "steps": side}
         log(f"closed-form batch (surrogate off): {cf_ms:.1f} ms/step")
 
     # a step captured into a graph and replayed: the closed-form batch, since
-    # graphs are offered for one-lane batches without the surrogate (the
-    # uneven batch's chunked 512 px classes enqueue ~10^5 launches: no graph
-    # there by default)
+    # graphs are offered for one-lane batches without the surrogate
     graph_ms = None
     want_graph = args.graph if args.graph is not None else args.workload == "grid"
     if want_graph and any(c["lanes"] != 1 for c in batch.classes()):
@@ -507,14 +714,7 @@ def main():
         batch.capture(images, field, zern, status, ws, gstream)
         with torch.cuda.stream(gstream):
             batch.launch(gstream)
-            g0 = torch.cuda.Event(enable_timing=True)
-            g1 = torch.cuda.Event(enable_timing=True)
-            g0.record(gstream)
-            for i in range(args.steps):
-                batch.launch(gstream)
-            g1.record(gstream)
-        gstream.synchronize()
-        graph_ms = g0.elapsed_time(g1) / args.steps
+            graph_ms = timed_steps(lambda: batch.launch(gstream), side, gstream)
         log(f"graph replay: {graph_ms:.1f} ms/step")
 
     # plain path: the same kernels, one tile per call, first class
@@ -535,6 +735,7 @@ def main():
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / P
     log(f"plain: {plain_s * 1e3:.1f} ms/tile")
+    del ws1
 
     pixel = assembly = None
     if args.workload == "grid":
@@ -546,26 +747,36 @@ def main():
             f"(mean {pixel['mean_iterations']:.0f} iterations); Zernike basis "
             f"{pixel['ms_zernike_basis']:.1f} ms")
 
-    # executed gram work: live (block pair, E chunk) triples x chunk x block^2 complex MACs
-    gram_exec = 0.0
+    # gram work per step: nonzero products of the E-sum (the algorithmic
+    # count), the dense E-sum, and the products the kernels issue (live
+    # (block pair, E chunk) triples x chunk x block^2 complex MACs)
+    gram_exec = gram_dense = gram_nz = 0.0
     for ci, w in enumerate(ws_list):
         steps_tab = plan.query(6, ci).reshape(-1, 5).astype(np.float64)
         sz = plan.sizes(ci)
         gram_exec += (w.n_tiles * steps_tab[:, 3].sum() * sz["gram_chunk"] * sz["gram_block"] ** 2
                       * 8.0)
+        gram_nz += w.n_tiles * gram_nonzero_flops(plan, ci)
     groups = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
                   "work_per_step": v[2] / args.steps} for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
     tot_ms, launches, work = prof[dom]
     if dom in FLOP_GROUPS:
+        if dom == "gram":
+            gram_dense = work / args.steps
+            work = gram_nz * args.steps
         achieved = work / (tot_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
         if dom == "gram":
-            # achieved counts the dense E-sum of the T-E gram; the kernels skip the
-            # chunks whose products are exactly zero, so they issue fewer flops
-            roof["executed_tflops"] = gram_exec / (tot_ms / args.steps * 1e-3) / 1e12
+            per_step_s = tot_ms / args.steps * 1e-3
+            roof["work"] = ("nonzero products of the E-sum (both u + k and u' + k in P), "
+                            "8 flops per complex MAC of the Hermitian lower triangle")
+            roof["flops_per_step"] = gram_nz
+            roof["dense_tflops"] = gram_dense / per_step_s / 1e12
+            roof["executed_tflops"] = gram_exec / per_step_s / 1e12
             roof["executed_frac"] = roof["executed_tflops"] / FP64_PEAK_TFLOPS
+            roof["executed_over_nonzero"] = gram_exec / gram_nz
             if args.workload == "grid" and n_total == 1024:
                 roof["traffic"] = measured_traffic()
     else:
@@ -607,7 +818,8 @@ def main():
     elif args.workload == "grid":
         w = ws_list[0]
         config = {"workload": f"{w.n_tiles} tiles {w.n}x{w.n}, 16 NA-matched + 32 darkfield "
-                              f"(NA 0.25 / 0.30 / 0.38), Poisson 1e4, 2x complex64 output",
+                              f"(NA 0.25 / 0.30 / 0.38), quadratic field aberrations up to "
+                              f"1.5 rad, Poisson 1e4, 2x complex64 output",
                   "tiles": w.n_tiles, "n": w.n, "n_bf": w.n_bf, "n_df": w.n_df,
                   "upsample": w.upsample}
     else:
@@ -618,16 +830,17 @@ def main():
     config["mode"] = "prepared batch, classes on concurrent streams, autotuned chunks" \
         if tune else "prepared batch, classes on concurrent streams"
     if sur_note is not None:
-        config["mode"] += ", surrogate pupil with closed-form fallback"
+        config["mode"] += ", surrogate seeds the pupil solve, closed form judges it (fallback)"
         config["surrogate"] = sur_note
     out = {
         "metric": METRIC, "value": mpx_step / (ms * 1e-3), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": config,
+        "pupil_rmse_vs_truth": accuracy,
         "closed_form_batch": closed_form,
         "graph": None if graph_ms is None else {"value": mpx_step / (graph_ms * 1e-3),
-                                                "ms_per_step": graph_ms,
+                                                "ms_per_step": graph_ms, "steps": side,
                                                 "of": "closed-form batch"},
         "plain": {"value": (nf0 * nf0 / 1e6) / plain_s, "unit": "Mpx/s", "tiles_timed": P,
                   "ms_per_tile": plain_s * 1e3, "class": 0},
@@ -642,10 +855,35 @@ def main():
         "rgb": rgb,
         "env": run_env(),
     }
-    if not args.no_cpu_baseline:
-        b0 = int(order[0][0])
-        log(f"cpu baseline: oracle on tile {b0}")
-        out["cpu_baseline"] = cpu_baseline(one[0][0].cpu().numpy(), w0)
+    if cpu_base is not None:
+        out["cpu_baseline"] = cpu_base
+
+    # the largest configurations beside the headline: the uneven batch (one
+    # full pass after one warmup pass) and a subset of the slide stream, each
+    # run only while the whole bench stays within its time budget
+    if args.workload == "grid" and not args.no_extra:
+        batch.close()
+        del images, field, ws
+        torch.cuda.empty_cache()
+        left = 560.0 - (time.time() - t_start)
+        out["uneven_batch"] = uneven_block(dev, args.ws_gb) if left > 200 else \
+            {"skipped": f"time budget ({left:.0f} s left)"}
+        left = 560.0 - (time.time() - t_start)
+        if left > 90:
+            args.chunk, args.buffers = 64, 3
+            rec = slide_stream(args, dev, tiles=128, steps=1, warmup=1)
+            out["slide_stream"] = {k: rec[k] for k in ("value", "unit", "steps", "warmup",
+                                                       "ms_per_step", "config", "timing",
+                                                       "tiles_per_s", "pcie",
+                                                       "resident_ms_per_tile",
+                                                       "stream_ms_per_reconstructed_tile",
+                                                       "surrogate_used_frac",
+                                                       "slide_extrapolation")}
+            out["slide_stream"]["subset"] = ("the first 128 scanned tiles of the raster order; "
+                                             "host wall-clock with the copies (PCIe-inclusive)")
+        else:
+            out["slide_stream"] = {"skipped": f"time budget ({left:.0f} s left)"}
+    out["bench_wall_s"] = time.time() - t_start
     print(json.dumps(out), flush=True)
 
 

@@ -387,6 +387,13 @@ class Batch:
         self._bound = None
         return ms[:len(classes)]
 
+    def fit(self, workspace_bytes):
+        """Halve the largest classes' chunks until the classes' workspace blocks
+        together fit ``workspace_bytes`` (apic_batch_fit), without timing runs."""
+        _check("apic_batch_fit", self.lib.apic_batch_fit(self.handle, int(workspace_bytes)))
+        self._refresh()
+        self._bound = None
+
     def close(self):
         if self.handle:
             self.lib.apic_batch_destroy(self.handle)
