@@ -2,7 +2,7 @@
 // upsampled output.  For darkfield image j (known set P, unknown set U, linear
 // region Q, excluded set E = (P - U) - Q, all plan tables):
 //
-//   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P              (k_df_phat)
+//   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P, 0 elsewhere  (k_df_phat)
 //   fpp      = fft2(|ifft2 P_hat|^2)        FP64 passes          (OpP*)
 //   fimg     = fft2(I_j)                    FP64 passes          (OpImg*)
 //   b(k)     = conj(fimg(k) - fpp(k)),  k in Q                   (OpR1)
@@ -150,13 +150,10 @@ __global__ __launch_bounds__(256) void k_df_rhs_gather(ClassArgs a, StepArgs s) 
   a.at<c64>(t, a.lay.gram)[(int64_t)s.nu * a.nu_pad + u] = make_double2(c.x * inv2, -c.y * inv2);
 }
 
-// P_hat(u + k) for u in U, k in E: read with periodic indexing.  u + k lies
-// within 3r of the darkfield support's centre and P within r of it, so a
-// wrapped position (off by a multiple of N > 4r) never falls in P, where
-// P_hat is nonzero: the periodic read equals the bounded one.
-__device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
-  return phat[fft_pos(ky, n) * n + fft_pos(kx, n)];
-}
+// The gram reads P_hat(u + k) for u in U, k in E with periodic indexing.
+// u + k lies within 3r of the darkfield support's centre and P within r of
+// it, so a wrapped position (off by a multiple of N > 4r) never falls in P,
+// where P_hat is nonzero: the periodic read equals the bounded one.
 
 // Gram of the darkfield system in 32 x 32 blocks (I >= J) of the N_u x N_u
 // Hermitian matrix, one wavefront per block: lane (ty, tx) = (lane / 8,
@@ -164,14 +161,21 @@ __device__ __forceinline__ c64 phat_at(const c64 *phat, int n, int ky, int kx) {
 // LDS row read consecutive elements (no bank conflicts).
 //
 // A product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only when both u + k
-// and u' + k fall in P, so the E-sum is sparse.  Small blocks and chunks of
-// kEChunk (2) excluded k follow that sparsity: only the chunks whose products
-// can be nonzero for both blocks (plan masks) are visited, in ascending order,
-// walking the mask words with wave-uniform state.  The operands of the next
-// chunk are gathered into registers while the current chunk is multiplied
-// from LDS.  A diagonal block has one operand and is formed whole (its upper
-// half is not read by the Cholesky).
-constexpr int kGramKC = kEChunk;
+// and u' + k fall in P, so the E-sum is sparse.  A plan mask per block of
+// unknowns marks the excluded k for which some unknown of the block lands in
+// P; a block pair visits the k marked for both blocks, in ascending order,
+// walking the mask words with wave-uniform state, two k per iteration.  Each
+// lane gathers one operand element per iteration (its unknown u of each
+// block, its k of the two); a lane without an element reads a grid position
+// that is never in P (the point opposite the support's centre), where P_hat
+// is zero, so every lane loads unconditionally.  Software pipeline: while the
+// current two k are multiplied from LDS, the operands of the next two are in
+// flight and the two after those are being looked up in E.  A diagonal block
+// has one operand and is formed whole (its upper half is not read by the
+// Cholesky).
+constexpr int kGramRows = 2;  // excluded k per iteration
+static_assert(kGramRows * kGramUB == 64, "one gathered element per lane and iteration");
+constexpr uint32_t kNoK = 0x7fff7fffu;  // padding: outside every support
 __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramUB - 1) / kGramUB;
   const int ntri = nb * (nb + 1) / 2;
@@ -185,21 +189,28 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   const int J = rem;
   const bool diag = I == J;
   const c64 *phat = a.at<c64>(t, a.lay.phat);
-  __shared__ c64 sA[kGramKC][kGramUB];
-  __shared__ c64 sB[kGramKC][kGramUB];
+  // a grid position outside the darkfield support (centre -k_j, radius
+  // r < N / 4): the centre shifted by (N/2, N/2), at distance N / sqrt 2
+  const int zpos = fft_pos(-s.ky + a.n / 2, a.n) * a.n + fft_pos(-s.kx + a.n / 2, a.n);
+  __shared__ c64 sA[kGramRows][kGramUB];
+  __shared__ c64 sB[kGramRows][kGramUB];
   __shared__ uint32_t su[2][kGramUB];
   const int lane = threadIdx.x;
   const int ty = lane >> 3, tx = lane & 7;
+  const int uu = lane & (kGramUB - 1), kk = lane / kGramUB;  // this lane's gather slot
+  const int ui = I * kGramUB + uu, uj = J * kGramUB + uu;
+  const uint32_t wa = ui < s.nu ? s.u[ui] : kNoK;
+  const uint32_t wb = uj < s.nu ? s.u[uj] : kNoK;
   if (lane < kGramUB) {
-    const int ui = I * kGramUB + lane, uj = J * kGramUB + lane;
-    su[0][lane] = ui < s.nu ? s.u[ui] : 0x7fff7fffu;  // padding: outside every support
-    su[1][lane] = uj < s.nu ? s.u[uj] : 0x7fff7fffu;
+    su[0][lane] = wa;
+    su[1][lane] = wb;
   }
-  // live chunks in ascending order, walked with wave-uniform state
+  const int ay = kunpack_y(wa), ax = kunpack_x(wa), by = kunpack_y(wb), bx = kunpack_x(wb);
+  // marked k in ascending order, walked with wave-uniform state
   const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
   int mw = 0;
   uint64_t bits = s.nwe > 0 ? (mi[0] & mj[0]) : 0;
-  auto next_chunk = [&]() -> int {
+  auto next_k = [&]() -> int {
     while (bits == 0) {
       if (++mw >= s.nwe) return -1;
       bits = mi[mw] & mj[mw];
@@ -208,55 +219,51 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     bits &= bits - 1;
     return c;
   };
+  // this lane's excluded k of a pair of E rows (kNoK for a missing row)
+  auto k_of = [&](int r0, int r1) -> uint32_t {
+    const int r = kk ? r1 : r0;
+    return r >= 0 ? s.e[r] : kNoK;
+  };
+  auto gather = [&](uint32_t kw, c64 &pa, c64 &pb) {
+    const bool kv = kw != kNoK;
+    const int ky = kunpack_y(kw), kx = kunpack_x(kw);
+    const int ia = (kv && wa != kNoK) ? fft_pos(ay + ky, a.n) * a.n + fft_pos(ax + kx, a.n) : zpos;
+    pa = phat[ia];
+    if (!diag) {
+      const int ib =
+          (kv && wb != kNoK) ? fft_pos(by + ky, a.n) * a.n + fft_pos(bx + kx, a.n) : zpos;
+      pb = phat[ib];
+    }
+  };
   c64 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
   __syncthreads();
-  constexpr int NEL = kGramKC * kGramUB, PER = (NEL + 63) / 64;
-  c64 pa[PER], pb[PER];
-  auto gather = [&](int chunk) {
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = lane + m * 64;
-      const int kk = e / kGramUB, uu = e % kGramUB;
-      const int k = chunk * kGramKC + kk;
-      pa[m] = make_double2(0.0, 0.0);
-      pb[m] = make_double2(0.0, 0.0);
-      if ((NEL % 64 == 0 || e < NEL) && k < s.ne) {
-        const uint32_t kw = s.e[k];
-        const int ky = kunpack_y(kw), kx = kunpack_x(kw);
-        const uint32_t wa = su[0][uu], wb = su[1][uu];
-        if (wa != 0x7fff7fffu) pa[m] = phat_at(phat, a.n, kunpack_y(wa) + ky, kunpack_x(wa) + kx);
-        if (diag)
-          pb[m] = pa[m];
-        else if (wb != 0x7fff7fffu)
-          pb[m] = phat_at(phat, a.n, kunpack_y(wb) + ky, kunpack_x(wb) + kx);
-      }
-    }
-  };
-  int cur = next_chunk();
-  if (cur >= 0) gather(cur);
-  while (cur >= 0) {
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = lane + m * 64;
-      if (NEL % 64 == 0 || e < NEL) {
-        sA[e / kGramUB][e % kGramUB] = pa[m];
-        sB[e / kGramUB][e % kGramUB] = pb[m];
-      }
-    }
+  int cur0 = next_k();
+  int cur1 = cur0 >= 0 ? next_k() : -1;
+  int nxt0 = cur1 >= 0 ? next_k() : -1;
+  int nxt1 = nxt0 >= 0 ? next_k() : -1;
+  c64 pa, pb = make_double2(0.0, 0.0);
+  gather(k_of(cur0, cur1), pa, pb);
+  uint32_t kw_nxt = k_of(nxt0, nxt1);
+  const c64(*sBd)[kGramUB] = diag ? sA : sB;  // the column operand
+  while (cur0 >= 0) {
+    sA[kk][uu] = pa;
+    if (!diag) sB[kk][uu] = pb;
     __syncthreads();
-    const int nxt = next_chunk();
-    if (nxt >= 0) gather(nxt);
-#pragma unroll 4
-    for (int kk = 0; kk < kGramKC; ++kk) {
+    const int nn0 = nxt1 >= 0 ? next_k() : -1;
+    const int nn1 = nn0 >= 0 ? next_k() : -1;
+    const uint32_t kw_nn = k_of(nn0, nn1);
+    gather(kw_nxt, pa, pb);
+    const int rows = cur1 >= 0 ? 2 : 1;
+    for (int r = 0; r < rows; ++r) {
       c64 av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty + 8 * i];
+      for (int i = 0; i < 4; ++i) av[i] = sA[r][ty + 8 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx + 8 * j];
+      for (int j = 0; j < 4; ++j) bv[j] = sBd[r][tx + 8 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -266,28 +273,37 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
         }
     }
     __syncthreads();
-    cur = nxt;
+    cur0 = nxt0;
+    cur1 = nxt1;
+    nxt0 = nn0;
+    nxt1 = nn1;
+    kw_nxt = kw_nn;
   }
-  // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4
+  // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4; per row the four
+  // Toeplitz values are read first (padding entries read a harmless value),
+  // then the valid entries stored, so those loads are in flight together
   const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
   const c64 *fpp = a.at<c64>(t, a.lay.fpp);
   c64 *G = a.at<c64>(t, a.lay.gram);
   const int ld = a.nu_pad;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = I * kGramUB + ty + 8 * i;
-    if (r >= s.nu) continue;
     const uint32_t wr = su[0][ty + 8 * i];
     const int ry = kunpack_y(wr), rx = kunpack_x(wr);
+    const int r = I * kGramUB + ty + 8 * i;
+    c64 tv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t wc = su[1][tx + 8 * j];
+      const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
+      tv[j] = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = J * kGramUB + tx + 8 * j;
-      if (c >= s.nu) continue;
-      const uint32_t wc = su[1][tx + 8 * j];
-      const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
-      const c64 tv = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
-      G[(int64_t)r * ld + c] = make_double2(tv.x * inv2 - acc[i][j].x * inv4,
-                                            tv.y * inv2 - acc[i][j].y * inv4);
+      if (r < s.nu && c < s.nu)
+        G[(int64_t)r * ld + c] = make_double2(tv[j].x * inv2 - acc[i][j].x * inv4,
+                                              tv[j].y * inv2 - acc[i][j].y * inv4);
     }
   }
 }

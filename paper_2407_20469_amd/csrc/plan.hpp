@@ -20,7 +20,7 @@ constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cell
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
 constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
-constexpr int kEChunk = 2;          // E rows per gram k-chunk
+constexpr int kEChunk = 1;          // E rows per bit of the gram's block masks
 constexpr int kPixMax = 7936;       // pupil pixels of the pixel-domain solve (LDS bound)
 // Coarse-to-fine continuation of the pupil solve: bands |K| <= f r for these
 // f, each band used when it holds at least kMinBandRows rows.
