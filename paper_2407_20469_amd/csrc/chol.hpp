@@ -57,22 +57,30 @@ __host__ __device__ inline int upd_tiles(const CholArgs &c) {
 // in registers.  Step q publishes column q through LDS (double-buffered, one
 // barrier per step) and every owner of a trailing element applies the
 // unscaled update D[r][c] -= D[r][q] conj(D[c][q]) / D[q][q]; the columns are
-// scaled by 1/sqrt(pivot) at the end.  Inverse M = L^-1: four lanes per
-// column q split the sum of M[i][q] = -(sum_{q<=p<i} L[i][p] M[p][q]) / L[i][i]
-// by p mod 4 and combine it with lane shuffles; lane i mod 4 keeps M[i][q]
-// (in the upper triangle of the LDS block, at D[q][i]) since it is the only
-// lane that reads it later.
+// scaled by 1/sqrt(pivot) at the end, into a packed lower triangle in LDS.
+// Inverse M = L^-1, column by column in parallel: four lanes per column q
+// split the sum M[i][q] = -(sum_{q<=p<i} L[i][p] M[p][q]) / L[i][i] by
+// p mod 4, each lane keeping the entries M[p][q] with p = its s mod 4 in
+// registers (the only terms it needs), and combine it with lane shuffles.
+// LDS holds only the packed factor (33 KB) and registers stay under 128 per
+// lane, so four workgroups share a compute unit: a 1024-tile launch runs in
+// one round.
+constexpr int kTri = kCB * (kCB + 1) / 2;  // packed lower triangle, row i at i (i + 1) / 2
 __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
   const int t = blockIdx.x, tid = threadIdx.x;
   const int n = c.n, kb = c.kb, ld = a.nu_pad;
   const int bs = min(kCB, n - kb);
   c64 *G = a.at<c64>(t, a.lay.gram);
-  __shared__ c64 D[kCB][kCB + 1];
+  __shared__ c64 Lp[kTri];
   __shared__ c64 col[2][kCB];
   __shared__ double piv[kCB], mdiag[kCB], pinv[2];
   __shared__ double red[256];
   __shared__ int fail;
   if (tid == 0) fail = 0;
+  // the column buffers start at zero: the masked update reads entries that
+  // no step has written (they are multiplied by 0, which needs them finite)
+  for (int e = tid; e < 2 * kCB; e += 256) col[e / kCB][e % kCB] = make_double2(0.0, 0.0);
+  __syncthreads();
   if (kb == 0) {
     double tr = 0.0;
     for (int i = tid; i < n; i += 256) tr += G[(int64_t)i * ld + i].x;
@@ -123,20 +131,21 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     __syncthreads();
     const double inv = pinv[q & 1];
     if (r > q && r < bs) {
-      // the column values first (one LDS wait), then branch-free updates; the
+      // v[j] -= m dr conj(col[c]) with m = 1 on the trailing part of the row
+      // (q < c <= r) and 0 elsewhere (an exact no-op there: every operand is
+      // finite), so no select keeps old and new values alive together; the
       // groups of four columns entirely at or left of q are skipped (q is
       // uniform, so the test is a scalar branch)
-      c64 cv[kCB / 4];
-#pragma unroll
-      for (int j = 0; j < kCB / 4; ++j)
-        if (4 * j + 3 > q) cv[j] = cq[s4 + 4 * j];
       const c64 dr = cscale(cq[r], inv);
 #pragma unroll
       for (int j = 0; j < kCB / 4; ++j) {
         if (4 * j + 3 > q) {
           const int cc = s4 + 4 * j;
-          const c64 nv = csub(v[j], cmulc(dr, cv[j]));
-          if (cc > q && cc <= r) v[j] = nv;
+          const double msk = (cc > q && cc <= r) ? 1.0 : 0.0;
+          const c64 cv = cq[cc];
+          const double tx = fma(dr.x, cv.x, dr.y * cv.y), ty = fma(dr.y, cv.x, -dr.x * cv.y);
+          v[j].x = fma(-msk, tx, v[j].x);
+          v[j].y = fma(-msk, ty, v[j].y);
         }
       }
     }
@@ -152,62 +161,71 @@ __global__ __launch_bounds__(256) void k_chol_potrf(ClassArgs a, CholArgs c) {
     mdiag[tid] = 1.0 / piv[tid];
   }
   __syncthreads();
-  // scaled factor to LDS (lower triangle) and back to the gram
+  // scaled factor to the packed triangle in LDS and back to the gram
   if (r < bs) {
 #pragma unroll
     for (int j = 0; j < kCB / 4; ++j) {
       const int cc = s4 + 4 * j;
       if (cc < r) {
         const c64 l = cscale(v[j], mdiag[cc]);
-        D[r][cc] = l;
+        Lp[r * (r + 1) / 2 + cc] = l;
         G[(int64_t)(kb + r) * ld + kb + cc] = l;
       } else if (cc == r) {
-        D[r][r] = make_double2(piv[r], 0.0);
+        Lp[r * (r + 1) / 2 + r] = make_double2(piv[r], 0.0);
         G[(int64_t)(kb + r) * ld + kb + r] = make_double2(piv[r], 0.0);
       }
     }
   }
   __syncthreads();
-  // inverse, column q = tid / 4 split over the four lanes s4 = tid % 4
-  {
-    const int q = r;
-    for (int i = 1; i < bs; ++i) {
-      c64 sum = make_double2(0.0, 0.0);
-      if (q < i) {
-        // terms p = q + ((s4 - q) & 3) + 4 m < i, four at a time: loads first
-        const int p0 = q + ((s4 - q) & 3);
-        for (int pb = p0; pb < i; pb += 16) {
-          c64 lv[4], mv[4];
+  // inverse, column q = tid / 4 split over the four lanes s4 = tid % 4; lane
+  // s4 keeps m[j] = M[4 j + s4][q] (zero above the diagonal, where p < q)
+  const int q = r;
+  c64 m[kCB / 4];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int p = min(pb + 4 * m, kCB - 1);
-            lv[m] = D[i][p];
-            mv[m] = D[q][p];
-          }
+  for (int j = 0; j < kCB / 4; ++j)
+    m[j] = (4 * j + s4 == q && q < bs) ? make_double2(mdiag[q], 0.0) : make_double2(0.0, 0.0);
+  for (int i = 1; i < bs; ++i) {
+    // terms p = 4 j + s4 < i (M[p][q] = 0 for p < q); the row's reads stay
+    // inside the packed triangle (i (i + 1) / 2 + p <= kTri - 1)
+    const c64 *Li = Lp + i * (i + 1) / 2;
+    const int jend = (i + 3) >> 2;  // uniform
+    c64 sum = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int p = pb + 4 * m;
-            const c64 mm = p == q ? make_double2(mdiag[q], 0.0) : mv[m];
-            const c64 tv = cmul(lv[m], mm);
-            if (p < i) sum = cadd(sum, tv);
-          }
-        }
+    for (int j = 0; j < kCB / 4; ++j) {
+      if (j < jend) {
+        const int p = 4 * j + s4;
+        const c64 tv = cmul(Li[p], m[j]);
+        if (p < i) sum = cadd(sum, tv);
       }
-      sum.x += __shfl_xor(sum.x, 1);
-      sum.y += __shfl_xor(sum.y, 1);
-      sum.x += __shfl_xor(sum.x, 2);
-      sum.y += __shfl_xor(sum.y, 2);
-      if (q < i && (i & 3) == s4) D[q][i] = cscale(sum, -mdiag[i]);
+      if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // loads four at a time
+    }
+    sum.x += __shfl_xor(sum.x, 1);
+    sum.y += __shfl_xor(sum.y, 1);
+    sum.x += __shfl_xor(sum.x, 2);
+    sum.y += __shfl_xor(sum.y, 2);
+    if (q < i && (i & 3) == s4) {
+      const c64 mi = cscale(sum, -mdiag[i]);
+      switch (i >> 2) {  // m[i / 4] with a wave-uniform index
+#define APIC_INV_CASE(j) \
+  case j:                \
+    m[j] = mi;           \
+    break;
+        APIC_INV_CASE(0) APIC_INV_CASE(1) APIC_INV_CASE(2) APIC_INV_CASE(3)
+        APIC_INV_CASE(4) APIC_INV_CASE(5) APIC_INV_CASE(6) APIC_INV_CASE(7)
+        APIC_INV_CASE(8) APIC_INV_CASE(9) APIC_INV_CASE(10) APIC_INV_CASE(11)
+        APIC_INV_CASE(12) APIC_INV_CASE(13) APIC_INV_CASE(14)
+        default:
+          m[15] = mi;
+#undef APIC_INV_CASE
+      }
     }
   }
-  __syncthreads();
+  // linv[row][col] = M[row][col] (zero above the diagonal and outside bs)
   c64 *linv = a.at<c64>(t, c.linv_off) + (int64_t)(kb / kCB) * kCB * kCB;
-  for (int e = tid; e < kCB * kCB; e += 256) {
-    const int rr = e / kCB, q = e % kCB;
-    c64 val = make_double2(0.0, 0.0);
-    if (rr < bs && q < rr) val = D[q][rr];
-    else if (rr < bs && q == rr) val = make_double2(mdiag[rr], 0.0);
-    linv[e] = val;
+#pragma unroll
+  for (int j = 0; j < kCB / 4; ++j) {
+    const int p = 4 * j + s4;
+    linv[p * kCB + q] = (p < bs && q < bs) ? m[j] : make_double2(0.0, 0.0);
   }
   if (tid == 0 && fail) status_or(a, t, APIC_TILE_DF_CHOL_FAIL);
 }
