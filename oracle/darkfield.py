@@ -44,10 +44,15 @@ def coords_of(mask):
 
 
 def minkowski_diff(a, b, n):
-    """Boolean grid over [-n, n]^2 (offset n) of the set {p - q : p in a, q in b}."""
+    """Boolean grid over [-n, n]^2 (offset n) of the set {p - q : p in a, q in b},
+    looping over the smaller of the two sets."""
     grid = np.zeros((2 * n + 1, 2 * n + 1), dtype=bool)
-    for qy, qx in b:
-        grid[a[:, 0] - qy + n, a[:, 1] - qx + n] = True
+    if len(b) <= len(a):
+        for qy, qx in b:
+            grid[a[:, 0] - qy + n, a[:, 1] - qx + n] = True
+    else:
+        for py, px in a:
+            grid[py - b[:, 0] + n, px - b[:, 1] + n] = True
     return grid
 
 
@@ -90,12 +95,26 @@ def gather_signed(arr, ky, kx):
     return np.where(ok, arr[yy, xx], 0.0)
 
 
-def conv_matrix(p_hat, q, u):
-    """C[k, u] = conj(P_hat(u + k)) / N^2 for rows k in q, columns u in u."""
+def padded_spectrum(p_hat):
+    """P_hat at its signed positions on a 2N x 2N zero grid: indexing it at
+    (ky mod 2N, kx mod 2N) for any ky, kx in [-N, N) gives P_hat(ky, kx)
+    inside [-N/2, N/2)^2 and 0 outside, as ``gather_signed`` does."""
     n = p_hat.shape[0]
-    ky = q[:, 0][:, None] + u[:, 0][None, :]
-    kx = q[:, 1][:, None] + u[:, 1][None, :]
-    return np.conj(gather_signed(p_hat, ky, kx)) / float(n) ** 2
+    ky, kx = k_grid(n)
+    out = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    out[np.mod(ky, 2 * n), np.mod(kx, 2 * n)] = p_hat
+    return out
+
+
+def conv_matrix(p_hat, q, u, padded=None):
+    """C[k, u] = conj(P_hat(u + k)) / N^2 for rows k in q, columns u in u
+    (every u + k lies in [-N, N)); ``padded`` is ``padded_spectrum(p_hat)``
+    when the caller has it."""
+    n = p_hat.shape[0]
+    pad = padded_spectrum(p_hat) if padded is None else padded
+    ky = np.mod(q[:, 0][:, None] + u[:, 0][None, :], 2 * n)
+    kx = np.mod(q[:, 1][:, None] + u[:, 1][None, :], 2 * n)
+    return np.conj(pad[ky, kx]) / float(n) ** 2
 
 
 def normal_equations_fullq(p_hat, q, u, b):
@@ -103,8 +122,9 @@ def normal_equations_fullq(p_hat, q, u, b):
     nu = len(u)
     g = np.zeros((nu, nu), dtype=np.complex128)
     v = np.zeros(nu, dtype=np.complex128)
+    pad = padded_spectrum(p_hat)
     for s in range(0, len(q), ROW_CHUNK):
-        c = conv_matrix(p_hat, q[s:s + ROW_CHUNK], u)
+        c = conv_matrix(p_hat, q[s:s + ROW_CHUNK], u, pad)
         g += c.conj().T @ c
         v += c.conj().T @ b[s:s + ROW_CHUNK]
     return g, v
@@ -162,8 +182,9 @@ def gram_t_minus_e(p_hat, sets):
     dx = np.mod(u[None, :, 1] - u[:, None, 1], 2 * n)
     g = rgrid[dy, dx] / float(n) ** 4
     del dy, dx
+    pad = padded_spectrum(p_hat)
     for s in range(0, len(e), ROW_CHUNK):
-        ce = conv_matrix(p_hat, e[s:s + ROW_CHUNK], u)
+        ce = conv_matrix(p_hat, e[s:s + ROW_CHUNK], u, pad)
         g -= ce.conj().T @ ce
     return g
 

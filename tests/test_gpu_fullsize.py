@@ -11,7 +11,7 @@ import oracle
 import apic_synth as S
 from apic_synth.batch import synth_batch
 from paper_2407_20469_amd import apic
-from gpu_helpers import rel_l2
+from gpu_helpers import rel_l2, band_rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -30,21 +30,26 @@ def test_grid_batch_full_size_sampled_parity():
     geom = oracle.Geometry(**w.geometry_kwargs())
     for t in (0, 613):
         ref = oracle.reconstruct(images[t].cpu().numpy().astype(np.float64), geom)
-        err = rel_l2(field[t].cpu().numpy(), ref["field"])
+        f = field[t].cpu().numpy()
+        err = rel_l2(f, ref["field"])
+        err_df, err_bf = band_rel_l2(f, ref, geom)
         dz = float(np.abs(zern[t].cpu().numpy() - ref["c"]).max())
-        print(f"[gpu-test] grid tile {t}: field rel-L2 {err:.3e} max|dc| {dz:.2e} "
+        print(f"[gpu-test] grid tile {t}: field rel-L2 {err:.3e} (darkfield band {err_df:.2e}, "
+              f"brightfield band {err_bf:.2e}) max|dc| {dz:.2e} "
               f"kappa {ref['pupil']['kappa']:.1f}", flush=True)
         assert dz < 1e-3
         assert err < 1e-4
+        assert err_df < 1e-3
 
 
 @pytest.mark.timeout(900)
 def test_grid_batch_with_surrogate_full_size():
     """The benchmark's timed configuration: the prepared batch of the 1024 grid
-    tiles with the surrogate trained on their own closed-form estimates (the
-    benchmark's recipe) and autotuned chunks.  Every tile equals the plain
-    surrogate call bit for bit; sampled tiles match the oracle given the
-    coefficients the fallback rule chose."""
+    tiles with the surrogate trained by the benchmark's recipe (closed-form
+    estimates of training tiles disjoint from these) seeding the pupil solve,
+    and autotuned chunks.  Every tile equals the plain surrogate call bit for
+    bit; sampled tiles match the oracle given the coefficients the fallback
+    rule chose, over the whole field and over the darkfield band."""
     import bench
     dev = torch.device("cuda:0")
     w = S.grid_batch(n_tiles=1024)
@@ -54,7 +59,9 @@ def test_grid_batch_with_surrogate_full_size():
     plan = apic.Plan(w.geometry_kwargs())
     plan.upload()
     print("[gpu-test] train the surrogate (benchmark recipe)", flush=True)
-    sur, pos, note = bench.train_grid_surrogate(plan, flat, w, dev)
+    sur, note = bench.train_grid_surrogate(w, dev)
+    assert sur.seeds_solve
+    pos = torch.tensor(w.positions, dtype=torch.float32, device=dev)
     descs, n_img_el, n_fld_el = apic.mixed_descs(plan, np.zeros(w.n_tiles, np.int64))
     assert n_img_el == flat.numel()
     batch = apic.Batch(plan, descs)
@@ -88,8 +95,11 @@ def test_grid_batch_with_surrogate_full_size():
         zc = zern[t].cpu().numpy()
         ref = oracle.reconstruct(images[t].cpu().numpy().astype(np.float64), geom,
                                  zernike=zc.astype(np.float64))
-        err = rel_l2(fv[t].cpu().numpy(), ref["field"])
+        f = fv[t].cpu().numpy()
+        err = rel_l2(f, ref["field"])
+        err_df, _ = band_rel_l2(f, ref, geom)
         print(f"[gpu-test] grid tile {t} (status {int(st[t])}): field rel-L2 {err:.3e} "
-              f"given the chosen coefficients", flush=True)
+              f"(darkfield band {err_df:.2e}) given the chosen coefficients", flush=True)
         assert err < 1e-4
+        assert err_df < 1e-3
     batch.close()

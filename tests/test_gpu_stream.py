@@ -119,12 +119,15 @@ def test_stream_with_surrogate_and_no_threshold(slide):
     assert not np.any(status & apic.TILE_BACKGROUND)
 
 
+@pytest.mark.timeout(900)
 def test_stream_at_slide_size_matches_in_memory_call():
     """The slide stream's own launch configuration (512 px tiles, 16 + 32
     images, chunks of 64 over 3 buffers, background threshold 3e-3): 130
     scanned tiles (two full chunks and a ragged one) cycling through a pool of
     2 tissue tiles and 1 glass tile; every reconstructed tile equals the
-    in-memory call on its pool tile bit for bit, the glass tiles are skipped."""
+    in-memory call on its pool tile bit for bit, the glass tiles are skipped,
+    and the first streamed tissue tile matches the FP64 oracle (field rel-L2
+    1e-4, darkfield band 1e-3, Zernike 1e-3 rad)."""
     from apic_synth import slide
     from apic_synth.batch import synth_batch
     w = slide.pool_workload(2, 1)
@@ -151,3 +154,20 @@ def test_stream_at_slide_size_matches_in_memory_call():
             assert torch.equal(fields[t], f_ref[k]), t
             assert np.array_equal(z[t], z_ref[k]), t
             assert status[t] == np.uint32(s_ref[k]), t
+    # the first streamed tissue tile against the FP64 oracle: the whole 512 px
+    # chain, 16 NA-matched and all 32 darkfield images (Eq. 4-13), through the
+    # T - E route of the oracle's gram
+    import oracle
+    from gpu_helpers import rel_l2, band_rel_l2
+    t0 = src.index(0)
+    _log(f"streamed tile {t0} (pool tile 0) against the oracle, 512 px, 16 + 32 images")
+    geom = oracle.Geometry(**w.geometry_kwargs())
+    ref = oracle.reconstruct(pool[0].numpy().astype(np.float64), geom, gram="t-e")
+    f = fields[t0].numpy()
+    err = rel_l2(f, ref["field"])
+    err_df, err_bf = band_rel_l2(f, ref, geom)
+    dz = float(np.abs(z[t0] - ref["c"]).max())
+    n_u = [d["n_u"] for d in ref["darkfield"]]
+    _log(f"  field rel-L2 {err:.2e} (darkfield band {err_df:.2e}, brightfield {err_bf:.2e}), "
+         f"max|dc| {dz:.2e}, N_u {min(n_u)}..{max(n_u)}")
+    assert err < 1e-4 and err_df < 1e-3 and dz < 1e-3

@@ -39,12 +39,12 @@ def test_clean_oracle_passes_p6():
 
 def test_dropped_conjugate_in_c_is_caught(monkeypatch):
     orig = odf.conv_matrix
-    monkeypatch.setattr(odf, "conv_matrix", lambda p, q, u: np.conj(orig(p, q, u)))
+    monkeypatch.setattr(odf, "conv_matrix", lambda p, q, u, *pad: np.conj(orig(p, q, u, *pad)))
     assert _p6_error() > 1e-3
 
 
 def test_transposed_difference_in_c_is_caught(monkeypatch):
-    def wrong(p_hat, q, u):  # P_hat(u - k) instead of P_hat(u + k)
+    def wrong(p_hat, q, u, padded=None):  # P_hat(u - k) instead of P_hat(u + k)
         n = p_hat.shape[0]
         ky = u[:, 0][None, :] - q[:, 0][:, None]
         kx = u[:, 1][None, :] - q[:, 1][:, None]
