@@ -22,3 +22,20 @@ def lattice_geometry():
             (20, -15)]
     return {"n": 128, "dx_um": 0.390625, "wavelength_um": 0.5, "na_obj": 0.25,
             "k_bf": np.array(ring, dtype=np.int64)}
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_cached_device_memory():
+    """After each test module, hand the memory torch's caching allocator kept
+    back to the device, so that a later module's own allocations (the slide
+    streamer's staging buffers, the library's batch tables) find it free."""
+    yield
+    try:
+        import gc
+        import torch
+        if torch.cuda.is_available():
+            gc.collect()
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    except Exception:
+        pass

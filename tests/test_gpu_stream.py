@@ -139,6 +139,9 @@ def test_stream_at_slide_size_matches_in_memory_call():
     fields = [torch.full((nf, nf), complex(3.0, 3.0), dtype=torch.complex64).pin_memory()
               for _ in src]
     plan = apic.Plan(w.geometry_kwargs())
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()  # the streamer allocates its staging buffers itself
     st = apic.Streamer(plan, 0, chunk=64, n_buffers=3)
     _log(f"stream {len(src)} tiles of 512 px, chunk 64, 3 buffers")
     z, status, stat = st.run([pool[k] for k in src], fields, bg_threshold=3e-3)
