@@ -336,6 +336,17 @@ apic_status apic_batch_classes(const apic_batch *batch, int32_t *n_classes, int3
  * factors) overlap the other's.  Changes apic_batch_workspace_bytes and drops
  * a captured graph. */
 apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, int32_t lanes);
+/* LDS tiling of class `cls`'s FFT column passes: variant 0 takes panels of
+ * up to 16 adjacent columns and 2048 elements per workgroup, variant 1 panels
+ * twice as wide (when the panel stays within 64 KiB of LDS and 16 columns,
+ * else half as wide).  Each column's transform is the same either way, so the
+ * results are identical; only the access pattern and the workgroup count
+ * change.  apic_batch_fft_panel reports a class's variant and its panel width
+ * in columns for complex128 passes of the class's N.  Drops a captured graph;
+ * APIC_EINVAL for a bad class or variant. */
+apic_status apic_batch_set_fft(apic_batch *batch, int32_t cls, int32_t variant);
+apic_status apic_batch_fft_panel(const apic_batch *batch, int32_t cls, int32_t *variant,
+                                 int32_t *panel_columns);
 /* Autotuner.  For class `cls` (all classes when cls < 0), times the method
  * (with the surrogate stage when apic_batch_set_surrogate switched it on) on
  * its first k tiles for k = 1, 2, 4, ... up to the class size, as long as k
@@ -343,7 +354,9 @@ apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, 
  * under 3% past k = 4, or after a run longer than 10 s).  It then sets the
  * class's chunk to the smallest k whose time per tile is within (1 + slack)
  * of the best, tries two lanes of half that chunk over the same tiles (same
- * workspace) and keeps them if 2% faster.  If the classes' chunk blocks
+ * workspace) and keeps them if 2% faster, then times the class's FFT column
+ * passes with their two panel widths (apic_batch_set_fft) over the chosen
+ * chunk and keeps the alternative if 2% faster.  If the classes' chunk blocks
  * together exceed `workspace_bytes` (they run concurrently), the largest
  * blocks are halved until they fit.
  * Synchronises the host with `stream` after every run (not

@@ -43,7 +43,8 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
            "apic_batch_capture", "apic_batch_launch", "apic_batch_classes", "apic_batch_set_chunk", "apic_batch_set_surrogate",
-           "apic_batch_autotune", "apic_batch_fit", "apic_background_stat",
+           "apic_batch_autotune", "apic_batch_fit", "apic_batch_set_fft", "apic_batch_fft_panel",
+           "apic_background_stat",
            "apic_estimate_pupil_pixel", "apic_assembly_create", "apic_assembly_destroy",
            "apic_assemble_phases", "apic_blend", "apic_rgb_combine",
            "apic_streamer_create", "apic_streamer_destroy", "apic_streamer_device_bytes",
@@ -137,6 +138,8 @@ def load_library(path=LIB_PATH):
     lib.apic_batch_set_surrogate.argtypes = [P, P, P, f32, f32, f32]
     lib.apic_batch_autotune.argtypes = [P, i32, P, P, P, P, P, sz, P, ctypes.c_double, P]
     lib.apic_batch_fit.argtypes = [P, sz]
+    lib.apic_batch_set_fft.argtypes = [P, i32, i32]
+    lib.apic_batch_fft_panel.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.apic_background_stat.argtypes = [P, i32, ctypes.POINTER(TileDesc), P, P, P, sz, P]
     lib.apic_rgb_combine.argtypes = [i32, i32, P, P, P, P, P, P, P, sz, P]
     lib.apic_assembly_create.argtypes = [i32, i32, P, i32, i32, i32, ctypes.POINTER(P)]
@@ -324,7 +327,8 @@ class Batch:
         self.workspace_bytes = b.value
 
     def classes(self):
-        """[{geom, n_tiles, chunk, lanes, tile_bytes}] in the order the batch runs them."""
+        """[{geom, n_tiles, chunk, lanes, tile_bytes, fft_variant, fft_panel_columns}] in the
+        order the batch runs them."""
         n = ctypes.c_int32(0)
         _check("apic_batch_classes", self.lib.apic_batch_classes(self.handle, ctypes.byref(n),
                                                                  None, None, None, None, None))
@@ -335,8 +339,20 @@ class Batch:
             self.handle, ctypes.byref(n), g.ctypes.data_as(ctypes.c_void_p),
             t.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
             ln.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p)))
-        return [{"geom": int(g[i]), "n_tiles": int(t[i]), "chunk": int(c[i]), "lanes": int(ln[i]),
-                 "tile_bytes": int(b[i])} for i in range(cap)]
+        out = []
+        for i in range(cap):
+            var, cols = ctypes.c_int32(0), ctypes.c_int32(0)
+            _check("apic_batch_fft_panel", self.lib.apic_batch_fft_panel(
+                self.handle, i, ctypes.byref(var), ctypes.byref(cols)))
+            out.append({"geom": int(g[i]), "n_tiles": int(t[i]), "chunk": int(c[i]),
+                        "lanes": int(ln[i]), "tile_bytes": int(b[i]), "fft_variant": var.value,
+                        "fft_panel_columns": cols.value})
+        return out
+
+    def set_fft(self, cls, variant):
+        """Panel variant of class ``cls``'s FFT column passes (apic_batch_set_fft)."""
+        _check("apic_batch_set_fft", self.lib.apic_batch_set_fft(self.handle, cls, variant))
+        self._bound = None
 
     def set_chunk(self, cls, tiles, lanes=1):
         _check("apic_batch_set_chunk", self.lib.apic_batch_set_chunk(self.handle, cls, tiles,

@@ -33,6 +33,11 @@ namespace {
   do {                                                  \
     if (hipGetLastError() != hipSuccess) return APIC_EHIP; \
   } while (0)
+#define APIC_CHECK(...)                     \
+  do {                                      \
+    const apic_status rc_ = (__VA_ARGS__);  \
+    if (rc_ != APIC_OK) return rc_;         \
+  } while (0)
 
 // ------------------------------------------------------------ twiddles
 std::mutex g_tw_mu;
@@ -112,7 +117,7 @@ template <class T> apic_status upload_vec(const std::vector<T> &v, void **dst) {
 
 void free_geom(GeomPlan &g) {
   void **ptrs[] = {&g.d_row_il, &g.d_row_k, &g.d_known_at, &g.d_coords, &g.d_masks,
-                   &g.d_pix_tab, &g.d_pix_ginv};
+                   &g.d_pix_tab, &g.d_pix_ginv, &g.d_prow_il, &g.d_prow_k};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -284,6 +289,21 @@ __global__ void k_spec_copy(ClassArgs a, float *spec, int to_ohat) {
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 // ------------------------------------------------------------ stage runners
+// A column pass of the class with its panel variant (a.fft_var).
+template <class C, int L, class Op>
+apic_status launch_cols(const ClassArgs &a, int arrays, const Op &op, hipStream_t st) {
+  if (a.fft_var == 1) {
+    constexpr int NS = ColShapeAlt<C, L>::NSEQ;
+    hipLaunchKernelGGL((k_cols<C, L, Op, NS>), dim3(col_blocks<C, L, NS>(arrays)),
+                       dim3(kFftThreads), 0, st, op);
+  } else {
+    hipLaunchKernelGGL((k_cols<C, L, Op>), dim3(col_blocks<C, L>(arrays)), dim3(kFftThreads), 0,
+                       st, op);
+  }
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
 template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t st) {
   const int arrays = a.T * a.n_bf;
   // bytes: image read twice (stats, pass 1), 4 complex64 read+write passes minus pass-1 read
@@ -293,15 +313,11 @@ template <int N> apic_status run_kk(const ClassArgs &a, c32 *kk_out, hipStream_t
   hipLaunchKernelGGL((k_rows<c32, N, OpKK1<N>>), dim3(row_blocks<c32, N>(arrays, N)),
                      dim3(kFftThreads), 0, st, OpKK1<N>{a});
   APIC_LAUNCHED();
-  hipLaunchKernelGGL((k_cols<c32, N, OpKK2<N>>), dim3(col_blocks<c32, N>(arrays)),
-                     dim3(kFftThreads), 0, st, OpKK2<N>{a});
-  APIC_LAUNCHED();
+  APIC_CHECK(launch_cols<c32, N>(a, arrays, OpKK2<N>{a}, st));
   hipLaunchKernelGGL((k_rows<c32, N, OpKK3<N>>), dim3(row_blocks<c32, N>(arrays, N)),
                      dim3(kFftThreads), 0, st, OpKK3<N>{a});
   APIC_LAUNCHED();
-  hipLaunchKernelGGL((k_cols<c32, N, OpKK4<N>>), dim3(col_blocks<c32, N>(arrays)),
-                     dim3(kFftThreads), 0, st, OpKK4<N>{a, kk_out});
-  APIC_LAUNCHED();
+  APIC_CHECK(launch_cols<c32, N>(a, arrays, OpKK4<N>{a, kk_out}, st));
   return APIC_OK;
 }
 
@@ -406,18 +422,14 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP1<N>{a});
       APIC_LAUNCHED();
-      hipLaunchKernelGGL((k_cols<c64, N, OpP2<N>>), dim3(col_blocks<c64, N>(a.T)),
-                         dim3(kFftThreads), 0, st, OpP2<N>{a});
-      APIC_LAUNCHED();
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a}, st));
       hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP3<N>{a});
       APIC_LAUNCHED();
       hipLaunchKernelGGL((k_rows<c64, N, OpImg1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpImg1<N>{a, s.img});
       APIC_LAUNCHED();
-      hipLaunchKernelGGL((k_cols<c64, N, OpImg2<N>>), dim3(col_blocks<c64, N>(a.T)),
-                         dim3(kFftThreads), 0, st, OpImg2<N>{a});
-      APIC_LAUNCHED();
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpImg2<N>{a}, st));
     }
     {
       // three FP64 passes: Q bitmap, fimg and fpp on Q, write (16 B per pixel
@@ -428,9 +440,7 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
       hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpR1<N>{a, s.qbits});
       APIC_LAUNCHED();
-      hipLaunchKernelGGL((k_cols<c64, N, OpR2<N>>), dim3(col_blocks<c64, N>(a.T)),
-                         dim3(kFftThreads), 0, st, OpR2<N>{a});
-      APIC_LAUNCHED();
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpR2<N>{a}, st));
       hipLaunchKernelGGL((k_rows<c64, N, OpR3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpR3<N>{a});
       APIC_LAUNCHED();
@@ -496,9 +506,7 @@ apic_status run_output_nf(const ClassArgs &a, const c32 *src, float *field, hipS
   hipLaunchKernelGGL((k_rows<c32, NF, OpOut1<NF>>), dim3(row_blocks<c32, NF>(a.T, N)),
                      dim3(kFftThreads), 0, st, OpOut1<NF>{a, src});
   APIC_LAUNCHED();
-  hipLaunchKernelGGL((k_cols<c32, NF, OpOut2<NF>>), dim3(col_blocks<c32, NF>(a.T)),
-                     dim3(kFftThreads), 0, st, OpOut2<NF>{a, reinterpret_cast<c32 *>(field)});
-  APIC_LAUNCHED();
+  APIC_CHECK(launch_cols<c32, NF>(a, a.T, OpOut2<NF>{a, reinterpret_cast<c32 *>(field)}, st));
   return APIC_OK;
 }
 template <int N>
@@ -562,9 +570,13 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
   }
   if (st_mask & S_PIX) {
     if (a.n_pix == 0) return APIC_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_pix_rows, dim3(a.T * a.n_chunks), dim3(256), 0, st, a);
+    // the pixel-domain passes walk the rows in pair order (their tables)
+    ClassArgs ap = a;
+    ap.row_il = (const uint32_t *)p->geoms[r.geom].d_prow_il;
+    ap.row_k = (const uint32_t *)p->geoms[r.geom].d_prow_k;
+    hipLaunchKernelGGL(k_pix_rows, dim3(ap.T * ap.n_chunks), dim3(256), 0, st, ap);
     APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_pix_cg, dim3(a.T), dim3(kPixThreads), 0, st, a, io.pix_tol,
+    hipLaunchKernelGGL(k_pix_cg, dim3(ap.T), dim3(kPixThreads), 0, st, ap, io.pix_tol,
                        io.pix_max_iter, io.phi_out, io.zout, io.pix_iters);
     APIC_LAUNCHED();
   }
@@ -738,6 +750,7 @@ struct apic_batch {
   std::vector<apic::ClassRun> runs;
   std::vector<int32_t> chunk;    // tiles per launch sequence, per class
   std::vector<int32_t> lanes;    // chunks of a class in flight at once (1 or 2)
+  std::vector<int32_t> fft_var;  // column-pass panel variant per class (0 or 1)
   std::vector<int64_t> cls_ws;   // workspace offset of each class's chunk blocks
   std::vector<hipStream_t> lane_stream;         // a class's second lane
   std::vector<hipEvent_t> lane_fork, lane_join;
@@ -821,7 +834,9 @@ apic_status apic_plan_upload(apic_plan *plan) {
     if ((rc = upload_vec(g.row_il, &g.d_row_il)) || (rc = upload_vec(g.row_k, &g.d_row_k)) ||
         (rc = upload_vec(g.known_at, &g.d_known_at)) || (rc = upload_vec(g.coords, &g.d_coords)) ||
         (rc = upload_vec(g.masks, &g.d_masks)) || (rc = upload_vec(g.pix_tab, &g.d_pix_tab)) ||
-        (rc = upload_vec(g.pix_ginv, &g.d_pix_ginv))) {
+        (rc = upload_vec(g.pix_ginv, &g.d_pix_ginv)) ||
+        (rc = upload_vec(g.pix_ok ? g.prow_il : std::vector<uint32_t>(), &g.d_prow_il)) ||
+        (rc = upload_vec(g.pix_ok ? g.prow_k : std::vector<uint32_t>(), &g.d_prow_k))) {
       for (GeomPlan &h : plan->geoms) free_geom(h);
       return rc;
     }
@@ -1204,6 +1219,7 @@ static apic_status batch_run_class(apic_batch *b, size_t c, int first, int count
   const ClassRun &r = b->runs[c];
   ClassArgs a = make_args(b->plan, r, images, ws, status, reinterpret_cast<const char *>(b->d_desc));
   a.ws = ws + b->cls_ws[c];
+  a.fft_var = b->fft_var[c];
   const int step = std::max(1, b->chunk[c]);  // chunks are >= 1 by construction
   // with two lanes, chunk i runs on lane i % 2 in that lane's workspace block:
   // one chunk's latency-bound kernels overlap the other's throughput-bound ones
@@ -1258,6 +1274,7 @@ apic_status apic_batch_create(apic_plan *plan, int32_t n_tiles, const apic_tile_
   for (const ClassRun &r : b->runs) {
     b->chunk.push_back((int32_t)r.gidx.size());
     b->lanes.push_back(1);
+    b->fft_var.push_back(0);
   }
   batch_layout(b);
   if (rc == APIC_OK) rc = apic_plan_upload(plan);
@@ -1428,6 +1445,33 @@ apic_status apic_batch_set_chunk(apic_batch *batch, int32_t cls, int32_t tiles, 
   return APIC_OK;
 }
 
+apic_status apic_batch_set_fft(apic_batch *batch, int32_t cls, int32_t variant) {
+  if (!batch_ok(batch) || cls < 0 || cls >= (int32_t)batch->runs.size()) return APIC_EINVAL;
+  if (variant != 0 && variant != 1) return APIC_EINVAL;
+  batch->fft_var[cls] = variant;
+  batch_drop_graph(batch);
+  return APIC_OK;
+}
+
+apic_status apic_batch_fft_panel(const apic_batch *batch, int32_t cls, int32_t *variant,
+                                 int32_t *panel_columns) {
+  if (!batch_ok(batch) || cls < 0 || cls >= (int32_t)batch->runs.size()) return APIC_EINVAL;
+  const int v = batch->fft_var[cls];
+  if (variant) *variant = v;
+  if (panel_columns) {
+    int cols = 0;
+    switch (batch->plan->geoms[batch->runs[cls].geom].n) {
+      case 64: cols = v ? ColShapeAlt<c64, 64>::NSEQ : ColShape<c64, 64>::NSEQ; break;
+      case 128: cols = v ? ColShapeAlt<c64, 128>::NSEQ : ColShape<c64, 128>::NSEQ; break;
+      case 256: cols = v ? ColShapeAlt<c64, 256>::NSEQ : ColShape<c64, 256>::NSEQ; break;
+      case 512: cols = v ? ColShapeAlt<c64, 512>::NSEQ : ColShape<c64, 512>::NSEQ; break;
+      default: return APIC_EUNSUPPORTED;
+    }
+    *panel_columns = cols;
+  }
+  return APIC_OK;
+}
+
 apic_status apic_batch_fit(apic_batch *batch, size_t workspace_bytes) {
   if (!batch_ok(batch)) return APIC_EINVAL;
   // the classes run concurrently: halve the largest blocks until they fit together
@@ -1480,7 +1524,8 @@ apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *ima
     return APIC_EHIP;
   }
   apic_status rc = APIC_OK;
-  const std::vector<int32_t> saved = batch->chunk, saved_lanes = batch->lanes;
+  const std::vector<int32_t> saved = batch->chunk, saved_lanes = batch->lanes,
+                             saved_fft = batch->fft_var;
   std::vector<int64_t> saved_ws = batch->cls_ws;
   // time tiles [0, count) of class c with the current chunk and lanes, from
   // offset 0 of the workspace
@@ -1556,6 +1601,20 @@ apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *ima
       }
       if (rc == APIC_OK && ms_per_tile) ms_per_tile[c] = std::min(ms1, ms2) / span;
     }
+    // the column passes' panel width (LDS tiling): kept if 2% faster over
+    // the chosen chunk
+    if (rc == APIC_OK) {
+      const int span = std::min(T, batch->chunk[c] * batch->lanes[c]);
+      float ms0 = 0.f, ms1 = 0.f;
+      batch->fft_var[c] = 0;
+      rc = time_class(c, span, ms0);
+      if (rc == APIC_OK) {
+        batch->fft_var[c] = 1;
+        rc = time_class(c, span, ms1);
+      }
+      if (rc == APIC_OK && !(ms1 < 0.98f * ms0)) batch->fft_var[c] = 0;
+      if (rc == APIC_OK && ms_per_tile) ms_per_tile[c] = std::min(ms0, ms1) / span;
+    }
     batch->cls_ws = saved_ws;
   }
   (void)hipEventDestroy(e0);
@@ -1563,6 +1622,7 @@ apic_status apic_batch_autotune(apic_batch *batch, int32_t cls, const float *ima
   if (rc != APIC_OK) {
     batch->chunk = saved;
     batch->lanes = saved_lanes;
+    batch->fft_var = saved_fft;
     batch_layout(batch);
     batch_drop_graph(batch);
     return rc;

@@ -75,6 +75,7 @@ struct ClassArgs {
   double r_d;             // pupil radius in double precision
   float log_floor_rel;
   int n_rows, n_chunks, nu_pad;
+  int fft_var;                    // column-pass panel: 0 ColShape, 1 ColShapeAlt
   int n_band;                     // band passes of the pupil continuation (0: single pass)
   int band_rows[kPupilBands];     // rows of each band pass (a prefix of the sorted rows)
   double ridge_pupil, ridge_df;

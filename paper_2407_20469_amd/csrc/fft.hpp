@@ -107,6 +107,16 @@ template <class C, int L> struct ColShape {
   // hides the strided HBM reads better than wider rows would.
   static constexpr int NSEQ = (2048 / L >= 16) ? 16 : (2048 / L >= 8) ? 8 : 4;
 };
+// The alternative panel the batch autotuner may pick per geometry class:
+// twice as wide (longer contiguous row segments, fewer workgroups) while the
+// panel stays within 64 KiB of LDS and 16 columns, else half as wide (more
+// workgroups per CU).  A column's transform is the same either way, so the
+// results are identical; only the memory access pattern changes.
+template <class C, int L> struct ColShapeAlt {
+  static constexpr int N0 = ColShape<C, L>::NSEQ;
+  static constexpr int NSEQ =
+      (2 * N0 <= 16 && 2 * N0 * L * (int)sizeof(C) <= 65536) ? 2 * N0 : (N0 >= 8 ? N0 / 2 : N0);
+};
 
 // Row pass: workgroup = ROWS consecutive rows of one 2D array.  Op provides
 //   static constexpr bool INV1, TWO, INV2;
@@ -142,9 +152,8 @@ __global__ __launch_bounds__(kFftThreads) void k_rows(Op op) {
 }
 
 // Column pass: workgroup = NSEQ adjacent columns of one 2D array (all L rows).
-template <class C, int L, class Op>
+template <class C, int L, class Op, int NSEQ = ColShape<C, L>::NSEQ>
 __global__ __launch_bounds__(kFftThreads) void k_cols(Op op) {
-  constexpr int NSEQ = ColShape<C, L>::NSEQ;
   __shared__ C buf[L * NSEQ];
   constexpr int groups = L / NSEQ;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring panels on one XCD
@@ -173,8 +182,8 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(Op op) {
 template <class C, int L> inline int row_blocks(int arrays, int rows) {
   return arrays * (rows / RowShape<C, L>::ROWS);
 }
-template <class C, int L> inline int col_blocks(int arrays) {
-  return arrays * (L / ColShape<C, L>::NSEQ);
+template <class C, int L, int NSEQ = ColShape<C, L>::NSEQ> inline int col_blocks(int arrays) {
+  return arrays * (L / NSEQ);
 }
 
 // Plain batched transform of contiguous L x L arrays (library utility).

@@ -96,8 +96,8 @@ static void build_pixel_tables(GeomPlan &p, int n_bf) {
   auto idx = [&](int ky, int kx) { return uint32_t(at[size_t(ky + h) * n + (kx + h)]); };
   p.pix_tab = pix;
   for (int rI = 0; rI < p.n_rows; ++rI) {
-    const int i = p.row_il[rI] & 0xff, l = (p.row_il[rI] >> 8) & 0xff;
-    const int Ky = unpack_ky(p.row_k[rI]), Kx = unpack_kx(p.row_k[rI]);
+    const int i = p.prow_il[rI] & 0xff, l = (p.prow_il[rI] >> 8) & 0xff;
+    const int Ky = unpack_ky(p.prow_k[rI]), Kx = unpack_kx(p.prow_k[rI]);
     const uint32_t a = idx(Ky + p.kbf[2 * i + 1], Kx + p.kbf[2 * i]);
     const uint32_t b = idx(Ky + p.kbf[2 * l + 1], Kx + p.kbf[2 * l]);
     p.pix_tab.push_back(a | (b << 16));
@@ -203,7 +203,10 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   p.n_rows = int(p.row_k.size());
   p.n_chunks = std::max(1, (p.n_rows + kAbChunk - 1) / kAbChunk);
   // band of each row: the first f with Kx^2 + Ky^2 <= (f r)^2, kPupilBands
-  // if none; rows sorted by band (stable), band passes = prefixes
+  // if none; rows sorted by band (stable), band passes = prefixes; the pair
+  // order is kept for the pixel-domain solve
+  p.prow_il = p.row_il;
+  p.prow_k = p.row_k;
   {
     std::vector<int> band(p.n_rows);
     std::vector<int64_t> count(kPupilBands + 1, 0);

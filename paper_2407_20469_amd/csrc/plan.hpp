@@ -77,10 +77,13 @@ struct GeomPlan {
   // the bands holding at least kMinBandRows); empty for the single pass
   bool pupil_bands = true;
   std::vector<int> band_rows;
+  // the same rows in pair order (pairs i < l, then K raster): the row order
+  // of the pixel-domain solve, whose passes sum each pair's rows in one run
+  std::vector<uint32_t> prow_il, prow_k;
   // pupil pixels (Eq. 10 with one unknown per pixel), raster order over the
   // disk (ky ascending, then kx): built when n_pix <= kPixMax.  pix_tab holds
-  // the pixels' packed k, then per pupil row the pixel indices of K + K_i
-  // (low half) and K + K_l (high half), then the pixel index of each
+  // the pixels' packed k, then per pupil row (in pair order, prow_*) the pixel
+  // indices of K + K_i (low half) and K + K_l (high half), then the pixel index of each
   // NA-matched k_i.  pix_ginv is the inverse Gram matrix of Noll Z_1..Z_15 over
   // the pixels (15 x 15, row-major), for the Zernike summary.
   int n_pix = 0;
@@ -98,7 +101,8 @@ struct GeomPlan {
   TileLayout lay;
   // device copies (owned; filled by upload)
   void *d_row_il = nullptr, *d_row_k = nullptr, *d_known_at = nullptr, *d_coords = nullptr,
-       *d_masks = nullptr, *d_pix_tab = nullptr, *d_pix_ginv = nullptr;
+       *d_masks = nullptr, *d_pix_tab = nullptr, *d_pix_ginv = nullptr, *d_prow_il = nullptr,
+       *d_prow_k = nullptr;
 };
 
 // Build the host tables of one geometry; returns APIC_OK or an error code.

@@ -6,6 +6,7 @@
         <copy_fetch_dir> <copy_write_dir> <min_grid>
     python -m paper_2407_20469_amd.pmc_summary traffic <fetch_dir> <write_dir> \
         <copy_fetch_dir> <copy_write_dir> <min_grid> [out.json]
+    python -m paper_2407_20469_amd.pmc_summary busy <kernel_trace.csv> <regex> [gap_ms]
 
 `traffic` reads the counter-collection CSVs of four `rocprofv3 --pmc` runs
 (FETCH_SIZE and WRITE_SIZE of the darkfield gram kernels, and the same two
@@ -119,6 +120,47 @@ def hbm(fetch_dir, write_dir, cf_dir, cw_dir, min_grid):
     return "\n".join(out)
 
 
+def busy(path, pattern, gap_ms=5.0):
+    """GPU busy fraction of the longest passes of the kernels matching
+    `pattern`: their dispatches are cut into passes at idle gaps longer than
+    `gap_ms` (no kernel of the pattern running), and for the two longest
+    passes the union of the dispatch intervals is compared with the pass's
+    span.  Concurrent dispatches on several streams count once."""
+    import re
+    rx = re.compile(pattern)
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                for r in csv.DictReader(open(path)) if rx.search(r["Kernel_Name"]))
+    passes, cur, end = [], [], None
+    for a, b in iv:
+        if end is not None and a - end > gap_ms * 1e6:
+            passes.append(cur)
+            cur = []
+            end = None
+        cur.append((a, b))
+        end = b if end is None else max(end, b)
+    if cur:
+        passes.append(cur)
+    out = ["| pass | dispatches | span s | busy s | busy fraction | idle s |",
+           "|---|---:|---:|---:|---:|---:|"]
+    ranked = sorted(range(len(passes)),
+                    key=lambda i: -(max(b for _, b in passes[i]) - passes[i][0][0]))[:2]
+    for i in sorted(ranked):
+        p = passes[i]
+        span = max(b for _, b in p) - p[0][0]
+        tot, ca, cb = 0, None, None
+        for a, b in p:
+            if cb is None or a > cb:
+                if cb is not None:
+                    tot += cb - ca
+                ca, cb = a, b
+            else:
+                cb = max(cb, b)
+        tot += cb - ca
+        out.append(f"| {i} | {len(p)} | {span / 1e9:.3f} | {tot / 1e9:.3f} | {tot / span:.4f} | "
+                   f"{(span - tot) / 1e9:.3f} |")
+    return "\n".join(out)
+
+
 def stats(path, top=16):
     rows = list(csv.DictReader(open(path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
@@ -144,5 +186,7 @@ if __name__ == "__main__":
         print(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4])))
     elif sys.argv[1] == "hbm":
         print(hbm(*sys.argv[2:6], int(sys.argv[6])))
+    elif sys.argv[1] == "busy":
+        print(busy(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else 5.0))
     elif sys.argv[1] == "hash":
         print(gram_source_hash())

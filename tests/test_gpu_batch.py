@@ -134,6 +134,32 @@ def test_graph_replay_matches_eager(uneven):
     batch.close()
 
 
+def test_fft_panel_variants_give_identical_results(uneven):
+    """Every class with the alternative panel width of its FFT column passes
+    (the autotuner's LDS-tiling choice) reproduces the plain call bit for bit:
+    each column's transform is the same, only the access pattern changes."""
+    _, _, _, _, plan, descs, n_fld_el, images = uneven
+    ref_f, ref_z, ref_s = _plain(plan, descs, images, n_fld_el)
+    batch = apic.Batch(plan, descs)
+    before = batch.classes()
+    for i in range(len(before)):
+        batch.set_fft(i, 1)
+    after = batch.classes()
+    _log("panel columns per class: " + ", ".join(
+        f"{b['fft_panel_columns']} -> {a['fft_panel_columns']}" for b, a in zip(before, after)))
+    assert all(a["fft_variant"] == 1 for a in after)
+    assert any(a["fft_panel_columns"] != b["fft_panel_columns"] for a, b in zip(after, before))
+    field, zern, status = _buffers(len(descs), n_fld_el)
+    batch.reconstruct(images, field, zern, status, apic.Workspace())
+    torch.cuda.synchronize()
+    assert np.array_equal(field.cpu().numpy(), ref_f)
+    assert np.array_equal(zern.cpu().numpy(), ref_z)
+    assert np.array_equal(status.cpu().numpy(), ref_s)
+    with pytest.raises(apic.ApicError):
+        batch.set_fft(0, 2)
+    batch.close()
+
+
 def test_batch_rejects_bad_descriptors(uneven):
     _, _, _, _, plan, descs, _, _ = uneven
     bad = (apic.TileDesc * 1)()
