@@ -168,7 +168,9 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
 apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
                             int32_t *out, int64_t cap, int64_t *len);
 
-/* Whole method: KK -> pupil -> stitch -> darkfield -> fN x fN field.
+/* Whole method: KK -> pupil -> stitch -> darkfield -> fN x fN field
+ * (paper Sec. 2.3 and Fig. 2: Eq. 4-7 field recovery, Eq. 8-10 aberration
+ * correction, Eq. 11-13 darkfield extension, then the up-sampled field).
  *   images        float   [per tile: n_bf + n_df][N][N]   (device, at image_offset)
  *   zernike_seed  float   [T][15] or NULL: re-wrap the pupil phases around it
  *   zernike_out   float   [T][15]
@@ -590,9 +592,14 @@ apic_status apic_profile_read(int32_t group, double *total_ms, int64_t *launches
  * apic_calib_fma64: `blocks` x 256 threads, each `iters` x 128 dependent-free
  *   FP64 FMAs (8 chains), writing one double per thread to out[blocks * 256];
  *   flops = blocks * 256 * iters * 256.
+ * apic_calib_mfma64: the same on the FP64 matrix cores: `blocks` x 4 waves,
+ *   each `iters` x 8 independent 16 x 16 x 4 FP64 matrix products
+ *   (v_mfma_f64_16x16x4f64), one double per thread to out[blocks * 256];
+ *   flops = blocks * 4 * iters * 8 * 2048.
  * apic_calib_copy: copies `bytes` (multiple of 16) from `in` to `out` with a
  *   grid-stride 16-byte loop; HBM traffic is bytes read + bytes written. */
 apic_status apic_calib_fma64(double *out, int32_t blocks, int32_t iters, void *stream);
+apic_status apic_calib_mfma64(double *out, int32_t blocks, int32_t iters, void *stream);
 apic_status apic_calib_copy(const void *in, void *out, int64_t bytes, void *stream);
 
 /* Library version string. */

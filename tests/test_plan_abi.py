@@ -38,12 +38,19 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.apic_version()
 
 
-@pytest.mark.parametrize("wl", ["single128", "small64", "two_ring128"])
+@pytest.mark.parametrize("wl", ["single128", "small64", "two_ring128", "grid256", "slide512"])
 def test_plan_sets_equal_oracle_sets(wl):
+    """Also at the two benchmark geometries: 256 px and 512 px, 16 NA-matched
+    and 32 darkfield images on two rings."""
     if wl == "single128":
         w = S.single_tile()
     elif wl == "small64":
         w = S.small_workload(n=64)
+    elif wl == "grid256":
+        w = S.grid_batch()
+    elif wl == "slide512":
+        from apic_synth import slide
+        w = slide.pool_workload(2, 1)
     else:
         w = S.small_workload(n=128, n_bf=12, n_df=24, na_df=(0.30, 0.38))
     plan = apic.Plan(w.geometry_kwargs())
