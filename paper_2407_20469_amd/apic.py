@@ -38,7 +38,7 @@ EXPORTS = ["apic_plan_create", "apic_plan_destroy", "apic_plan_upload", "apic_wo
            "apic_plan_query", "apic_reconstruct_tiles", "apic_reconstruct_tiles_static",
            "apic_estimate_pupil", "apic_kk_spectra",
            "apic_stitch_brightfield", "apic_extend_darkfield", "apic_upsample_field", "apic_fft2",
-           "apic_profile", "apic_profile_read", "apic_calib_fma64", "apic_calib_copy",
+           "apic_profile", "apic_profile_read", "apic_calib_fma64", "apic_calib_mfma64", "apic_calib_copy",
            "apic_mlp_forward", "apic_mlp_train", "apic_mlp_grad", "apic_bf16_gemm",
            "apic_estimate_pupil_sur", "apic_reconstruct_tiles_sur", "apic_batch_create",
            "apic_batch_destroy", "apic_batch_workspace_bytes", "apic_batch_reconstruct",
@@ -154,6 +154,7 @@ def load_library(path=LIB_PATH):
     lib.apic_streamer_run.argtypes = [P, i32, P, P, P, ctypes.POINTER(MlpModel), f32, f32, f32,
                                       f32, P, P, P]
     lib.apic_calib_fma64.argtypes = [P, i32, i32, P]
+    lib.apic_calib_mfma64.argtypes = [P, i32, i32, P]
     lib.apic_calib_copy.argtypes = [P, P, i64, P]
     lib.apic_profile.argtypes = [i32]
     lib.apic_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),

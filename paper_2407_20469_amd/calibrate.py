@@ -2,9 +2,10 @@
 
     python -m paper_2407_20469_amd.calibrate
 
-Runs the library's probes: a sustained FP64 FMA loop and a plain 4 GiB copy
-(three repetitions).  Prints one JSON line with the FP64 rate in TFLOP/s and
-the copy bandwidth (read + write bytes over time) in GB/s.  Under
+Runs the library's probes: a sustained FP64 FMA loop, the same work on the
+FP64 matrix cores and a plain 4 GiB copy (three repetitions).  Prints one
+JSON line with the two FP64 rates in TFLOP/s and the copy bandwidth (read +
+write bytes over time) in GB/s.  Under
 `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` the copy dispatches give the
 counter-to-bytes scale: each copy moves exactly COPY_BYTES each way.
 """
@@ -29,6 +30,12 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     res = {"fp64_fma_tflops": blocks * 256 * iters * 256 / e0.elapsed_time(e1) / 1e9}
+    apic._check("apic_calib_mfma64", lib.apic_calib_mfma64(ctypes.c_void_p(out.data_ptr()), blocks, 10, st))
+    e0.record()
+    apic._check("apic_calib_mfma64", lib.apic_calib_mfma64(ctypes.c_void_p(out.data_ptr()), blocks, iters, st))
+    e1.record()
+    torch.cuda.synchronize()
+    res["fp64_mfma_tflops"] = blocks * 4 * iters * 8 * 2048 / e0.elapsed_time(e1) / 1e9
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     best = 0.0

@@ -1059,6 +1059,14 @@ apic_status apic_calib_fma64(double *out, int32_t blocks, int32_t iters, void *s
   return APIC_OK;
 }
 
+apic_status apic_calib_mfma64(double *out, int32_t blocks, int32_t iters, void *stream) {
+  if (!out || blocks <= 0 || iters < 0) return APIC_EINVAL;
+  hipLaunchKernelGGL(k_calib_mfma64, dim3(blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), out, iters, 0.5, 0.25);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
 apic_status apic_calib_copy(const void *in, void *out, int64_t bytes, void *stream) {
   if (!in || !out || bytes <= 0 || (bytes % 16) != 0) return APIC_EINVAL;
   hipLaunchKernelGGL(k_calib_copy, dim3(256 * 64), dim3(256), 0,

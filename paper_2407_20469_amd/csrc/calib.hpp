@@ -1,7 +1,8 @@
 // Measurement probes for roofline reporting: a sustained FP64 FMA loop (eight
-// independent chains per lane) and a plain grid-stride 16-byte copy whose HBM
-// traffic is known exactly (used to scale the FETCH_SIZE / WRITE_SIZE
-// counters of the other kernels).
+// independent chains per lane), the same on the FP64 matrix cores (16 x 16 x 4
+// products, eight independent accumulators per wave) and a plain grid-stride
+// 16-byte copy whose HBM traffic is known exactly (used to scale the
+// FETCH_SIZE / WRITE_SIZE counters of the other kernels).
 #pragma once
 
 #include "common.hpp"
@@ -21,6 +22,22 @@ __global__ __launch_bounds__(256) void k_calib_fma64(double *out, int iters, dou
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) s += x[k];
+  out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+typedef double calib_d4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_calib_mfma64(double *out, int iters, double a, double b) {
+  calib_d4 c[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] = calib_d4{0.0, 0.0, 0.0, (double)k};
+  const double x = a + threadIdx.x, y = b - threadIdx.x;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c[k], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += c[k][0] + c[k][1] + c[k][2] + c[k][3];
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
