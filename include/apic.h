@@ -113,7 +113,7 @@ typedef struct {
   double log_floor_rel;    /* eps = log_floor_rel * mean(I) before the log (1e-6)   */
   int32_t pupil_bands;     /* 1 (default): solve Eq. 10 coarse to fine, first on the
                               rows with |K| <= f r for f = 0.05, 0.1, 0.2, 0.4, 0.8,
-                              1.6 (bands of fewer than 256 rows skipped), each band
+                              1.6 (bands of fewer than 32 rows skipped), each band
                               re-wrapping beta about the previous band's solution
                               (the seeded variant) and solved with a ridge of
                               0.1 tr(A)/12, then on every row; phase

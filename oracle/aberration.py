@@ -26,7 +26,11 @@ Readings taken:
   by the last band.  Near K = 0 the row operator is about K times a gradient
   difference of the pupil phase, so the low-|K| rows stay unwrapped however
   large the aberration, and every later band only has to add a correction
-  smaller than pi.  A band holding fewer than MIN_BAND_ROWS rows is skipped.
+  smaller than pi.  A band holding fewer than MIN_BAND_ROWS rows (32, above
+  the 12 unknowns; the band ridge below covers what its rows leave
+  unconstrained) is skipped.  The first band solved must be small enough that
+  its rows do not wrap: on 128 px tiles with 8 NA-matched LEDs the two
+  smallest bands hold 40 and 168 rows.
   The band solves carry a strong ridge (PUPIL_BAND_RIDGE tr(A) / 12): the
   low-|K| rows leave some directions of c nearly unconstrained, and the ridge
   keeps the band's increment there near zero instead of fitting noise, which
@@ -44,7 +48,7 @@ N_FEATURE_ANGLE = 8
 N_FEATURE_BAND = 4
 N_FEATURES = N_FEATURE_ANGLE * N_FEATURE_BAND
 PUPIL_BANDS = (0.05, 0.1, 0.2, 0.4, 0.8, 1.6)
-MIN_BAND_ROWS = 256
+MIN_BAND_ROWS = 32
 PUPIL_BAND_RIDGE = 0.1
 
 

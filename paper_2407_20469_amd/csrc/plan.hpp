@@ -26,7 +26,7 @@ constexpr int kPixMax = 7936;       // pupil pixels of the pixel-domain solve (L
 // f, each band used when it holds at least kMinBandRows rows.
 constexpr int kPupilBands = 6;
 constexpr double kPupilBandFrac[kPupilBands] = {0.05, 0.1, 0.2, 0.4, 0.8, 1.6};
-constexpr int kMinBandRows = 256;
+constexpr int kMinBandRows = 32;
 // Ridge of the band solves (relative, mu tr(A) / 12): keeps each band's
 // increment near zero in the directions its low-|K| rows hardly constrain.
 constexpr double kPupilBandRidge = 0.1;
