@@ -17,12 +17,14 @@ from .leds import led_ring, led_rings
 from .objects import (gaussian_smooth_periodic, minmax, object_smooth, object_background,
                       object_blobs)
 from .configs import (OPTICS, Workload, single_tile, grid_batch, uneven_batch, uneven_classes, uneven_tiles,
-                      field_model_quadratic, pupil_random, small_workload)
+                      field_model_quadratic, field_model_on_grid, pupil_random, small_workload,
+                      surrogate_train_batch, surrogate_eval_batch)
 from .imaging import form_images, add_poisson
 
 __all__ = [
     "led_ring", "led_rings", "gaussian_smooth_periodic", "minmax", "object_smooth",
     "object_background", "object_blobs", "OPTICS", "Workload", "single_tile", "grid_batch",
-    "uneven_batch", "uneven_classes", "uneven_tiles", "field_model_quadratic", "pupil_random", "small_workload",
+    "uneven_batch", "uneven_classes", "uneven_tiles", "field_model_quadratic", "field_model_on_grid",
+    "pupil_random", "small_workload", "surrogate_train_batch", "surrogate_eval_batch",
     "form_images", "add_poisson",
 ]

@@ -132,41 +132,86 @@ def uneven_classes():
     return out
 
 
-def uneven_tiles(n_tiles=4096, seed=2):
-    """Per-tile (size, n_bf, background, grid position) of the uneven batch:
-    sizes 128/256/512 in the ratio 4:3:1, n_bf uniform in {8, 12, 16}, 40%
-    background tiles, on a 64 x 64 field grid."""
+def uneven_tiles(n_tiles=4096, seed=2, background_fraction=0.4, random_positions=False):
+    """Per-tile (size, n_bf, background, position) of the uneven batch: sizes
+    128/256/512 in the ratio 4:3:1, n_bf uniform in {8, 12, 16}, 40%
+    background tiles (``background_fraction``), on a square field grid
+    (64 x 64 for 4096 tiles) or, with ``random_positions``, at positions
+    uniform over [-1, 1]^2 (``default_rng([2, 3, seed])``)."""
     rng = np.random.default_rng([2, 2, seed])
     sizes = np.array([128] * (n_tiles // 2) + [256] * (3 * n_tiles // 8)
                      + [512] * (n_tiles - n_tiles // 2 - 3 * n_tiles // 8))
     rng.shuffle(sizes)
     nbf = rng.choice([8, 12, 16], size=n_tiles)
     bg = np.zeros(n_tiles, dtype=bool)
-    bg[rng.choice(n_tiles, size=int(round(0.4 * n_tiles)), replace=False)] = True
-    g = np.arange(n_tiles)
-    side = int(round(np.sqrt(n_tiles)))
-    u = (g % side - (side - 1) / 2) / ((side - 1) / 2)
-    v = (g // side - (side - 1) / 2) / ((side - 1) / 2)
+    bg[rng.choice(n_tiles, size=int(round(background_fraction * n_tiles)), replace=False)] = True
+    if random_positions:
+        uv = np.random.default_rng([2, 3, seed]).uniform(-1.0, 1.0, (n_tiles, 2))
+        u, v = uv[:, 0], uv[:, 1]
+    else:
+        g = np.arange(n_tiles)
+        side = int(round(np.sqrt(n_tiles)))
+        u = (g % side - (side - 1) / 2) / ((side - 1) / 2)
+        v = (g // side - (side - 1) / 2) / ((side - 1) / 2)
     return {"n": sizes, "n_bf": nbf, "background": bg, "u": u, "v": v}
 
 
-def uneven_batch(n_tiles=4096, photons=1e4, seed=2):
+def field_model_on_grid(u, v, side=64):
+    """The quadratic field model with the scale fitted on a side x side grid
+    of [-1, 1]^2 (max |c| = 1.5 rad there), evaluated at positions (u, v)."""
+    g = np.arange(side * side)
+    _, a = field_model_quadratic((g % side - (side - 1) / 2) / ((side - 1) / 2),
+                                 (g // side - (side - 1) / 2) / ((side - 1) / 2))
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    c = np.zeros(u.shape + (15,))
+    c[..., 3:15] = np.stack([np.ones_like(u), u, v, u * u, u * v, v * v], axis=-1) @ a.T
+    return c
+
+
+def uneven_batch(n_tiles=4096, photons=1e4, seed=2, background_fraction=0.4,
+                 random_positions=False, darkfield=True, seed_base=20):
     """The uneven batch as one Workload per geometry class (in the order of
     ``uneven_classes``), each with the batch-wide indices of its tiles in
     ``extra["tiles"]`` and its background flags in ``extra["background"]``.
-    True pupils follow the quadratic field model at each tile's grid position."""
+    True pupils follow the quadratic field model at each tile's position,
+    scaled on the batch's own grid (random positions: on the 64 x 64 grid of
+    the 4096-tile batch).  ``darkfield=False``
+    drops the darkfield images (a training set for the surrogate, whose inputs
+    and labels come from the NA-matched images only); ``seed_base`` gives the
+    classes' object and noise seeds (seed_base + class)."""
     classes = uneven_classes()
-    tiles = uneven_tiles(n_tiles, seed)
-    c_all, _ = field_model_quadratic(tiles["u"], tiles["v"])
+    tiles = uneven_tiles(n_tiles, seed, background_fraction, random_positions)
+    if random_positions:
+        c_all = field_model_on_grid(tiles["u"], tiles["v"])
+    else:
+        c_all, _ = field_model_quadratic(tiles["u"], tiles["v"])
     out = []
     for ci, g in enumerate(classes):
         sel = np.nonzero((tiles["n"] == g["n"]) & (tiles["n_bf"] == g["n_bf"]))[0]
         if len(sel) == 0:
             continue
-        out.append(Workload(f"uneven-{g['n']}-{g['n_bf']}", g["n"], g["k_bf"], g["k_df"],
-                            upsample=2, n_tiles=len(sel), photons=photons, seed_id=20 + ci,
-                            coeffs=c_all[sel],
+        out.append(Workload(f"uneven-{g['n']}-{g['n_bf']}", g["n"], g["k_bf"],
+                            g["k_df"] if darkfield else [],
+                            upsample=2, n_tiles=len(sel), photons=photons,
+                            seed_id=seed_base + ci, coeffs=c_all[sel],
                             positions=np.stack([tiles["u"][sel], tiles["v"][sel]], axis=1),
                             extra={"tiles": sel, "background": tiles["background"][sel],
                                    "class": ci}))
     return out
+
+
+def surrogate_train_batch(n_tiles=16384):
+    """Training set of the learned-surrogate workload: content tiles of the
+    uneven recipe (no background), NA-matched images only, at uniform random
+    field positions; objects and noise from their own seeds (classes 40..48),
+    so the set is disjoint from the evaluation set."""
+    return uneven_batch(n_tiles, seed=5, background_fraction=0.0, random_positions=True,
+                        darkfield=False, seed_base=40)
+
+
+def surrogate_eval_batch(n_tiles=4096):
+    """Evaluation set of the learned-surrogate workload: the uneven recipe with
+    70% background tiles and all darkfield images, on the 64 x 64 grid
+    (classes 60..68)."""
+    return uneven_batch(n_tiles, seed=6, background_fraction=0.7, seed_base=60)

@@ -37,6 +37,19 @@ background tiles, nine geometry classes run concurrently in chunks that fit
 and 0.47 um; 256 px tiles, 8 NA-matched + 16 darkfield LEDs per channel) as
 one batch of three geometry classes, then the colour combination.
 
+``--workload surrogate`` runs the learned surrogate's own workload: the
+surrogate is trained on the closed-form estimates (coarse-to-fine
+continuation) of 16384 content tiles of the uneven recipe (nine classes,
+NA-matched images only, uniform random field positions; labels whose
+linearised residual exceeds 1 rad^2 are left out), then the 4096-tile
+uneven batch with 70% background tiles and all darkfield images runs twice:
+closed form only, and with the surrogate and its fallback rule (the closed
+form replaces the surrogate where the surrogate's residual exceeds the closed
+form's by more than 0.05 rad and the closed form is trustworthy).  The line's
+value is the pupil RMSE against the truth of the chosen coefficients; beside
+it the closed form's, the surrogate's alone, each split into background and
+content tiles, and both passes' output rates.
+
 ``--workload slide`` streams a slide: 512 px tiles (16 + 32 images) whose image
 stacks sit in pinned host memory, reconstructed in chunks through device
 staging buffers on several streams, background tiles skipped by their
@@ -45,7 +58,7 @@ fallback.  The rate is host wall-clock including the host-device copies; the
 sample is the first ``--tiles`` scanned tiles of the raster order (default
 256).
 
-    python bench.py [--steps K] [--warmup W] [--workload grid|uneven|slide|rgb] [--tiles T]
+    python bench.py [--steps K] [--warmup W] [--workload grid|uneven|slide|rgb|surrogate] [--tiles T]
                     [--no-autotune] [--no-surrogate] [--no-cpu-baseline] [--no-extra]
 
 Prints one JSON line.  Only one GPU is supported.
@@ -565,13 +578,150 @@ def uneven_block(dev, ws_gb, warmup=1, steps=1):
     return rec
 
 
+def surrogate_workload(args, dev):
+    """The learned surrogate's workload (see the module docstring).  Returns
+    the JSON record."""
+    import numpy as np
+    import torch
+    import apic_synth as S
+    from apic_synth.batch import synth_batch
+    from paper_2407_20469_amd import apic
+    t_start = time.time()
+    # training: the closed-form estimates of the training tiles, class by class
+    # a label is kept when the closed form trusts itself by the fallback rule's
+    # own bound: its linearised residual R(c) at most resid_max = 1 rad^2
+    xs, ys, rs, lab_err = [], [], [], []
+    tr = S.surrogate_train_batch(args.train_tiles)
+    for w in tr:
+        imgs = synth_batch(w, dev)
+        plan = apic.Plan(w.geometry_kwargs())
+        z, diag, feat, _ = apic.estimate_pupil(plan, imgs)
+        del imgs
+        plan.close()
+        pos = torch.tensor(w.positions, dtype=torch.float32, device=dev)
+        xs.append(torch.cat([pos, feat], dim=1))
+        ys.append(z[:, 3:15])
+        rs.append(diag[:, 0])
+        lab_err.append(z.cpu().numpy()[:, 3:15] - w.coeffs[:, 3:15])
+        log(f"training labels: class {w.name}, {w.n_tiles} tiles")
+    torch.cuda.empty_cache()
+    x, y, resid = torch.cat(xs), torch.cat(ys), torch.cat(rs)
+    ok = torch.isfinite(x).all(1) & torch.isfinite(y).all(1) & (resid <= 1.0)
+    lab_err = np.concatenate(lab_err)
+    ok_np = ok.cpu().numpy()
+    t_lab = time.time() - t_start
+    t0 = time.time()
+    sur, l0, l1 = fit_surrogate(x[ok].contiguous(), y[ok].contiguous(), seed=47,
+                                epochs=args.epochs)
+    torch.cuda.synchronize()
+    t_fit = time.time() - t0
+    log(f"surrogate: labels {t_lab:.1f} s, fit {t_fit:.1f} s on {int(ok.sum())} of "
+        f"{len(ok_np)} tiles "
+        f"(loss {l0:.4f} -> {l1:.5f})")
+    del xs, ys, x, y
+
+    # evaluation: the uneven batch with 70% background, closed form, then with
+    # the surrogate and the fallback rule
+    ev = S.surrogate_eval_batch(args.tiles)
+    order = [w.extra["tiles"] for w in ev]
+    plan = apic.Plan([w.geometry_kwargs() for w in ev])
+    plan.upload()
+    descs, images, n_fld = synth_into(ev, order, plan, dev)
+    T = sum(w.n_tiles for w in ev)
+    truth, bg, pos = np.zeros((T, 15)), np.zeros(T, bool), np.zeros((T, 2))
+    for w, idx in zip(ev, order):
+        truth[idx], bg[idx], pos[idx] = w.coeffs, w.extra["background"], w.positions
+    pos_dev = torch.tensor(pos, dtype=torch.float32, device=dev)
+    mpx = sum(w.n_tiles * (w.n * w.upsample) ** 2 for w in ev) / 1e6
+    field = torch.empty(n_fld, dtype=torch.complex64, device=dev)
+    zern = torch.empty((T, 15), dtype=torch.float32, device=dev)
+    status = torch.empty((T,), dtype=torch.int32, device=dev)
+    batch = apic.Batch(plan, descs)
+    batch.fit(int(args.ws_gb * 2 ** 30))
+    ws = apic.Workspace()
+    stream = torch.cuda.current_stream()
+    cf_ms = timed_steps(lambda: batch.reconstruct(images, field, zern, status, ws), 1, stream)
+    z_cf = zern.cpu().numpy().astype(np.float64)
+    log(f"closed-form pass: {cf_ms / 1e3:.1f} s")
+    batch.set_surrogate(sur, pos_dev, rho_max=0.05, kappa_max=1e6, resid_max=1.0)
+    sur_ms = timed_steps(lambda: batch.reconstruct(images, field, zern, status, ws), 1, stream)
+    z_ch = zern.cpu().numpy().astype(np.float64)
+    st = status.cpu().numpy()
+    log(f"surrogate pass: {sur_ms / 1e3:.1f} s")
+    batch.close()
+    del field, ws
+    # the surrogate alone, from the features of each class's NA-matched images
+    z_sur = np.zeros((T, 15))
+    for w, idx in zip(ev, order):
+        per = w.n_img * w.n * w.n
+        stack = torch.stack([images[descs[int(b)].image_offset:descs[int(b)].image_offset + per]
+                             .view(w.n_img, w.n, w.n)[:w.n_bf] for b in idx])
+        pl = apic.Plan({**w.geometry_kwargs(), "k_df": np.zeros((0, 2), np.int64)})
+        _, _, feat, _ = apic.estimate_pupil(pl, stack)
+        pl.close()
+        del stack
+        z_sur[idx, 3:15] = sur.forward(torch.cat([pos_dev[idx], feat], dim=1)).cpu().numpy()
+    del images
+    torch.cuda.empty_cache()
+
+    def err(z, sel=None, ref=truth):
+        d = (z - ref)[:, 3:15]
+        if sel is not None:
+            d = d[sel]
+        return np.sqrt(np.sum(d * d, axis=1))
+
+    def rmse(z, sel=None, ref=truth):
+        return float(np.sqrt(np.mean(err(z, sel, ref) ** 2)))
+
+    split = {"all": None, "background": bg, "content": ~bg}
+    cands = (("chosen", z_ch), ("closed_form", z_cf), ("surrogate_alone", z_sur))
+    acc = {name: {k: rmse(z, sel) for k, sel in split.items()} for name, z in cands}
+    acc["surrogate_vs_closed_form"] = {k: rmse(z_sur, sel, z_cf) for k, sel in split.items()}
+    med = {name: {k: float(np.median(err(z, sel))) for k, sel in split.items()}
+           for name, z in cands}
+    kept = (st & apic.TILE_SURROGATE_USED) != 0
+    log(f"pupil RMSE vs truth: {acc}")
+    log(f"median error vs truth: {med}")
+    w_desc = (f"learned surrogate on uneven-recipe tiles: trained on the closed-form estimates "
+              f"of {args.train_tiles} content tiles (128/256/512 px 4:3:1, 8/12/16 NA-matched "
+              f"LEDs, random field positions, quadratic field model up to 1.5 rad, Poisson 1e4); "
+              f"evaluated on {T} tiles of the same recipe with 70% background and 2x darkfield "
+              f"images, fallback at 0.05 rad")
+    return {"metric": "pupil RMSE vs truth, surrogate with closed-form fallback",
+            "value": acc["chosen"]["all"], "unit": "rad", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 MLP (fp32 accumulate) + f32/f64 closed form", "data": "synthetic",
+            "config": {"workload": w_desc},
+            "accuracy_rad": acc,
+            "accuracy_note": "RMSE over tiles of the Noll 4..15 error norm; median_rad: the "
+                             "median of that norm",
+            "median_rad": med,
+            "label_rmse_vs_truth": {
+                "all": float(np.sqrt(np.mean(np.sum(lab_err ** 2, axis=1)))),
+                "kept": float(np.sqrt(np.mean(np.sum(lab_err[ok_np] ** 2, axis=1))))},
+            "training": {"tiles": int(ok.sum()), "of": int(len(ok_np)),
+                         "rule": "closed-form labels with R(c) <= 1 rad^2",
+                         "epochs": args.epochs, "loss_first": l0,
+                         "loss_last": l1, "labels_s": t_lab, "fit_s": t_fit},
+            "decisions": {"surrogate_kept": int(kept.sum()),
+                          "closed_form_kept": int(((st & apic.TILE_FALLBACK_USED) != 0).sum()),
+                          "surrogate_kept_background": int((kept & bg).sum()),
+                          "surrogate_kept_content": int((kept & ~bg).sum())},
+            "rate_Mpx_s": {"closed_form": mpx / (cf_ms * 1e-3),
+                           "with_surrogate": mpx / (sur_ms * 1e-3)},
+            "wall_s": time.time() - t_start}
+
+
 def main():
     t_start = time.time()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["grid", "uneven", "slide", "rgb"], default="grid")
+    ap.add_argument("--workload", choices=["grid", "uneven", "slide", "rgb", "surrogate"],
+                    default="grid")
+    ap.add_argument("--train-tiles", type=int, default=16384, help="surrogate: training tiles")
+    ap.add_argument("--epochs", type=int, default=150, help="surrogate: training epochs")
     ap.add_argument("--tiles", type=int, default=None)
     ap.add_argument("--ws-gb", type=float, default=128.0)
     ap.add_argument("--no-autotune", action="store_true")
@@ -590,7 +740,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.tiles is None:
-        args.tiles = {"grid": 1024, "uneven": 4096, "slide": 256, "rgb": 256}[args.workload]
+        args.tiles = {"grid": 1024, "uneven": 4096, "slide": 256, "rgb": 256,
+                      "surrogate": 4096}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the per-tile reconstruction has no "
               "cross-GPU step (tiles shard across GPUs without communication)",
@@ -614,6 +765,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "slide":
         return run_slide_stream(args, dev)
+    if args.workload == "surrogate":
+        print(json.dumps(surrogate_workload(args, dev)), flush=True)
+        return
     if args.workload == "grid":
         ws_list = [S.grid_batch(n_tiles=args.tiles)]
         order = [np.arange(ws_list[0].n_tiles)]
