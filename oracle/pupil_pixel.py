@@ -22,11 +22,18 @@ Readings taken (the paper names no solver):
   reported as 0).
 Here the normal matrix is formed densely and inverted on its range through its
 eigendecomposition (eigenvalues under 1e-10 of the largest count as null).
+For pupils too large for a dense normal matrix (512 px tiles: about 30,000
+pixels) the same minimum-norm solution is taken by LSQR on the weighted rows
+sqrt(w) D phi = sqrt(w) beta started from zero (scipy's LSQR, a library
+primitive: its iterates stay in the range of D^T, so it ends at the
+minimum-norm least-squares solution); the tests pin the two routes to each
+other on the smaller geometries.
 """
 
 import numpy as np
 import scipy.linalg
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .aberration import pupil_pairs
 from .grid import fft_index
@@ -74,24 +81,36 @@ def pixel_system(spectra, k_bf, r):
     return D, np.concatenate(betas), np.concatenate(ws), (pky, pkx)
 
 
-def solve_pixel_pupil(spectra, k_bf, r, null_rel=1e-10):
+def solve_pixel_pupil(spectra, k_bf, r, null_rel=1e-10, method="eig", tol=1e-13,
+                      iter_lim=200000):
     """Eq. 10 on the pupil pixels.  Returns dict with phi (N_p,), the pixel
     coordinates, phi_map (N, N) in FFT order (0 outside the pupil), c (15,)
-    the Zernike summary and the null-space dimension found."""
+    the Zernike summary and the null-space dimension found (eig) or the LSQR
+    iterations taken (lsqr, where null_dim is None)."""
     n = spectra.shape[-1]
     D, beta, w, (pky, pkx) = pixel_system(spectra, k_bf, r)
-    Dw = D.multiply(w[:, None]).tocsr()
-    A = (D.T @ Dw).toarray()
-    rhs = D.T @ (w * beta)
-    ev, U = scipy.linalg.eigh(A)
-    keep = ev > null_rel * ev.max()
-    phi = U[:, keep] @ ((U[:, keep].T @ rhs) / ev[keep])
+    null_dim, iters = None, None
+    if method == "eig":
+        Dw = D.multiply(w[:, None]).tocsr()
+        A = (D.T @ Dw).toarray()
+        rhs = D.T @ (w * beta)
+        ev, U = scipy.linalg.eigh(A)
+        keep = ev > null_rel * ev.max()
+        phi = U[:, keep] @ ((U[:, keep].T @ rhs) / ev[keep])
+        null_dim = int((~keep).sum())
+    elif method == "lsqr":
+        sw = np.sqrt(w)
+        out = spla.lsqr(D.multiply(sw[:, None]).tocsr(), sw * beta, atol=tol, btol=tol,
+                        conlim=1e12, iter_lim=iter_lim)
+        phi, iters = out[0], int(out[2])
+    else:
+        raise ValueError(method)
     phi_map = np.zeros((n, n))
     yy, xx = fft_index(pky, pkx, n)
     phi_map[yy, xx] = phi
     return {"phi": phi, "ky": pky, "kx": pkx, "phi_map": phi_map,
             "c": zernike_summary(phi, pky, pkx, r), "rows": D.shape[0],
-            "null_dim": int((~keep).sum())}
+            "null_dim": null_dim, "iters": iters}
 
 
 def zernike_summary(phi, pky, pkx, r):

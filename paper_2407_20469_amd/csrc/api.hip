@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <complex>
 #include <cmath>
 #include <cstring>
@@ -373,6 +374,44 @@ apic_status run_pupil(const ClassArgs &a, const float *caller_seed, float *zout,
   return pupil_pass(a, caller_seed, src, 1, false, zout, diag, feat, st);
 }
 
+// Pixel-domain solve beyond the LDS bound: CG with its vectors in the
+// workspace, each iteration a many-workgroup row pass and a per-tile step;
+// every kPixPoll iterations the host reads the number of live tiles and stops
+// when none is left (the call blocks the host there).
+constexpr int kPixPoll = 32;
+static apic_status run_pixel_wide(const ClassArgs &a, double tol, int max_iter, float *phi_out,
+                                  float *zout, int32_t *iters_out, hipStream_t st) {
+  const int wgs = std::max(1, (a.n_rows + 4 * kPixgRowsPerWave - 1) / (4 * kPixgRowsPerWave));
+  hipLaunchKernelGGL(k_pixg_clear, dim3(blocks_for(a.n_pix, 256), a.T), dim3(256), 0, st, a);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_pixg_apply, dim3((unsigned)(a.T * wgs)), dim3(256), 0, st, a, 1, wgs);
+  APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_pixg_init, dim3(a.T), dim3(kPixThreads), 0, st, a, tol);
+  APIC_LAUNCHED();
+  const void *active_dev =
+      a.ws + a.lay.gram + pixg_vec_off(a.n_rows, a.n_pix, 4) + offsetof(PixState, active);
+  for (int it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL(k_pixg_apply, dim3((unsigned)(a.T * wgs)), dim3(256), 0, st, a, 0, wgs);
+    APIC_LAUNCHED();
+    hipLaunchKernelGGL(k_pixg_step, dim3(a.T), dim3(kPixThreads), 0, st, a, max_iter);
+    APIC_LAUNCHED();
+    if (it % kPixPoll == 0 && it < max_iter) {
+      hipLaunchKernelGGL(k_pixg_count, dim3(1), dim3(256), 0, st, a);
+      APIC_LAUNCHED();
+      int active = 0;
+      if (hipMemcpyAsync(&active, active_dev, sizeof(int), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return APIC_EHIP;
+      if (active == 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_pixg_finish, dim3(a.T), dim3(kPixThreads), 0, st, a, phi_out, zout,
+                     iters_out);
+  APIC_LAUNCHED();
+  return APIC_OK;
+}
+
 apic_status run_stitch(const ClassArgs &a, int64_t n_disk, float *spec_out, hipStream_t st) {
   // bytes: each KK spectrum read on its support, O_hat written
   ProfScope ps(APIC_PROF_STITCH, (double)a.T * 8.0 * ((double)a.n_bf * n_disk + a.n * a.n), st);
@@ -576,9 +615,14 @@ apic_status run_class_n(const apic_plan *p, const ClassRun &r, const ClassArgs &
     ap.row_k = (const uint32_t *)p->geoms[r.geom].d_prow_k;
     hipLaunchKernelGGL(k_pix_rows, dim3(ap.T * ap.n_chunks), dim3(256), 0, st, ap);
     APIC_LAUNCHED();
-    hipLaunchKernelGGL(k_pix_cg, dim3(ap.T), dim3(kPixThreads), 0, st, ap, io.pix_tol,
-                       io.pix_max_iter, io.phi_out, io.zout, io.pix_iters);
-    APIC_LAUNCHED();
+    if (ap.n_pix <= kPixMax) {
+      hipLaunchKernelGGL(k_pix_cg, dim3(ap.T), dim3(kPixThreads), 0, st, ap, io.pix_tol,
+                         io.pix_max_iter, io.phi_out, io.zout, io.pix_iters);
+      APIC_LAUNCHED();
+    } else {
+      rc = run_pixel_wide(ap, io.pix_tol, io.pix_max_iter, io.phi_out, io.zout, io.pix_iters, st);
+      if (rc) return rc;
+    }
   }
   if (st_mask & S_SUR) {
     if (!sur_seeds) {

@@ -89,7 +89,7 @@ static void build_pixel_tables(GeomPlan &p, int n_bf) {
         pix.push_back(pack_k(ky, kx));
       }
   p.n_pix = int(pix.size());
-  p.pix_ok = p.n_pix <= kPixMax && p.n_rows > 0;
+  p.pix_ok = p.n_pix <= kPixIdxMax && p.n_rows > 0;
   p.pix_tab.clear();
   p.pix_ginv.clear();
   if (!p.pix_ok) return;
@@ -451,8 +451,13 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.vec = take(int64_t(p.nu_pad) * c64);
   // the gram block also serves the pixel-domain pupil solve (a separate call):
   // per-row weights and phases (float) and two double vectors over the pixels
+  // (the iterate and the residual); beyond the LDS bound also the search
+  // direction, the operator's image and the per-tile iteration state
+  const int64_t pix_vecs = p.n_pix > kPixMax ? 4 : 2;
   const int64_t pix_need =
-      p.pix_ok ? 2 * align256(int64_t(p.n_rows) * 4) + 2 * align256(int64_t(p.n_pix) * 8) : 0;
+      p.pix_ok ? 2 * align256(int64_t(p.n_rows) * 4) +
+                     pix_vecs * align256(int64_t(p.n_pix) * 8) + (p.n_pix > kPixMax ? 256 : 0)
+               : 0;
   L.gram = take(std::max<int64_t>(p.n_active ? int64_t(p.nu_pad) * p.nu_pad * c64 : 256, pix_need));
   L.linv = take(int64_t(p.nu_pad / kGramBlock) * kGramBlock * kGramBlock * c64);
   L.part = take(int64_t(p.n_chunks) * kAbEntries * 8);

@@ -21,7 +21,8 @@ constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
 constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
 constexpr int kEChunk = 1;          // E rows per bit of the gram's block masks
-constexpr int kPixMax = 7936;       // pupil pixels of the pixel-domain solve (LDS bound)
+constexpr int kPixMax = 7936;       // pupil pixels of the one-workgroup pixel solve (LDS bound)
+constexpr int kPixIdxMax = 65536;   // pupil pixels of the pixel solve (16-bit pixel indices)
 // Coarse-to-fine continuation of the pupil solve: bands |K| <= f r for these
 // f, each band used when it holds at least kMinBandRows rows.
 constexpr int kPupilBands = 6;
@@ -81,7 +82,7 @@ struct GeomPlan {
   // of the pixel-domain solve, whose passes sum each pair's rows in one run
   std::vector<uint32_t> prow_il, prow_k;
   // pupil pixels (Eq. 10 with one unknown per pixel), raster order over the
-  // disk (ky ascending, then kx): built when n_pix <= kPixMax.  pix_tab holds
+  // disk (ky ascending, then kx): built when n_pix <= kPixIdxMax.  pix_tab holds
   // the pixels' packed k, then per pupil row (in pair order, prow_*) the pixel
   // indices of K + K_i (low half) and K + K_l (high half), then the pixel index of each
   // NA-matched k_i.  pix_ginv is the inverse Gram matrix of Noll Z_1..Z_15 over

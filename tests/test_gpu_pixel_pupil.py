@@ -12,8 +12,9 @@ pixel system amplifies by at most its condition number on the range (about
 Bars: phi within 1e-4 rad at every pixel and 1e-5 rad RMS (observed: at
 most 3e-6 and 2.5e-7); the Zernike summary within 1e-3 rad (the contract's
 pupil bar; observed 2e-8); exact zeros outside the pupil.  Cases: 64 px / 8 LEDs, 128 px / 8 LEDs (a checkerboard joins the null
-space), 128 px / 16 LEDs with Poisson noise, and the 256 px / 16 LED
-geometry of the 1024-tile benchmark.
+space), 128 px / 16 LEDs with Poisson noise, the 256 px / 16 LED geometry of
+the 1024-tile benchmark, and the 512 px slide geometry (the many-workgroup
+path, against the oracle's LSQR route).
 """
 
 import numpy as np
@@ -92,6 +93,66 @@ def test_pixel_pupil_benchmark_geometry():
     assert not (st[0] & apic.TILE_PIXEL_NOT_CONVERGED)
     assert np.abs(d).max() < 1e-4 and rms < 1e-5
     assert np.abs(z[0] - ref["c"]).max() < 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_pixel_pupil_512_slide_geometry():
+    """Two tissue tiles of the 512 px slide geometry (16 NA-matched + 32
+    darkfield LEDs; 30,461 pupil pixels, 930,336 rows): beyond the LDS bound,
+    so the CG vectors live in the workspace and each row pass spreads over
+    many workgroups.  Tile 0 against the oracle's LSQR route (the dense
+    normal matrix would be 7 GB); tile 1 run alone equals tile 1 of the pair
+    (the per-tile state is per tile; the FP64 atomics of the row passes add in
+    any order and phi is returned in float32, hence a 1e-6 rad bar, a few
+    float32 steps, instead of bit equality).
+
+    The 512 px pixel system is near-singular in a few directions: on the CPU,
+    a random relative perturbation of 2e-5 of the oracle's FP64 spectra (the
+    level at which the FP32 KK spectra agree with them) moves the oracle's own
+    solution by up to 0.33 rad at one pixel, 1.9e-3 rad RMS and 2.4e-5 rad in
+    the Zernike summary.  Bars, against that: phi within 1e-3 rad RMS and
+    0.05 rad at every pixel (a wrong row, sign or shift gives tenths of a
+    radian RMS), the Zernike summary within 1e-3 rad (observed: 5.5e-5 RMS,
+    9.3e-3 max, 5.6e-7)."""
+    from apic_synth import slide
+    from apic_synth.batch import synth_batch
+    w = slide.pool_workload(2, 1)
+    imgs = synth_batch(w, torch.device(DEV), tiles=[0, 1])
+    plan = apic.Plan(w.geometry_kwargs())
+    _log("512 px slide geometry, two tiles, tol 1e-12")
+    phi, z, iters, st = apic.estimate_pupil_pixel(plan, imgs, tol=1e-12, max_iter=20000)
+    phi1, z1, _, _ = apic.estimate_pupil_pixel(plan, imgs[1:].contiguous(), tol=1e-12,
+                                               max_iter=20000)
+    phi, z, iters, st, phi1 = (x.cpu().numpy() for x in (phi, z, iters, st, phi1))
+    assert np.abs(phi[1] - phi1[0]).max() < 1e-6
+    host = imgs[0, :w.n_bf].cpu().numpy().astype(np.float64)
+    k_bf = np.asarray(w.k_bf, np.int64)
+    spectra = np.stack([oracle.kk_spectrum(host[i], k_bf[i], w.r) for i in range(w.n_bf)])
+    ref = solve_pixel_pupil(spectra, k_bf, w.r, method="lsqr", tol=1e-13)
+    d = phi[0] - ref["phi_map"]
+    inside = circ(*k_grid(w.n), w.r)
+    rms = float(np.sqrt(np.mean(d[inside] ** 2)))
+    _log(f"  {iters[0]}, {iters[1]} iterations (oracle LSQR {ref['iters']}), "
+         f"max |dphi| {np.abs(d).max():.2e}, rms {rms:.2e}, "
+         f"max |dc| {np.abs(z[0] - ref['c']).max():.2e}")
+    assert not (st[0] & apic.TILE_PIXEL_NOT_CONVERGED)
+    assert not (st[1] & apic.TILE_PIXEL_NOT_CONVERGED)
+    assert np.all(phi[0][~inside] == 0)
+    assert np.abs(d).max() < 0.05 and rms < 1e-3
+    assert np.abs(z[0] - ref["c"]).max() < 1e-3
+
+
+def test_pixel_pupil_iteration_cap_at_512():
+    """The many-workgroup path stops at max_iter, also across a host poll."""
+    from apic_synth import slide
+    from apic_synth.batch import synth_batch
+    w = slide.pool_workload(2, 1)
+    imgs = synth_batch(w, torch.device(DEV), tiles=[0])
+    plan = apic.Plan(w.geometry_kwargs())
+    for cap in (3, 40):
+        _, _, iters, st = apic.estimate_pupil_pixel(plan, imgs, max_iter=cap)
+        assert int(iters.cpu()[0]) == cap
+        assert int(st.cpu()[0]) & apic.TILE_PIXEL_NOT_CONVERGED
 
 
 def test_pixel_pupil_iteration_cap_sets_status():

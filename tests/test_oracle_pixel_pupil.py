@@ -121,3 +121,19 @@ def test_zernike_phase_matches_zernike_basis_solve():
     assert np.abs(pix["c"] - c_true).max() < 1e-8
     assert np.abs(zb["c"] - c_true).max() < 1e-8
     assert np.all(pix["c"][:3] == 0)
+
+
+@pytest.mark.parametrize("n,count", [(64, 8), (128, 8), (128, 16)])
+def test_lsqr_route_equals_eigendecomposition_route(n, count):
+    """The LSQR route (for pupils too large for a dense normal matrix) reaches
+    the same minimum-norm solution as the eigendecomposition on the range,
+    also where the checkerboard joins the null space (128 px / 8 LEDs), on
+    noisy spectra whose rows are inconsistent."""
+    n, r, k_bf = _geometry(n, count)
+    rng = np.random.default_rng([n, count, 7])
+    s = _spectra(n, r, k_bf, lambda ky, kx: 0.3 * np.sin(0.2 * kx) + 0.01 * ky * ky / r)
+    s = s * np.exp(1j * rng.normal(0, 0.05, s.shape)) * (s != 0)
+    a = solve_pixel_pupil(s, k_bf, r)
+    b = solve_pixel_pupil(s, k_bf, r, method="lsqr")
+    assert np.abs(a["phi"] - b["phi"]).max() < 1e-7
+    assert np.abs(a["c"] - b["c"]).max() < 1e-9
