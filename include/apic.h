@@ -231,8 +231,9 @@ apic_status apic_estimate_pupil(const apic_plan *plan, int32_t n_tiles,
  *   zernike_out  float [T][15]: least-squares fit of Noll Z_1..Z_15 to phi
  *                over the pupil pixels, c_1..c_3 reported as 0
  *   iters_out    int32 [T] or NULL: iterations taken
- * Single-geometry plans with at most 65536 pupil pixels (N <= 1024 at these
- * optics); APIC_EUNSUPPORTED otherwise.  Up to 7936 pupil pixels (N <= 256)
+ * Single-geometry plans (APIC_EUNSUPPORTED otherwise); every valid plan's
+ * pupil (4r < N, N fN <= 1024) stays under the 65536 pupil pixels the
+ * tables' 16-bit indices allow.  Up to 7936 pupil pixels (N <= 256)
  * one workgroup per tile holds the CG vectors in LDS; beyond that the
  * vectors stay in the workspace, the row passes are spread over many
  * workgroups per tile (FP64 atomics in L2), and the call waits on the host

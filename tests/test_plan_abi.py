@@ -151,9 +151,11 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     rc = lib.apic_estimate_pupil_pixel(plan.handle, 2, descs, fake, 1e-10, 0, fake, fake, None,
                                        fake, fake, need, None)
     assert rc == apic.APIC_EINVAL
-    big = S.small_workload(n=512, n_df=0)
-    plan512 = apic.Plan(big.geometry_kwargs())
-    rc = lib.apic_estimate_pupil_pixel(plan512.handle, 2, descs, fake, 1e-10, 100, fake, fake,
+    # a plan of several geometry classes is refused (one class per call); a
+    # valid plan's pupil (r < N/4, N <= 512) stays under the 65536-pixel limit
+    two = apic.Plan([S.small_workload(n=64).geometry_kwargs(),
+                     S.small_workload(n=128).geometry_kwargs()])
+    rc = lib.apic_estimate_pupil_pixel(two.handle, 2, descs, fake, 1e-10, 100, fake, fake,
                                        None, fake, fake, need, None)
     assert rc == apic.APIC_EUNSUPPORTED
     # assembly: layout arguments, bad handle, ramp width >= 1
