@@ -905,13 +905,13 @@ def main():
 
     # gram work per step: nonzero products of the E-sum (the algorithmic
     # count), the dense E-sum, and the products the kernels issue (live
-    # (block pair, E chunk) triples x chunk x block^2 complex MACs)
+    # (16 x 16 quadrant of a block pair, E row) pairs x 16^2 complex MACs)
     gram_exec = gram_dense = gram_nz = 0.0
     for ci, w in enumerate(ws_list):
         steps_tab = plan.query(6, ci).reshape(-1, 5).astype(np.float64)
         sz = plan.sizes(ci)
-        gram_exec += (w.n_tiles * steps_tab[:, 3].sum() * sz["gram_chunk"] * sz["gram_block"] ** 2
-                      * 8.0)
+        gram_exec += (w.n_tiles * steps_tab[:, 3].sum() * sz["gram_chunk"]
+                      * (sz["gram_block"] // 2) ** 2 * 8.0)
         gram_nz += w.n_tiles * gram_nonzero_flops(plan, ci)
     groups = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
                   "work_per_step": v[2] / args.steps} for k, v in prof.items()}

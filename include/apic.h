@@ -161,8 +161,10 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *             pupil_bands is 0)
  *          5: sizes: n_pairs, n_rows, nu_max, m_max, ne_max, n_active_steps,
  *             unknowns per gram block, E rows per gram chunk, pupil pixels
- *          6: per darkfield step (N_u, |Q|, |E|, live gram chunks of all lower
- *             block pairs, live gram chunks of the diagonal blocks); U and E
+ *          6: per darkfield step (N_u, |Q|, |E|, live gram work of all lower
+ *             block pairs, of the diagonal blocks), the work counted in
+ *             (16 x 16 quadrant, excluded k) pairs, i.e. in units of 256
+ *             complex MACs: the products the gram issues; U and E
  *             are in the plan's processing order (compact squares), P and Q
  *             in FFT raster order */
 apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,

@@ -161,20 +161,27 @@ __global__ __launch_bounds__(256) void k_df_rhs_gather(ClassArgs a, StepArgs s) 
 // LDS row read consecutive elements (no bank conflicts).
 //
 // A product P_hat(u + k) conj(P_hat(u' + k)) is nonzero only when both u + k
-// and u' + k fall in P, so the E-sum is sparse.  A plan mask per block of
-// unknowns marks the excluded k for which some unknown of the block lands in
-// P; a block pair visits the k marked for both blocks, in ascending order,
-// walking the mask words with wave-uniform state, two k per iteration.  Each
-// lane gathers one operand element per iteration (its unknown u of each
-// block, its k of the two); a lane without an element reads a grid position
-// that is never in P (the point opposite the support's centre), where P_hat
-// is zero, so every lane loads unconditionally.  Software pipeline: while the
-// current two k are multiplied from LDS, the operands of the next two are in
-// flight and the two after those are being looked up in E.  A diagonal block
+// and u' + k fall in P, so the E-sum is sparse.  A plan mask per half-block
+// (16 unknowns) marks the excluded k for which some unknown of the half lands
+// in P; a block pair visits the k marked in a half of each block, in
+// ascending order, walking the mask words with wave-uniform state, two k per
+// iteration (four k).  Every lane holds part of each 16 x 16 quadrant (rows ty + 8 i
+// lie in half i / 2, columns tx + 8 j in half j / 2), so for each k the wave
+// skips, with a uniform branch, the quadrants whose two halves do not both
+// mark it: a quarter of the multiply-adds per quadrant.  Each
+// lane gathers two operand elements per iteration (its unknown u of each
+// block, for two of the four k); a lane without an element reads a grid
+// position that is never in P (the point opposite the support's centre),
+// where P_hat is zero, so every lane loads unconditionally.  Software
+// pipeline: while the current four k are multiplied from LDS, the operands of
+// the next four are in flight and the four after those are being looked up in
+// E.  Four k per iteration (not two) give each wave twice the multiply-adds
+// per gather latency, which the four waves per SIMD did not hide.  A diagonal block
 // has one operand and is formed whole (its upper half is not read by the
 // Cholesky).
-constexpr int kGramRows = 2;  // excluded k per iteration
-static_assert(kGramRows * kGramUB == 64, "one gathered element per lane and iteration");
+constexpr int kGramRows = 4;                          // excluded k per iteration
+constexpr int kGramSlots = kGramRows * kGramUB / 64;  // gathers per lane and iteration
+static_assert(kGramSlots * 64 == kGramRows * kGramUB, "the lanes cover the gathers exactly");
 constexpr uint32_t kNoK = 0x7fff7fffu;  // padding: outside every support
 __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   const int nb = (s.nu + kGramUB - 1) / kGramUB;
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
   __shared__ uint32_t su[2][kGramUB];
   const int lane = threadIdx.x;
   const int ty = lane >> 3, tx = lane & 7;
-  const int uu = lane & (kGramUB - 1), kk = lane / kGramUB;  // this lane's gather slot
+  const int uu = lane & (kGramUB - 1), kk = lane / kGramUB;  // slot sl: k row kk + 2 sl
   const int ui = I * kGramUB + uu, uj = J * kGramUB + uu;
   const uint32_t wa = ui < s.nu ? s.u[ui] : kNoK;
   const uint32_t wb = uj < s.nu ? s.u[uj] : kNoK;
@@ -206,34 +213,57 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     su[1][lane] = wb;
   }
   const int ay = kunpack_y(wa), ax = kunpack_x(wa), by = kunpack_y(wb), bx = kunpack_x(wb);
-  // marked k in ascending order, walked with wave-uniform state
-  const uint64_t *mi = s.gmask + (int64_t)I * s.nwe, *mj = s.gmask + (int64_t)J * s.nwe;
+  // marked k in ascending order, walked with wave-uniform state: each step
+  // returns the E row in the low 24 bits and the live quadrants (bit 2 hi +
+  // hj: row half hi, column half hj) above them
+  const uint64_t *ma0 = s.gmask + (int64_t)(2 * I) * s.nwe, *ma1 = ma0 + s.nwe;
+  const uint64_t *mb0 = s.gmask + (int64_t)(2 * J) * s.nwe, *mb1 = mb0 + s.nwe;
   int mw = 0;
-  uint64_t bits = s.nwe > 0 ? (mi[0] & mj[0]) : 0;
+  uint64_t w00 = 0, w01 = 0, w10 = 0, w11 = 0, bits = 0;
+  auto load_word = [&]() {
+    const uint64_t a0 = ma0[mw], a1 = ma1[mw], b0 = mb0[mw], b1 = mb1[mw];
+    w00 = a0 & b0;
+    w01 = a0 & b1;
+    w10 = a1 & b0;
+    w11 = a1 & b1;
+    bits = w00 | w01 | w10 | w11;
+  };
+  if (s.nwe > 0) load_word();
   auto next_k = [&]() -> int {
     while (bits == 0) {
       if (++mw >= s.nwe) return -1;
-      bits = mi[mw] & mj[mw];
+      load_word();
     }
-    const int c = mw * 64 + __builtin_ctzll(bits);
+    const int p = __builtin_ctzll(bits);
     bits &= bits - 1;
-    return c;
+    const int q = (int)((w00 >> p) & 1) | (int)(((w01 >> p) & 1) << 1) |
+                  (int)(((w10 >> p) & 1) << 2) | (int)(((w11 >> p) & 1) << 3);
+    return (mw * 64 + p) | (q << 24);
   };
-  // this lane's excluded k of a pair of E rows (kNoK for a missing row)
-  auto k_of = [&](int r0, int r1) -> uint32_t {
-    const int r = kk ? r1 : r0;
-    return r >= 0 ? s.e[r] : kNoK;
+  constexpr int kRowMask = (1 << 24) - 1;
+  // this lane's excluded k of slot sl among four E rows (kNoK for a missing row)
+  auto k_of = [&](const int (&rr)[kGramRows], int sl) -> uint32_t {
+    const int r = kk ? rr[2 * sl + 1] : rr[2 * sl];
+    return r >= 0 ? s.e[r & kRowMask] : kNoK;
   };
-  auto gather = [&](uint32_t kw, c64 &pa, c64 &pb) {
+  // this lane's operand elements of one k: P_hat(u_a + k), P_hat(u_b + k)
+  // (the second only off the diagonal)
+  struct Ops {
+    c64 a, b;
+  };
+  auto gather = [&](uint32_t kw) -> Ops {
     const bool kv = kw != kNoK;
     const int ky = kunpack_y(kw), kx = kunpack_x(kw);
     const int ia = (kv && wa != kNoK) ? fft_pos(ay + ky, a.n) * a.n + fft_pos(ax + kx, a.n) : zpos;
-    pa = phat[ia];
+    Ops o;
+    o.a = phat[ia];
+    o.b = make_double2(0.0, 0.0);
     if (!diag) {
       const int ib =
           (kv && wb != kNoK) ? fft_pos(by + ky, a.n) * a.n + fft_pos(bx + kx, a.n) : zpos;
-      pb = phat[ib];
+      o.b = phat[ib];
     }
+    return o;
   };
   c64 acc[4][4];
 #pragma unroll
@@ -241,43 +271,60 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
   __syncthreads();
-  int cur0 = next_k();
-  int cur1 = cur0 >= 0 ? next_k() : -1;
-  int nxt0 = cur1 >= 0 ? next_k() : -1;
-  int nxt1 = nxt0 >= 0 ? next_k() : -1;
-  c64 pa, pb = make_double2(0.0, 0.0);
-  gather(k_of(cur0, cur1), pa, pb);
-  uint32_t kw_nxt = k_of(nxt0, nxt1);
+  int cur[kGramRows], nxt[kGramRows];
+#pragma unroll
+  for (int r = 0; r < kGramRows; ++r) cur[r] = next_k();
+#pragma unroll
+  for (int r = 0; r < kGramRows; ++r) nxt[r] = next_k();
+  static_assert(kGramSlots == 2, "two gathers per lane and iteration");
+  Ops g0 = gather(k_of(cur, 0)), g1 = gather(k_of(cur, 1));
+  uint32_t kw_nxt0 = k_of(nxt, 0), kw_nxt1 = k_of(nxt, 1);
   const c64(*sBd)[kGramUB] = diag ? sA : sB;  // the column operand
-  while (cur0 >= 0) {
-    sA[kk][uu] = pa;
-    if (!diag) sB[kk][uu] = pb;
+  while (cur[0] >= 0) {
+    sA[kk][uu] = g0.a;
+    sA[kk + 2][uu] = g1.a;
+    if (!diag) {
+      sB[kk][uu] = g0.b;
+      sB[kk + 2][uu] = g1.b;
+    }
     __syncthreads();
-    const int nn0 = nxt1 >= 0 ? next_k() : -1;
-    const int nn1 = nn0 >= 0 ? next_k() : -1;
-    const uint32_t kw_nn = k_of(nn0, nn1);
-    gather(kw_nxt, pa, pb);
-    const int rows = cur1 >= 0 ? 2 : 1;
-    for (int r = 0; r < rows; ++r) {
+    int nn[kGramRows];
+#pragma unroll
+    for (int r = 0; r < kGramRows; ++r) nn[r] = next_k();  // -1 once the walk has ended
+    const uint32_t kw_nn0 = k_of(nn, 0), kw_nn1 = k_of(nn, 1);
+    g0 = gather(kw_nxt0);
+    g1 = gather(kw_nxt1);
+#pragma unroll
+    for (int r = 0; r < kGramRows; ++r) {
+      if (cur[r] < 0) break;  // wave-uniform; the rows in use are a prefix
+      const int quad = cur[r] >> 24;
       c64 av[4], bv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) av[i] = sA[r][ty + 8 * i];
 #pragma unroll
       for (int j = 0; j < 4; ++j) bv[j] = sBd[r][tx + 8 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int hi = 0; hi < 2; ++hi)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // acc += a * conj(b)
-          acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
-          acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
+        for (int hj = 0; hj < 2; ++hj) {
+          if (!(quad & (1 << (2 * hi + hj)))) continue;  // wave-uniform
+#pragma unroll
+          for (int i = 2 * hi; i < 2 * hi + 2; ++i)
+#pragma unroll
+            for (int j = 2 * hj; j < 2 * hj + 2; ++j) {  // acc += a * conj(b)
+              acc[i][j].x = fma(av[i].x, bv[j].x, fma(av[i].y, bv[j].y, acc[i][j].x));
+              acc[i][j].y = fma(av[i].y, bv[j].x, fma(-av[i].x, bv[j].y, acc[i][j].y));
+            }
         }
     }
     __syncthreads();
-    cur0 = nxt0;
-    cur1 = nxt1;
-    nxt0 = nn0;
-    nxt1 = nn1;
-    kw_nxt = kw_nn;
+#pragma unroll
+    for (int r = 0; r < kGramRows; ++r) {
+      cur[r] = nxt[r];
+      nxt[r] = nn[r];
+    }
+    kw_nxt0 = kw_nn0;
+    kw_nxt1 = kw_nn1;
   }
   // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4; per row the four
   // Toeplitz values are read first (padding entries read a harmless value),

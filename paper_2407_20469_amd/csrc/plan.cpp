@@ -375,17 +375,19 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     p.coords.insert(p.coords.end(), Q.begin(), Q.end());
     st.off_e = int64_t(p.coords.size());
     p.coords.insert(p.coords.end(), E.begin(), E.end());
-    // block-sparsity masks: dilate P by each block of unknowns
+    // block-sparsity masks: dilate P by each half-block (kGramHB unknowns);
+    // a gram block (two halves) visits the k marked in either half, and
+    // skips its 16 x 16 quadrants whose two halves do not both hold that k
     {
       std::vector<uint8_t> live(size_t(W) * W);
-      const int nub = (st.nu + kGramUB - 1) / kGramUB;
+      const int nhb = (st.nu + kGramHB - 1) / kGramHB;
       const int nec = (st.ne + kEChunk - 1) / kEChunk;
       st.nwe = (nec + 63) / 64;
       st.off_gmask = int64_t(p.masks.size());
-      p.masks.resize(p.masks.size() + size_t(nub) * st.nwe, 0);
-      for (int b = 0; b < nub; ++b) {
+      p.masks.resize(p.masks.size() + size_t(nhb + 1) * st.nwe, 0);  // + an empty half
+      for (int b = 0; b < nhb; ++b) {
         std::fill(live.begin(), live.end(), 0);
-        for (int ui = b * kGramUB; ui < std::min(st.nu, (b + 1) * kGramUB); ++ui)
+        for (int ui = b * kGramHB; ui < std::min(st.nu, (b + 1) * kGramHB); ++ui)
           for (auto &q : Pc)  // k with u + k in P: k = q - u
             live[size_t(q.first - Uc[ui].first + n) * W + (q.second - Uc[ui].second + n)] = 1;
         auto is_live = [&](uint32_t w) {
@@ -397,12 +399,16 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
             p.masks[st.off_gmask + size_t(b) * st.nwe + c / 64] |= uint64_t(1) << (c % 64);
           }
       }
+      // issued work: live (quadrant of a lower block pair, k) pairs
+      const int nub = (st.nu + kGramUB - 1) / kGramUB;
+      auto hm = [&](int h, int w) { return p.masks[st.off_gmask + size_t(h) * st.nwe + w]; };
       for (int I = 0; I < nub; ++I)
         for (int J = 0; J <= I; ++J)
           for (int w = 0; w < st.nwe; ++w) {
-            const int64_t c = __builtin_popcountll(
-                p.masks[st.off_gmask + size_t(I) * st.nwe + w] &
-                p.masks[st.off_gmask + size_t(J) * st.nwe + w]);
+            int64_t c = 0;
+            for (int hi = 0; hi < 2; ++hi)
+              for (int hj = 0; hj < 2; ++hj)
+                c += __builtin_popcountll(hm(2 * I + hi, w) & hm(2 * J + hj, w));
             st.gram_live += c;
             if (I == J) st.gram_live_diag += c;
           }

@@ -19,7 +19,8 @@ constexpr int kNumFeat = 32;        // 8 pair-angle bins x 4 radial bands
 constexpr int kAbEntries = 78 + 12 + 2 + kNumFeat;  // A upper, b, sbb, sw, cells
 constexpr int kAbChunk = 2048;      // pupil rows per workgroup
 constexpr int kGramBlock = 64;      // gram storage / Cholesky padding granularity
-constexpr int kGramUB = 32;         // unknowns per gram block (block-sparsity masks)
+constexpr int kGramUB = 32;         // unknowns per gram block
+constexpr int kGramHB = 16;         // unknowns per half-block (block-sparsity masks)
 constexpr int kEChunk = 1;          // E rows per bit of the gram's block masks
 constexpr int kPixMax = 7936;       // pupil pixels of the one-workgroup pixel solve (LDS bound)
 constexpr int kPixIdxMax = 65536;   // pupil pixels of the pixel solve (16-bit pixel indices)
@@ -51,7 +52,7 @@ struct DfStep {
   // the N x N grid (FFT order, bit y N + x).
   int32_t nwe = 0;                   // 64-bit words per block of kGramUB unknowns
   int64_t off_gmask = 0, off_qbits = 0;
-  int64_t gram_live = 0;             // live (I >= J block pair, E chunk) triples
+  int64_t gram_live = 0;             // live (quadrant of an I >= J block pair, E row) pairs
   int64_t gram_live_diag = 0;        // the I = J part of gram_live
 };
 
