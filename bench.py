@@ -811,10 +811,11 @@ def main():
                                  slack=0.0, log=log)
         del buf
         tune = [{"geom": c["geom"], "tiles": c["n_tiles"], "chunk": c["chunk"],
-                 "lanes": c["lanes"], "ms_per_tile": float(m)}
+                 "lanes": c["lanes"], "fft_variant": c.get("fft_variant"),
+                 "fft_panel_columns": c.get("fft_panel_columns"), "ms_per_tile": float(m)}
                 for c, m in zip(batch.classes(), ms_tile)]
-        log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk, lanes) "
-            f"{[(c['geom'], c['tiles'], c['chunk'], c['lanes']) for c in tune]}")
+        log(f"autotune {time.time() - t0:.1f} s: (geom, tiles, chunk, lanes, fft variant) "
+            f"{[(c['geom'], c['tiles'], c['chunk'], c['lanes'], c['fft_variant']) for c in tune]}")
     elif batch.workspace_bytes > budget:
         batch.fit(budget)
     ws = apic.Workspace()

@@ -417,6 +417,9 @@ apic_status run_stitch(const ClassArgs &a, int64_t n_disk, float *spec_out, hipS
   ProfScope ps(APIC_PROF_STITCH, (double)a.T * 8.0 * ((double)a.n_bf * n_disk + a.n * a.n), st);
   hipLaunchKernelGGL(k_coef_led_phase, dim3(blocks_for(a.T, 64)), dim3(64), 0, st, a);
   APIC_LAUNCHED();
+  hipLaunchKernelGGL(k_pupil_phasor, dim3(blocks_for((int64_t)a.T * a.n * a.n, 256)), dim3(256), 0,
+                     st, a);
+  APIC_LAUNCHED();
   hipLaunchKernelGGL(k_stitch, dim3(blocks_for((int64_t)a.T * a.n * a.n, 256)), dim3(256), 0, st,
                      a, spec_out);
   APIC_LAUNCHED();

@@ -476,29 +476,72 @@ __global__ __launch_bounds__(64) void k_coef_led_phase(ClassArgs a) {
 
 // ---------------------------------------------------------------- stitch
 // O_hat(k) = mean over covering i of s_i(k) exp(-j[phi_c(k+k_i) - phi_c(k_i)]).
-__global__ __launch_bounds__(256) void k_stitch(ClassArgs a, float *spec_out) {
+// The phasor exp(-j phi_c(q)) depends on the pupil point q = k + k_i only:
+// k_pupil_phasor evaluates it once per point of the pupil disk, into the
+// tile's ptil block (free until the darkfield stage, which overwrites it),
+// and k_stitch gathers it for each covering image, times exp(j phi_c(k_i)).
+__global__ __launch_bounds__(256) void k_pupil_phasor(ClassArgs a) {
   const int nn = a.n * a.n;
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (gid >= (int64_t)a.T * nn) return;
   const int t = (int)(gid / nn), pix = (int)(gid % nn);
-  const int ky = signed_idx(pix / a.n, a.n), kx = signed_idx(pix % a.n, a.n);
+  const int qy = signed_idx(pix / a.n, a.n), qx = signed_idx(pix % a.n, a.n);
+  if (!a.circ(qy, qx)) return;
   const float *co = a.at<float>(t, a.lay.coef);
   float c[12];
 #pragma unroll
   for (int j = 0; j < 12; ++j) c[j] = co[j];
+  float sn, cs;
+  sincosf(pupil_phase12(c, (float)qx, (float)qy, a.inv_r), &sn, &cs);
+  a.at<c32>(t, a.lay.ptil)[pix] = make_float2(cs, -sn);
+}
+
+__global__ __launch_bounds__(256) void k_stitch(ClassArgs a, float *spec_out) {
+  const int nn = a.n * a.n;  // a multiple of 256: a workgroup stays in one tile
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int t = (int)min((int64_t)a.T - 1, ((int64_t)blockIdx.x * 256) / nn);
+  __shared__ c32 led[kMaxBf];  // exp(j phi_c(k_i))
+  if (threadIdx.x < a.n_bf) {
+    float sn, cs;
+    sincosf(a.at<float>(t, a.lay.coef)[16 + threadIdx.x], &sn, &cs);
+    led[threadIdx.x] = make_float2(cs, sn);
+  }
+  __syncthreads();
+  if (gid >= (int64_t)a.T * nn) return;
+  const int pix = (int)(gid % nn);
+  const int ky = signed_idx(pix / a.n, a.n), kx = signed_idx(pix % a.n, a.n);
   const c32 *stack = a.at<c32>(t, a.lay.stack);
+  const c32 *tab = a.at<c32>(t, a.lay.ptil);
+  // eight images at a time: their loads first (independent, in flight
+  // together), then their sums
+  constexpr int G = 8;
   float ax = 0.f, ay = 0.f;
   int cnt = 0;
-  for (int i = 0; i < a.n_bf; ++i) {
-    const int qy = ky + a.ky[i], qx = kx + a.kx[i];
-    if (!a.circ(qy, qx)) continue;
-    const float ph = pupil_phase12(c, (float)qx, (float)qy, a.inv_r) - co[16 + i];
-    float sn, cs;
-    sincosf(ph, &sn, &cs);
-    const c32 v = stack[(int64_t)i * nn + pix];
-    ax += v.x * cs + v.y * sn;  // v * exp(-j ph)
-    ay += v.y * cs - v.x * sn;
-    ++cnt;
+  for (int i0 = 0; i0 < a.n_bf; i0 += G) {
+    c32 v[G], e[G];
+    bool in[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+      v[g] = e[g] = make_float2(0.f, 0.f);
+      in[g] = false;
+      if (i < a.n_bf) {
+        const int qy = ky + a.ky[i], qx = kx + a.kx[i];
+        in[g] = a.circ(qy, qx);
+        if (in[g]) {
+          e[g] = tab[fft_pos(qy, a.n) * a.n + fft_pos(qx, a.n)];
+          v[g] = stack[(int64_t)i * nn + pix];
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (!in[g]) continue;
+      const c32 w = cmul(e[g], led[i0 + g]);
+      ax += v[g].x * w.x - v[g].y * w.y;  // v * exp(-j [phi_c(q) - phi_c(k_i)])
+      ay += v[g].x * w.y + v[g].y * w.x;
+      ++cnt;
+    }
   }
   const float inv = cnt ? 1.f / (float)cnt : 0.f;
   const c32 o = make_float2(ax * inv, ay * inv);
