@@ -161,6 +161,24 @@ def busy(path, pattern, gap_ms=5.0):
     return "\n".join(out)
 
 
+def counters(d, pattern, min_grid):
+    """Per-dispatch mean of every counter of one --pmc run, over the dispatches
+    of the kernels matching `pattern` with at least `min_grid` work-items."""
+    import re
+    rx = re.compile(pattern)
+    tot, cnt = {}, {}
+    for r in _counter_rows(d):
+        if int(r["Grid_Size"]) < min_grid or not rx.search(r["Kernel_Name"]):
+            continue
+        k = r["Counter_Name"]
+        tot[k] = tot.get(k, 0.0) + float(r["Counter_Value"])
+        cnt[k] = cnt.get(k, 0) + 1
+    out = ["| counter | dispatches | per dispatch |", "|---|---:|---:|"]
+    for k in sorted(tot):
+        out.append(f"| {k} | {cnt[k]} | {tot[k] / cnt[k]:.4g} |")
+    return "\n".join(out)
+
+
 def stats(path, top=16):
     rows = list(csv.DictReader(open(path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
@@ -184,6 +202,8 @@ if __name__ == "__main__":
         print(text)
     elif sys.argv[1] == "dispatches":
         print(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4])))
+    elif sys.argv[1] == "counters":
+        print(counters(sys.argv[2], sys.argv[3], int(sys.argv[4])))
     elif sys.argv[1] == "hbm":
         print(hbm(*sys.argv[2:6], int(sys.argv[6])))
     elif sys.argv[1] == "busy":
