@@ -241,26 +241,39 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     return (mw * 64 + p) | (q << 24);
   };
   constexpr int kRowMask = (1 << 24) - 1;
-  // this lane's excluded k of slot sl among four E rows (kNoK for a missing row)
+  // this lane's excluded k of slot sl among four E rows (kNoK for a missing
+  // row).  The rows are wave-uniform: both candidate words are read through
+  // the constant address space (scalar loads; the table is read-only here)
+  // and each lane selects its own.
+  typedef const uint32_t __attribute__((address_space(4))) *cword_ptr;
+  const cword_ptr ew = (cword_ptr)s.e;
   auto k_of = [&](const int (&rr)[kGramRows], int sl) -> uint32_t {
-    const int r = kk ? rr[2 * sl + 1] : rr[2 * sl];
-    return r >= 0 ? s.e[r & kRowMask] : kNoK;
+    const int r0 = rr[2 * sl], r1 = rr[2 * sl + 1];
+    const uint32_t e0 = r0 >= 0 ? ew[r0 & kRowMask] : kNoK;
+    const uint32_t e1 = r1 >= 0 ? ew[r1 & kRowMask] : kNoK;
+    return kk ? e1 : e0;
   };
   // this lane's operand elements of one k: P_hat(u_a + k), P_hat(u_b + k)
   // (the second only off the diagonal)
   struct Ops {
     c64 a, b;
   };
+  // grid position of u + k with shifts and masks (N is a power of two),
+  // always in range; a select replaces it by zpos for a missing u or k
+  const uint32_t nmask = (uint32_t)a.n - 1u, nshift = (uint32_t)__builtin_ctz(a.n);
+  const bool va = wa != kNoK, vb = wb != kNoK;
+  auto pos_of = [&](int uy, int ux, int ky, int kx) -> uint32_t {
+    return ((((uint32_t)(uy + ky)) & nmask) << nshift) | (((uint32_t)(ux + kx)) & nmask);
+  };
   auto gather = [&](uint32_t kw) -> Ops {
     const bool kv = kw != kNoK;
     const int ky = kunpack_y(kw), kx = kunpack_x(kw);
-    const int ia = (kv && wa != kNoK) ? fft_pos(ay + ky, a.n) * a.n + fft_pos(ax + kx, a.n) : zpos;
+    const uint32_t ia = (kv && va) ? pos_of(ay, ax, ky, kx) : (uint32_t)zpos;
     Ops o;
     o.a = phat[ia];
     o.b = make_double2(0.0, 0.0);
     if (!diag) {
-      const int ib =
-          (kv && wb != kNoK) ? fft_pos(by + ky, a.n) * a.n + fft_pos(bx + kx, a.n) : zpos;
+      const uint32_t ib = (kv && vb) ? pos_of(by, bx, ky, kx) : (uint32_t)zpos;
       o.b = phat[ib];
     }
     return o;
