@@ -65,3 +65,29 @@ def test_slide_mask_and_scan_order():
     w = slide.pool_workload(16, 4)
     assert (w.n, w.n_bf, w.n_df, w.n_tiles) == (512, 16, 32, 20)
     assert np.abs(w.coeffs).max() <= 1.5 + 1e-9
+
+
+def test_surrogate_workload_sets():
+    """The surrogate workload's sets: 16384 training tiles of the uneven
+    recipe without background or darkfield images at random positions, 4096
+    evaluation tiles with 70% background and darkfield on the 64 x 64 grid;
+    the two draw objects and noise from disjoint class seeds, and their pupils
+    come from one field model (max 1.5 rad on the evaluation grid)."""
+    import numpy as np
+    tr = S.surrogate_train_batch()
+    ev = S.surrogate_eval_batch()
+    assert sum(w.n_tiles for w in tr) == 16384 and sum(w.n_tiles for w in ev) == 4096
+    assert all(w.n_df == 0 and not w.extra["background"].any() for w in tr)
+    assert all(w.n_df == 2 * w.n_bf for w in ev)
+    assert sum(int(w.extra["background"].sum()) for w in ev) == round(0.7 * 4096)
+    assert {w.seed_id for w in tr}.isdisjoint({w.seed_id for w in ev})
+    sizes = np.concatenate([[w.n] * w.n_tiles for w in tr])
+    assert (sizes == 128).sum() == 8192 and (sizes == 256).sum() == 6144
+    pos = np.concatenate([w.positions for w in tr])
+    assert np.all(np.abs(pos) <= 1.0) and len(np.unique(pos[:, 0])) == 16384
+    c_ev = np.concatenate([w.coeffs for w in ev])
+    assert abs(np.abs(c_ev).max() - 1.5) < 1e-12
+    # the training pupils follow the same field model: evaluated at the
+    # evaluation grid's positions they reproduce its coefficients
+    w0 = ev[0]
+    assert np.allclose(S.field_model_on_grid(w0.positions[:, 0], w0.positions[:, 1]), w0.coeffs)
