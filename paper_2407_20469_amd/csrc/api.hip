@@ -456,27 +456,22 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     const int64_t pix = (int64_t)a.T * N * N;
     const double nu = d.nu, T = a.T;
     {
-      // P_hat (read O_hat 8 B, write 16 B), 3 FP64 passes (32 B each, plus
-      // 16 B for P), image FFT (read 4 B, write 16 B, then 32 B)
-      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 3 * 32.0 + 16.0 + 20.0 + 32.0), st);
-      hipLaunchKernelGGL(k_df_phat, dim3(blocks_for(pix, 256)), dim3(256), 0, st, a, s);
-      APIC_LAUNCHED();
+      // three FP64 passes: P_hat formed in the first (read O_hat 8 B, write
+      // P_hat 16 B, write 16 B), then read, write P, read the image, write
+      // (52 B), then read, write (32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (40.0 + 52.0 + 32.0), st);
       hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                         dim3(kFftThreads), 0, st, OpP1<N>{a});
+                         dim3(kFftThreads), 0, st, OpP1<N>{a, s});
       APIC_LAUNCHED();
-      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a}, st));
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a, s.img}, st));
       hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP3<N>{a});
       APIC_LAUNCHED();
-      hipLaunchKernelGGL((k_rows<c64, N, OpImg1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                         dim3(kFftThreads), 0, st, OpImg1<N>{a, s.img});
-      APIC_LAUNCHED();
-      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpImg2<N>{a}, st));
     }
     {
-      // three FP64 passes: Q bitmap, fimg and fpp on Q, write (16 B per pixel
-      // + 32 B per Q point); read and read P, write (48 B); read, write (32 B);
-      // then N_u gathers (32 B each)
+      // three FP64 passes: Q bitmap, z(k) and z(-k) on Q, write (16 B per
+      // pixel + 32 B per Q point); read and read P, write (48 B); read, write
+      // (32 B); then N_u gathers (32 B each)
       ProfScope ps(APIC_PROF_DF_RHS,
                    (double)pix * (16.0 + 48.0 + 32.0 + 0.125) + T * (32.0 * d.m + 32.0 * nu), st);
       hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, N)),

@@ -2,9 +2,10 @@
 // upsampled output.  For darkfield image j (known set P, unknown set U, linear
 // region Q, excluded set E = (P - U) - Q, all plan tables):
 //
-//   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P, 0 elsewhere  (k_df_phat)
-//   fpp      = fft2(|ifft2 P_hat|^2)        FP64 passes          (OpP*)
-//   fimg     = fft2(I_j)                    FP64 passes          (OpImg*)
+//   P_hat(k) = O_hat(k) exp(j phi_c(k + k_j)) on P, 0 elsewhere  (OpP1 load)
+//   z        = fft2(|ifft2 P_hat|^2 + i I_j)  FP64 passes        (OpP*)
+//   fpp(k)   = (z(k) + conj z(-k)) / 2 = fft2(|P|^2)(k)
+//   fimg(k)  = (z(k) - conj z(-k)) / 2i = fft2(I_j)(k)
 //   b(k)     = conj(fimg(k) - fpp(k)),  k in Q                   (OpR1)
 //   G[u,u']  = sum_{k in Q} P_hat(u+k) conj(P_hat(u'+k)) / N^4   (k_df_gram)
 //            = fpp(u - u') / N^2 - sum_{k in E} P_hat(u+k) conj(P_hat(u'+k)) / N^4
@@ -13,6 +14,8 @@
 //   x        = (G + lambda tr(G)/N_u I)^-1 v   FP64 Cholesky     (chol.hpp)
 //   O_hat(u) = x(u) exp(-j phi_c(u + k_j)),  u in U              (k_chol_back)
 //
+// |P|^2 and I_j are both real, so their spectra are Hermitian and one complex
+// transform of |P|^2 + i I_j carries both: the pair z(k), z(-k) separates them.
 // The gram identity: the sum over every k of P_hat(u+k) conj(P_hat(u'+k)) is
 // the autocorrelation of P_hat at u' - u, which is N^2 fpp(u - u'); Q and E
 // partition P - U, so the Q-sum is that minus the (smaller) E-sum.
@@ -26,11 +29,9 @@
 
 namespace apic {
 
-__global__ __launch_bounds__(256) void k_df_phat(ClassArgs a, StepArgs s) {
-  const int nn = a.n * a.n;
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= (int64_t)a.T * nn) return;
-  const int t = (int)(gid / nn), pix = (int)(gid % nn);
+// P_hat at grid index pix of tile t (zero off the shifted pupil and on
+// points not yet known before image j).
+__device__ __forceinline__ c64 phat_at(const ClassArgs &a, const StepArgs &s, int t, int pix) {
   const int ky = signed_idx(pix / a.n, a.n), kx = signed_idx(pix % a.n, a.n);
   c64 v = make_double2(0.0, 0.0);
   const int qy = ky + s.ky, qx = kx + s.kx;
@@ -45,33 +46,41 @@ __global__ __launch_bounds__(256) void k_df_phat(ClassArgs a, StepArgs s) {
     const c32 o = a.at<c32>(t, a.lay.ohat)[pix];
     v = make_double2((double)o.x * cs - (double)o.y * sn, (double)o.x * sn + (double)o.y * cs);
   }
-  a.at<c64>(t, a.lay.phat)[pix] = v;
+  return v;
 }
 
-// P chain, pass 1 (rows): row IFFT of P_hat.
+// P chain, pass 1 (rows): form P_hat (kept for the gram's gathers) and
+// row-IFFT it.
 template <int N> struct OpP1 {
   static constexpr bool INV1 = true, TWO = false, INV2 = false;
   ClassArgs a;
+  StepArgs s;
   __device__ int rows() const { return N; }
   __device__ int row_of(int r) const { return r; }
-  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.phat)[y * N + x]; }
+  __device__ c64 load(int t, int y, int x) const {
+    const c64 v = phat_at(a, s, t, y * N + x);
+    a.at<c64>(t, a.lay.phat)[y * N + x] = v;
+    return v;
+  }
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
 };
 // Pass 2 (columns): column IFFT gives N^2 P; keep P (normalised) for the
-// right-hand side; |P|^2 = |.|^2 / N^4; column FFT.
+// right-hand side; |P|^2 = |.|^2 / N^4 as the real part and the darkfield
+// image as the imaginary part; column FFT.
 template <int N> struct OpP2 {
   static constexpr bool INV1 = true, TWO = true, INV2 = false;
   ClassArgs a;
+  int img;
   __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
   __device__ void mid(int t, int y, int x, c64 &v) const {
     constexpr double inv2 = 1.0 / ((double)N * N), inv4 = inv2 * inv2;
     a.at<c64>(t, a.lay.ptil)[y * N + x] = make_double2(v.x * inv2, v.y * inv2);
-    v = make_double2((v.x * v.x + v.y * v.y) * inv4, 0.0);
+    v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)a.image(t, img)[y * N + x]);
   }
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
 };
-// Pass 3 (rows): row FFT completes fpp = fft2(|P|^2).
+// Pass 3 (rows): row FFT completes z = fft2(|P|^2 + i I_j).
 template <int N> struct OpP3 {
   static constexpr bool INV1 = false, TWO = false, INV2 = false;
   ClassArgs a;
@@ -81,29 +90,14 @@ template <int N> struct OpP3 {
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fpp)[y * N + x] = v; }
 };
-// fft2 of the darkfield image in FP64: rows, then columns in place.
-template <int N> struct OpImg1 {
-  static constexpr bool INV1 = false, TWO = false, INV2 = false;
-  ClassArgs a;
-  int img;
-  __device__ int rows() const { return N; }
-  __device__ int row_of(int r) const { return r; }
-  __device__ c64 load(int t, int y, int x) const {
-    return make_double2((double)a.image(t, img)[y * N + x], 0.0);
-  }
-  __device__ void mid(int, int, int, c64 &) const {}
-  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fimg)[y * N + x] = v; }
-};
-template <int N> struct OpImg2 {
-  static constexpr bool INV1 = false, TWO = false, INV2 = false;
-  ClassArgs a;
-  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.fimg)[y * N + x]; }
-  __device__ void mid(int, int, int, c64 &) const {}
-  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fimg)[y * N + x] = v; }
-};
+// Grid index of -k for the grid index of k.
+template <int N> __device__ __forceinline__ int neg_pix(int y, int x) {
+  return ((N - y) & (N - 1)) * N + ((N - x) & (N - 1));
+}
 
 // Right-hand side pass 1 (rows): b(k) = conj(fft2(I_j)(k) - fft2(|P|^2)(k))
-// on Q (Eq. 13, conjugated), zero elsewhere; row FFT.
+// on Q (Eq. 13, conjugated), zero elsewhere, both spectra separated from z;
+// row FFT.
 template <int N> struct OpR1 {
   static constexpr bool INV1 = false, TWO = false, INV2 = false;
   ClassArgs a;
@@ -113,7 +107,10 @@ template <int N> struct OpR1 {
   __device__ c64 load(int t, int y, int x) const {
     const int pix = y * N + x;
     if (!((qbits[pix >> 6] >> (pix & 63)) & 1u)) return make_double2(0.0, 0.0);
-    return cconj(csub(a.at<c64>(t, a.lay.fimg)[pix], a.at<c64>(t, a.lay.fpp)[pix]));
+    // conj(fimg - fpp) from z(k) and z(-k)
+    const c64 *z = a.at<c64>(t, a.lay.fpp);
+    const c64 z1 = z[pix], z2 = z[neg_pix<N>(y, x)];
+    return make_double2(0.5 * ((z1.y + z2.y) - (z1.x + z2.x)), 0.5 * ((z1.x - z2.x) + (z1.y - z2.y)));
   }
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
@@ -339,11 +336,12 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     kw_nxt0 = kw_nn0;
     kw_nxt1 = kw_nn1;
   }
-  // G[r][c] = fft2(|P|^2)(u_r - u_c) / N^2 - acc / N^4; per row the four
-  // Toeplitz values are read first (padding entries read a harmless value),
-  // then the valid entries stored, so those loads are in flight together
-  const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2;
-  const c64 *fpp = a.at<c64>(t, a.lay.fpp);
+  // G[r][c] = fft2(|P|^2)(d) / N^2 - acc / N^4 with d = u_r - u_c, where
+  // fft2(|P|^2)(d) = (z(d) + conj z(-d)) / 2; per row the Toeplitz values are
+  // read first (padding entries read a harmless value), then the valid
+  // entries stored, so those loads are in flight together
+  const double n2 = (double)a.n * a.n, inv2 = 1.0 / n2, inv4 = inv2 * inv2, hinv2 = 0.5 * inv2;
+  const c64 *z = a.at<c64>(t, a.lay.fpp);
   c64 *G = a.at<c64>(t, a.lay.gram);
   const int ld = a.nu_pad;
 #pragma unroll
@@ -351,19 +349,20 @@ __global__ __launch_bounds__(64) void k_df_gram(ClassArgs a, StepArgs s) {
     const uint32_t wr = su[0][ty + 8 * i];
     const int ry = kunpack_y(wr), rx = kunpack_x(wr);
     const int r = I * kGramUB + ty + 8 * i;
-    c64 tv[4];
+    c64 tv[4], tw[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t wc = su[1][tx + 8 * j];
       const int dy = ry - kunpack_y(wc), dx = rx - kunpack_x(wc);
-      tv[j] = fpp[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
+      tv[j] = z[fft_pos(dy, a.n) * a.n + fft_pos(dx, a.n)];
+      tw[j] = z[fft_pos(-dy, a.n) * a.n + fft_pos(-dx, a.n)];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = J * kGramUB + tx + 8 * j;
       if (r < s.nu && c < s.nu)
-        G[(int64_t)r * ld + c] = make_double2(tv[j].x * inv2 - acc[i][j].x * inv4,
-                                              tv[j].y * inv2 - acc[i][j].y * inv4);
+        G[(int64_t)r * ld + c] = make_double2((tv[j].x + tw[j].x) * hinv2 - acc[i][j].x * inv4,
+                                              (tv[j].y - tw[j].y) * hinv2 - acc[i][j].y * inv4);
     }
   }
 }

@@ -452,7 +452,6 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
   L.phat = take(int64_t(nn) * c64);
   L.dtmp = take(int64_t(nn) * c64);
   L.fpp = take(int64_t(nn) * c64);
-  L.fimg = take(int64_t(nn) * c64);
   L.ptil = take(int64_t(nn) * c64);
   L.vec = take(int64_t(p.nu_pad) * c64);
   // the gram block also serves the pixel-domain pupil solve (a separate call):

@@ -58,7 +58,7 @@ struct DfStep {
 
 // Per-tile workspace layout (byte offsets from the tile's base).
 struct TileLayout {
-  int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, fimg = 0, ptil = 0, vec = 0,
+  int64_t stack = 0, ohat = 0, phat = 0, dtmp = 0, fpp = 0, ptil = 0, vec = 0,
           gram = 0, linv = 0, part = 0, sums = 0, coef = 0, sur = 0, seed = 0, eps = 0, stride = 0;
 };
 
