@@ -453,33 +453,45 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.gmask = a.masks + d.off_gmask;
     s.nwe = d.nwe;
     s.qbits = a.masks + d.off_qbits;
+    // row ranges of the pruned passes, whole row-pass workgroups (at least one)
+    constexpr int RW = RowShape<c64, N>::ROWS;
+    auto rows_of = [&](int lo, int hi, int &y0, int &cnt) {
+      y0 = lo & (N - 1);
+      cnt = std::min(N, std::max(RW, (hi - lo + 1 + RW - 1) / RW * RW));
+    };
+    rows_of(d.d_lo, d.d_hi, s.dy0, s.dn);
+    rows_of(d.q_lo, d.q_hi, s.qy0, s.qn);
     const int64_t pix = (int64_t)a.T * N * N;
-    const double nu = d.nu, T = a.T;
+    const double nu = d.nu, T = a.T, fd = (double)s.dn / N, fq = (double)s.qn / N;
     {
       // three FP64 passes: P_hat formed in the first (read O_hat 8 B, write
-      // P_hat 16 B, write 16 B), then read, write P, read the image, write
-      // (52 B), then read, write (32 B)
-      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (40.0 + 52.0 + 32.0), st);
+      // P_hat 16 B, write 16 B on the rows of D), then read (rows of D),
+      // write P, read the image, write (36 B + 16 B on D), then read, write
+      // (32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 36.0 + 32.0 + 32.0 * fd), st);
       hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP1<N>{a, s});
       APIC_LAUNCHED();
-      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a, s.img}, st));
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a, s}, st));
       hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP3<N>{a});
       APIC_LAUNCHED();
     }
     {
-      // three FP64 passes: Q bitmap, z(k) and z(-k) on Q, write (16 B per
-      // pixel + 32 B per Q point); read and read P, write (48 B); read, write
-      // (32 B); then N_u gathers (32 B each)
+      // three FP64 passes: on the rows of Q the Q bitmap, z(k) and z(-k) on
+      // Q, write (16 B per pixel + 32 B per Q point); read (rows of Q), read
+      // P, write (rows of D) (16 B + 16 B on Q + 16 B on D); read, write on
+      // the rows of D (32 B); then N_u gathers (32 B each)
       ProfScope ps(APIC_PROF_DF_RHS,
-                   (double)pix * (16.0 + 48.0 + 32.0 + 0.125) + T * (32.0 * d.m + 32.0 * nu), st);
-      hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                         dim3(kFftThreads), 0, st, OpR1<N>{a, s.qbits});
+                   (double)pix * (16.125 * fq + 16.0 + 16.0 * fq + 48.0 * fd) +
+                       T * (32.0 * d.m + 32.0 * nu),
+                   st);
+      hipLaunchKernelGGL((k_rows<c64, N, OpR1<N>>), dim3(row_blocks<c64, N>(a.T, s.qn)),
+                         dim3(kFftThreads), 0, st, OpR1<N>{a, s});
       APIC_LAUNCHED();
-      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpR2<N>{a}, st));
-      hipLaunchKernelGGL((k_rows<c64, N, OpR3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                         dim3(kFftThreads), 0, st, OpR3<N>{a});
+      APIC_CHECK(launch_cols<c64, N>(a, a.T, OpR2<N>{a, s}, st));
+      hipLaunchKernelGGL((k_rows<c64, N, OpR3<N>>), dim3(row_blocks<c64, N>(a.T, s.dn)),
+                         dim3(kFftThreads), 0, st, OpR3<N>{a, s});
       APIC_LAUNCHED();
       hipLaunchKernelGGL(k_df_rhs_gather, dim3(blocks_for(d.nu, 256), a.T), dim3(256), 0, st,
                          a, s);

@@ -130,7 +130,15 @@ struct StepArgs {
   const uint64_t *gmask;          // block-sparsity masks of E chunks
   int nwe;                        // mask words per block of 64 unknowns
   const uint64_t *qbits;          // Q membership over the grid (bit y N + x)
+  // rows of D (P_hat and the unknowns) and of Q (b): FFT-order first row and
+  // row count, rounded up to whole row-pass workgroups
+  int dy0, dn, qy0, qn;
 };
+
+// Row y (FFT order) lies in the cyclic range of cnt rows from y0.
+__device__ __forceinline__ bool row_in(int y, int y0, int cnt, int n) {
+  return ((y - y0) & (n - 1)) < cnt;
+}
 
 // Workgroups are dispatched to the 8 XCDs round robin (workgroup b on XCD
 // b mod 8), each XCD with its own L2.  Maps the b-th of n workgroups to a work

@@ -63,7 +63,10 @@ template <int N> struct OpP1 {
     return v;
   }
   __device__ void mid(int, int, int, c64 &) const {}
-  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+  // rows outside D are zero rows: not stored, and read as zero by pass 2
+  __device__ void store(int t, int y, int x, c64 v) const {
+    if (row_in(y, s.dy0, s.dn, N)) a.at<c64>(t, a.lay.dtmp)[y * N + x] = v;
+  }
 };
 // Pass 2 (columns): column IFFT gives N^2 P; keep P (normalised) for the
 // right-hand side; |P|^2 = |.|^2 / N^4 as the real part and the darkfield
@@ -71,12 +74,15 @@ template <int N> struct OpP1 {
 template <int N> struct OpP2 {
   static constexpr bool INV1 = true, TWO = true, INV2 = false;
   ClassArgs a;
-  int img;
-  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  StepArgs s;
+  __device__ c64 load(int t, int y, int x) const {
+    if (!row_in(y, s.dy0, s.dn, N)) return make_double2(0.0, 0.0);
+    return a.at<c64>(t, a.lay.dtmp)[y * N + x];
+  }
   __device__ void mid(int t, int y, int x, c64 &v) const {
     constexpr double inv2 = 1.0 / ((double)N * N), inv4 = inv2 * inv2;
     a.at<c64>(t, a.lay.ptil)[y * N + x] = make_double2(v.x * inv2, v.y * inv2);
-    v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)a.image(t, img)[y * N + x]);
+    v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)a.image(t, s.img)[y * N + x]);
   }
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
 };
@@ -101,12 +107,12 @@ template <int N> __device__ __forceinline__ int neg_pix(int y, int x) {
 template <int N> struct OpR1 {
   static constexpr bool INV1 = false, TWO = false, INV2 = false;
   ClassArgs a;
-  const uint64_t *qbits;
-  __device__ int rows() const { return N; }
-  __device__ int row_of(int r) const { return r; }
+  StepArgs s;
+  __device__ int rows() const { return s.qn; }  // the rows of Q; pass 2 reads the rest as zero
+  __device__ int row_of(int r) const { return (s.qy0 + r) & (N - 1); }
   __device__ c64 load(int t, int y, int x) const {
     const int pix = y * N + x;
-    if (!((qbits[pix >> 6] >> (pix & 63)) & 1u)) return make_double2(0.0, 0.0);
+    if (!((s.qbits[pix >> 6] >> (pix & 63)) & 1u)) return make_double2(0.0, 0.0);
     // conj(fimg - fpp) from z(k) and z(-k)
     const c64 *z = a.at<c64>(t, a.lay.fpp);
     const c64 z1 = z[pix], z2 = z[neg_pix<N>(y, x)];
@@ -119,18 +125,26 @@ template <int N> struct OpR1 {
 template <int N> struct OpR2 {
   static constexpr bool INV1 = false, TWO = true, INV2 = false;
   ClassArgs a;
-  __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
+  StepArgs s;
+  __device__ c64 load(int t, int y, int x) const {
+    if (!row_in(y, s.qy0, s.qn, N)) return make_double2(0.0, 0.0);
+    return a.at<c64>(t, a.lay.dtmp)[y * N + x];
+  }
   __device__ void mid(int t, int y, int x, c64 &v) const {
     v = cmul(v, a.at<c64>(t, a.lay.ptil)[y * N + x]);
   }
-  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+  // only the rows of D (which hold U) go on to pass 3
+  __device__ void store(int t, int y, int x, c64 v) const {
+    if (row_in(y, s.dy0, s.dn, N)) a.at<c64>(t, a.lay.dtmp)[y * N + x] = v;
+  }
 };
-// Pass 3 (rows): row FFT completes N^2 v over the grid.
+// Pass 3 (rows of D): row FFT completes N^2 v on the rows that hold U.
 template <int N> struct OpR3 {
   static constexpr bool INV1 = false, TWO = false, INV2 = false;
   ClassArgs a;
-  __device__ int rows() const { return N; }
-  __device__ int row_of(int r) const { return r; }
+  StepArgs s;
+  __device__ int rows() const { return s.dn; }
+  __device__ int row_of(int r) const { return (s.dy0 + r) & (N - 1); }
   __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }

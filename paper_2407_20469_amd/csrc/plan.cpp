@@ -371,6 +371,18 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
     });
     st.m = int(Q.size());
     st.ne = int(E.size());
+    {
+      int dlo = n, dhi = -n, qlo = n, qhi = -n;
+      for (auto &c : Pc) dlo = std::min(dlo, c.first), dhi = std::max(dhi, c.first);
+      for (auto &c : Uc) dlo = std::min(dlo, c.first), dhi = std::max(dhi, c.first);
+      for (uint32_t w : Q) qlo = std::min(qlo, unpack_ky(w)), qhi = std::max(qhi, unpack_ky(w));
+      st.d_lo = dlo;  // U is not empty here
+      st.d_hi = dhi;
+      if (!Q.empty()) {
+        st.q_lo = qlo;
+        st.q_hi = qhi;
+      }
+    }
     st.off_q = int64_t(p.coords.size());
     p.coords.insert(p.coords.end(), Q.begin(), Q.end());
     st.off_e = int64_t(p.coords.size());

@@ -54,6 +54,10 @@ struct DfStep {
   int64_t off_gmask = 0, off_qbits = 0;
   int64_t gram_live = 0;             // live (quadrant of an I >= J block pair, E row) pairs
   int64_t gram_live_diag = 0;        // the I = J part of gram_live
+  // Signed row spans (ky) of D = P + U (the shifted pupil's points: where
+  // P_hat and the unknowns lie) and of Q (where b is nonzero); the FFT passes
+  // of P_hat and of the right-hand side skip the rows outside them.
+  int32_t d_lo = 0, d_hi = -1, q_lo = 0, q_hi = -1;
 };
 
 // Per-tile workspace layout (byte offsets from the tile's base).
