@@ -12,6 +12,8 @@
 // output r to (j / NS) NS R + (j mod NS) + r NS.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace apic {
@@ -151,24 +153,58 @@ __global__ __launch_bounds__(kFftThreads) void k_rows(Op op) {
   }
 }
 
+// An op of a two-transform column pass may read one float per element for its
+// between-transform hook (SIDE = true: side() and mid_side()); the column pass
+// issues those reads with its loads, so they are not a dependent wait between
+// the two transforms.
+template <class Op, class = void> struct SideOf {
+  static constexpr bool value = false;
+};
+template <class Op> struct SideOf<Op, std::void_t<decltype(Op::SIDE)>> {
+  static constexpr bool value = Op::SIDE;
+};
+
 // Column pass: workgroup = NSEQ adjacent columns of one 2D array (all L rows).
 template <class C, int L, class Op, int NSEQ = ColShape<C, L>::NSEQ>
 __global__ __launch_bounds__(kFftThreads) void k_cols(Op op) {
   __shared__ C buf[L * NSEQ];
   constexpr int groups = L / NSEQ;
+  constexpr bool kSide = SideOf<Op>::value;
+  constexpr int PER = (L * NSEQ) / kFftThreads;  // elements per thread
+  static_assert(PER * kFftThreads == L * NSEQ, "whole elements per thread");
   const int bid = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring panels on one XCD
   const int arr = bid / groups;
   const int x0 = (bid % groups) * NSEQ;
-  for (int e = threadIdx.x; e < L * NSEQ; e += kFftThreads) {
-    const int y = e / NSEQ, c = e % NSEQ;
-    buf[e] = op.load(arr, y, x0 + c);
+  float side[kSide ? PER : 1];
+  if constexpr (kSide) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * kFftThreads;
+      const int y = e / NSEQ, c = e % NSEQ;
+      buf[e] = op.load(arr, y, x0 + c);
+      side[i] = op.side(arr, y, x0 + c);
+    }
+  } else {
+    for (int e = threadIdx.x; e < L * NSEQ; e += kFftThreads) {
+      const int y = e / NSEQ, c = e % NSEQ;
+      buf[e] = op.load(arr, y, x0 + c);
+    }
   }
   __syncthreads();
   lds_fft<C, L, NSEQ, kFftThreads, Op::INV1, true, 1, NSEQ>(buf);
   if constexpr (Op::TWO) {
-    for (int e = threadIdx.x; e < L * NSEQ; e += kFftThreads) {
-      const int y = e / NSEQ, c = e % NSEQ;
-      op.mid(arr, y, x0 + c, buf[e]);
+    if constexpr (kSide) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * kFftThreads;
+        const int y = e / NSEQ, c = e % NSEQ;
+        op.mid_side(arr, y, x0 + c, buf[e], side[i]);
+      }
+    } else {
+      for (int e = threadIdx.x; e < L * NSEQ; e += kFftThreads) {
+        const int y = e / NSEQ, c = e % NSEQ;
+        op.mid(arr, y, x0 + c, buf[e]);
+      }
     }
     __syncthreads();
     lds_fft<C, L, NSEQ, kFftThreads, Op::INV2, true, 1, NSEQ>(buf);

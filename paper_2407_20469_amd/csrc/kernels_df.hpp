@@ -72,17 +72,19 @@ template <int N> struct OpP1 {
 // right-hand side; |P|^2 = |.|^2 / N^4 as the real part and the darkfield
 // image as the imaginary part; column FFT.
 template <int N> struct OpP2 {
-  static constexpr bool INV1 = true, TWO = true, INV2 = false;
+  static constexpr bool INV1 = true, TWO = true, INV2 = false, SIDE = true;
   ClassArgs a;
   StepArgs s;
   __device__ c64 load(int t, int y, int x) const {
     if (!row_in(y, s.dy0, s.dn, N)) return make_double2(0.0, 0.0);
     return a.at<c64>(t, a.lay.dtmp)[y * N + x];
   }
-  __device__ void mid(int t, int y, int x, c64 &v) const {
+  // the image pixel, read with the loads
+  __device__ float side(int t, int y, int x) const { return a.image(t, s.img)[y * N + x]; }
+  __device__ void mid_side(int t, int y, int x, c64 &v, float img) const {
     constexpr double inv2 = 1.0 / ((double)N * N), inv4 = inv2 * inv2;
     a.at<c64>(t, a.lay.ptil)[y * N + x] = make_double2(v.x * inv2, v.y * inv2);
-    v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)a.image(t, s.img)[y * N + x]);
+    v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)img);
   }
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
 };
