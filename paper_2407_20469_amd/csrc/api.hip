@@ -461,20 +461,22 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     };
     rows_of(d.d_lo, d.d_hi, s.dy0, s.dn);
     rows_of(d.q_lo, d.q_hi, s.qy0, s.qn);
+    rows_of(d.z_lo, d.z_hi, s.zy0, s.zn);
     const int64_t pix = (int64_t)a.T * N * N;
-    const double nu = d.nu, T = a.T, fd = (double)s.dn / N, fq = (double)s.qn / N;
+    const double nu = d.nu, T = a.T, fd = (double)s.dn / N, fq = (double)s.qn / N,
+                 fz = (double)s.zn / N;
     {
       // three FP64 passes: P_hat formed in the first (read O_hat 8 B, write
       // P_hat 16 B, write 16 B on the rows of D), then read (rows of D),
-      // write P, read the image, write (36 B + 16 B on D), then read, write
-      // (32 B)
-      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 36.0 + 32.0 + 32.0 * fd), st);
+      // write P, read the image (20 B + 16 B on D + 16 B on the rows where z
+      // is read), then read, write on those rows (32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 20.0 + 32.0 * fd + 48.0 * fz), st);
       hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
                          dim3(kFftThreads), 0, st, OpP1<N>{a, s});
       APIC_LAUNCHED();
       APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a, s}, st));
-      hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, N)),
-                         dim3(kFftThreads), 0, st, OpP3<N>{a});
+      hipLaunchKernelGGL((k_rows<c64, N, OpP3<N>>), dim3(row_blocks<c64, N>(a.T, s.zn)),
+                         dim3(kFftThreads), 0, st, OpP3<N>{a, s});
       APIC_LAUNCHED();
     }
     {

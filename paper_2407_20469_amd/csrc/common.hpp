@@ -130,9 +130,10 @@ struct StepArgs {
   const uint64_t *gmask;          // block-sparsity masks of E chunks
   int nwe;                        // mask words per block of 64 unknowns
   const uint64_t *qbits;          // Q membership over the grid (bit y N + x)
-  // rows of D (P_hat and the unknowns) and of Q (b): FFT-order first row and
-  // row count, rounded up to whole row-pass workgroups
-  int dy0, dn, qy0, qn;
+  // rows of D (P_hat and the unknowns), of Q (b) and where z is read:
+  // FFT-order first row and row count, rounded up to whole row-pass
+  // workgroups
+  int dy0, dn, qy0, qn, zy0, zn;
 };
 
 // Row y (FFT order) lies in the cyclic range of cnt rows from y0.

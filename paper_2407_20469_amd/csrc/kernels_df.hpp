@@ -86,14 +86,18 @@ template <int N> struct OpP2 {
     a.at<c64>(t, a.lay.ptil)[y * N + x] = make_double2(v.x * inv2, v.y * inv2);
     v = make_double2((v.x * v.x + v.y * v.y) * inv4, (double)img);
   }
-  __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.dtmp)[y * N + x] = v; }
+  // only the rows where z is read go on to pass 3
+  __device__ void store(int t, int y, int x, c64 v) const {
+    if (row_in(y, s.zy0, s.zn, N)) a.at<c64>(t, a.lay.dtmp)[y * N + x] = v;
+  }
 };
-// Pass 3 (rows): row FFT completes z = fft2(|P|^2 + i I_j).
+// Pass 3 (the rows where z is read): row FFT completes z = fft2(|P|^2 + i I_j).
 template <int N> struct OpP3 {
   static constexpr bool INV1 = false, TWO = false, INV2 = false;
   ClassArgs a;
-  __device__ int rows() const { return N; }
-  __device__ int row_of(int r) const { return r; }
+  StepArgs s;
+  __device__ int rows() const { return s.zn; }
+  __device__ int row_of(int r) const { return (s.zy0 + r) & (N - 1); }
   __device__ c64 load(int t, int y, int x) const { return a.at<c64>(t, a.lay.dtmp)[y * N + x]; }
   __device__ void mid(int, int, int, c64 &) const {}
   __device__ void store(int t, int y, int x, c64 v) const { a.at<c64>(t, a.lay.fpp)[y * N + x] = v; }

@@ -378,9 +378,15 @@ apic_status build_geom_plan(const apic_geometry &g, GeomPlan &p) {
       for (uint32_t w : Q) qlo = std::min(qlo, unpack_ky(w)), qhi = std::max(qhi, unpack_ky(w));
       st.d_lo = dlo;  // U is not empty here
       st.d_hi = dhi;
+      int ulo = n, uhi = -n;
+      for (auto &c : Uc) ulo = std::min(ulo, c.first), uhi = std::max(uhi, c.first);
+      st.z_lo = -(uhi - ulo);
+      st.z_hi = uhi - ulo;
       if (!Q.empty()) {
         st.q_lo = qlo;
         st.q_hi = qhi;
+        st.z_lo = std::min({st.z_lo, qlo, -qhi});
+        st.z_hi = std::max({st.z_hi, qhi, -qlo});
       }
     }
     st.off_q = int64_t(p.coords.size());

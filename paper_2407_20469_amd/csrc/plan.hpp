@@ -58,6 +58,10 @@ struct DfStep {
   // P_hat and the unknowns lie) and of Q (where b is nonzero); the FFT passes
   // of P_hat and of the right-hand side skip the rows outside them.
   int32_t d_lo = 0, d_hi = -1, q_lo = 0, q_hi = -1;
+  // Signed row span where z = fft2(|P|^2 + i I_j) is read: the rows of Q and
+  // of -Q (right-hand side) and the row differences of U (the gram's Toeplitz
+  // term at u - u' and u' - u).
+  int32_t z_lo = 0, z_hi = -1;
 };
 
 // Per-tile workspace layout (byte offsets from the tile's base).
