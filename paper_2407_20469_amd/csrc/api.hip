@@ -431,6 +431,10 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
                           hipStream_t st) {
   const GeomPlan &g = p->geoms[r.geom];
   bool skipped = false;
+  constexpr int RW = RowShape<c64, N>::ROWS;
+  // rows of P_hat that may be nonzero: all of them before the first image
+  // (the workspace holds an earlier call's data), then the last image's D
+  int prev_y0 = 0, prev_n = N;
   for (int j = 0; j < g.n_df; ++j) {
     const DfStep &d = g.steps[j];
     if (d.nu == 0) {
@@ -454,7 +458,6 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.nwe = d.nwe;
     s.qbits = a.masks + d.off_qbits;
     // row ranges of the pruned passes, whole row-pass workgroups (at least one)
-    constexpr int RW = RowShape<c64, N>::ROWS;
     auto rows_of = [&](int lo, int hi, int &y0, int &cnt) {
       y0 = lo & (N - 1);
       cnt = std::min(N, std::max(RW, (hi - lo + 1 + RW - 1) / RW * RW));
@@ -462,16 +465,27 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     rows_of(d.d_lo, d.d_hi, s.dy0, s.dn);
     rows_of(d.q_lo, d.q_hi, s.qy0, s.qn);
     rows_of(d.z_lo, d.z_hi, s.zy0, s.zn);
+    {
+      // the shortest cyclic row range that holds this image's D and the
+      // previous one's
+      const int off_d = (s.dy0 - prev_y0) & (N - 1), off_p = (prev_y0 - s.dy0) & (N - 1);
+      const int len_p = std::max(prev_n, off_d + s.dn), len_d = std::max(s.dn, off_p + prev_n);
+      s.py0 = len_p <= len_d ? prev_y0 : s.dy0;
+      s.pn = std::min(N, (std::min(len_p, len_d) + RW - 1) / RW * RW);
+      prev_y0 = s.dy0;
+      prev_n = s.dn;
+    }
     const int64_t pix = (int64_t)a.T * N * N;
     const double nu = d.nu, T = a.T, fd = (double)s.dn / N, fq = (double)s.qn / N,
-                 fz = (double)s.zn / N;
+                 fz = (double)s.zn / N, fp = (double)s.pn / N;
     {
       // three FP64 passes: P_hat formed in the first (read O_hat 8 B, write
-      // P_hat 16 B, write 16 B on the rows of D), then read (rows of D),
-      // write P, read the image (20 B + 16 B on D + 16 B on the rows where z
-      // is read), then read, write on those rows (32 B)
-      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (24.0 + 20.0 + 32.0 * fd + 48.0 * fz), st);
-      hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, N)),
+      // P_hat 16 B on its rows, write 16 B on the rows of D), then read (rows
+      // of D), write P, read the image (20 B + 16 B on D + 16 B on the rows
+      // where z is read), then read, write on those rows (32 B)
+      ProfScope ps(APIC_PROF_DF_FFT, (double)pix * (20.0 + 24.0 * fp + 32.0 * fd + 48.0 * fz),
+                   st);
+      hipLaunchKernelGGL((k_rows<c64, N, OpP1<N>>), dim3(row_blocks<c64, N>(a.T, s.pn)),
                          dim3(kFftThreads), 0, st, OpP1<N>{a, s});
       APIC_LAUNCHED();
       APIC_CHECK(launch_cols<c64, N>(a, a.T, OpP2<N>{a, s}, st));

@@ -130,10 +130,11 @@ struct StepArgs {
   const uint64_t *gmask;          // block-sparsity masks of E chunks
   int nwe;                        // mask words per block of 64 unknowns
   const uint64_t *qbits;          // Q membership over the grid (bit y N + x)
-  // rows of D (P_hat and the unknowns), of Q (b) and where z is read:
+  // rows of D (P_hat and the unknowns), of Q (b), where z is read, and
+  // where P_hat is written (D and the previous image's D, which it clears):
   // FFT-order first row and row count, rounded up to whole row-pass
   // workgroups
-  int dy0, dn, qy0, qn, zy0, zn;
+  int dy0, dn, qy0, qn, zy0, zn, py0, pn;
 };
 
 // Row y (FFT order) lies in the cyclic range of cnt rows from y0.

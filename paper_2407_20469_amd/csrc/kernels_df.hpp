@@ -50,13 +50,16 @@ __device__ __forceinline__ c64 phat_at(const ClassArgs &a, const StepArgs &s, in
 }
 
 // P chain, pass 1 (rows): form P_hat (kept for the gram's gathers) and
-// row-IFFT it.
+// row-IFFT it.  P_hat is zero outside the rows of D, so the pass runs over
+// D's rows and those of the previous image's D (which it clears); every row
+// outside the two already holds zeros (the first image of a call covers all
+// rows).
 template <int N> struct OpP1 {
   static constexpr bool INV1 = true, TWO = false, INV2 = false;
   ClassArgs a;
   StepArgs s;
-  __device__ int rows() const { return N; }
-  __device__ int row_of(int r) const { return r; }
+  __device__ int rows() const { return s.pn; }
+  __device__ int row_of(int r) const { return (s.py0 + r) & (N - 1); }
   __device__ c64 load(int t, int y, int x) const {
     const c64 v = phat_at(a, s, t, y * N + x);
     a.at<c64>(t, a.lay.phat)[y * N + x] = v;
