@@ -166,7 +166,12 @@ apic_status apic_workspace_bytes(const apic_plan *plan, int32_t n_tiles,
  *             (16 x 16 quadrant, excluded k) pairs, i.e. in units of 256
  *             complex MACs: the products the gram issues; U and E
  *             are in the plan's processing order (compact squares), P and Q
- *             in FFT raster order */
+ *             in FFT raster order
+ *          8: per darkfield step the signed row spans (ky) the FFT passes
+ *             of that step are restricted to: (lo, hi) of P + U, of Q, and
+ *             of the rows where fft2(|P|^2 + i I_j) is read (Q, -Q and the
+ *             row differences of U); (0, -1) for an empty span and for
+ *             steps without unknowns */
 apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, int32_t j,
                             int32_t *out, int64_t cap, int64_t *len);
 

@@ -957,6 +957,11 @@ apic_status apic_plan_query(const apic_plan *plan, int32_t geom, int32_t what, i
          g.n_pix};
   } else if (what == 7) {
     v.assign(g.band_rows.begin(), g.band_rows.end());
+  } else if (what == 8) {
+    for (const DfStep &d : g.steps) {
+      const int32_t sp[] = {d.d_lo, d.d_hi, d.q_lo, d.q_hi, d.z_lo, d.z_hi};
+      v.insert(v.end(), sp, sp + 6);
+    }
   } else if (what == 6) {
     for (const DfStep &d : g.steps) {
       v.push_back(d.nu);

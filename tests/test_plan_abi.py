@@ -93,6 +93,53 @@ def test_plan_sets_equal_oracle_sets(wl):
         assert inside.sum() == cnt and np.all(inside[:cnt])
 
 
+@pytest.mark.parametrize("wl", ["small64", "two_ring128", "grid256"])
+def test_plan_row_spans_cover_every_read(wl):
+    """The darkfield FFT passes skip rows (Eq. 11-13 chain): P_hat and U lie on
+    the rows of P + U, b on the rows of Q, and fft2(|P|^2 + i I_j) is read on
+    Q, on -Q and at the row differences of U. Each span the plan reports is
+    the exact extent of the oracle's sets."""
+    if wl == "small64":
+        w = S.small_workload(n=64)
+    elif wl == "grid256":
+        w = S.grid_batch()
+    else:
+        w = S.small_workload(n=128, n_bf=12, n_df=24, na_df=(0.30, 0.38))
+    plan = apic.Plan(w.geometry_kwargs())
+    spans = plan.query(8).reshape(-1, 6)
+    assert spans.shape[0] == len(w.k_df)
+    n, r = w.n, w.r
+    ky, kx = k_grid(n)
+    known = np.zeros((n, n), bool)
+    for k in w.k_bf:
+        known |= circ(ky + k[1], kx + k[0], r)
+    executed = 0
+    for j, k_j in enumerate(w.k_df):
+        sets = odf.darkfield_sets(n, k_j, known, r)
+        known |= sets["U_mask"]
+        d_lo, d_hi, q_lo, q_hi, z_lo, z_hi = spans[j].tolist()
+        u = np.asarray(sets["U"]).reshape(-1, 2)
+        if len(u) == 0:
+            assert (d_lo, d_hi, q_lo, q_hi, z_lo, z_hi) == (0, -1, 0, -1, 0, -1), j
+            continue
+        executed += 1
+        pu_rows = np.concatenate([np.asarray(sets["P"]).reshape(-1, 2)[:, 0], u[:, 0]])
+        assert (d_lo, d_hi) == (pu_rows.min(), pu_rows.max()), j
+        q_rows = np.asarray(sets["Q"]).reshape(-1, 2)[:, 0]
+        w_u = int(u[:, 0].max() - u[:, 0].min())
+        read = [np.arange(-w_u, w_u + 1)]  # row differences of U, both signs
+        if len(q_rows):
+            assert (q_lo, q_hi) == (q_rows.min(), q_rows.max()), j
+            read += [q_rows, -q_rows]
+        else:
+            assert (q_lo, q_hi) == (0, -1), j
+        read = np.concatenate(read)
+        assert (z_lo, z_hi) == (read.min(), read.max()), j
+        # every span fits the grid without wrapping onto itself
+        assert d_hi - d_lo < n and z_hi - z_lo < n, j
+    assert executed > 0
+
+
 def test_plan_rejects_bad_geometry():
     w = S.small_workload(n=64)
     g = w.geometry_kwargs()
