@@ -20,6 +20,7 @@
 #include "kernels_rgb.hpp"
 #include "chol.hpp"
 #include "calib.hpp"
+#include "rowspan.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
 
@@ -434,7 +435,9 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
   constexpr int RW = RowShape<c64, N>::ROWS;
   // rows of P_hat that may be nonzero: all of them before the first image
   // (the workspace holds an earlier call's data), then the last image's D
-  int prev_y0 = 0, prev_n = N;
+  RowRange prev;
+  prev.y0 = 0;
+  prev.n = N;
   for (int j = 0; j < g.n_df; ++j) {
     const DfStep &d = g.steps[j];
     if (d.nu == 0) {
@@ -457,24 +460,21 @@ apic_status run_darkfield(const apic_plan *p, const ClassRun &r, const ClassArgs
     s.gmask = a.masks + d.off_gmask;
     s.nwe = d.nwe;
     s.qbits = a.masks + d.off_qbits;
-    // row ranges of the pruned passes, whole row-pass workgroups (at least one)
-    auto rows_of = [&](int lo, int hi, int &y0, int &cnt) {
-      y0 = lo & (N - 1);
-      cnt = std::min(N, std::max(RW, (hi - lo + 1 + RW - 1) / RW * RW));
-    };
-    rows_of(d.d_lo, d.d_hi, s.dy0, s.dn);
-    rows_of(d.q_lo, d.q_hi, s.qy0, s.qn);
-    rows_of(d.z_lo, d.z_hi, s.zy0, s.zn);
-    {
-      // the shortest cyclic row range that holds this image's D and the
-      // previous one's
-      const int off_d = (s.dy0 - prev_y0) & (N - 1), off_p = (prev_y0 - s.dy0) & (N - 1);
-      const int len_p = std::max(prev_n, off_d + s.dn), len_d = std::max(s.dn, off_p + prev_n);
-      s.py0 = len_p <= len_d ? prev_y0 : s.dy0;
-      s.pn = std::min(N, (std::min(len_p, len_d) + RW - 1) / RW * RW);
-      prev_y0 = s.dy0;
-      prev_n = s.dn;
-    }
+    // row ranges of the pruned passes, whole row-pass workgroups
+    const RowRange rd = rows_of_span(d.d_lo, d.d_hi, N, RW);
+    const RowRange rq = rows_of_span(d.q_lo, d.q_hi, N, RW);
+    const RowRange rz = rows_of_span(d.z_lo, d.z_hi, N, RW);
+    // P_hat's pass: this image's D and the previous one's, which it clears
+    const RowRange rp = cyclic_hull(prev, rd, N, RW);
+    prev = rd;
+    s.dy0 = rd.y0;
+    s.dn = rd.n;
+    s.qy0 = rq.y0;
+    s.qn = rq.n;
+    s.zy0 = rz.y0;
+    s.zn = rz.n;
+    s.py0 = rp.y0;
+    s.pn = rp.n;
     const int64_t pix = (int64_t)a.T * N * N;
     const double nu = d.nu, T = a.T, fd = (double)s.dn / N, fq = (double)s.qn / N,
                  fz = (double)s.zn / N, fp = (double)s.pn / N;
