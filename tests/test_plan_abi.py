@@ -93,7 +93,7 @@ def test_plan_sets_equal_oracle_sets(wl):
         assert inside.sum() == cnt and np.all(inside[:cnt])
 
 
-@pytest.mark.parametrize("wl", ["small64", "two_ring128", "grid256"])
+@pytest.mark.parametrize("wl", ["small64", "two_ring128", "grid256", "slide512"])
 def test_plan_row_spans_cover_every_read(wl):
     """The darkfield FFT passes skip rows (Eq. 11-13 chain): P_hat and U lie on
     the rows of P + U, b on the rows of Q, and fft2(|P|^2 + i I_j) is read on
@@ -103,6 +103,9 @@ def test_plan_row_spans_cover_every_read(wl):
         w = S.small_workload(n=64)
     elif wl == "grid256":
         w = S.grid_batch()
+    elif wl == "slide512":
+        from apic_synth import slide
+        w = slide.pool_workload(2, 1)
     else:
         w = S.small_workload(n=128, n_bf=12, n_df=24, na_df=(0.30, 0.38))
     plan = apic.Plan(w.geometry_kwargs())
